@@ -1,0 +1,19 @@
+"""FP64 CPU oracle for time-domain backprojection (TDBP).
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call anything here. The
+product path (``paper_2101_05888_amd``) never imports this package and fails
+loudly when its HIP library is missing.
+
+The oracle is a plain, slow, obviously correct NumPy transcription of the
+backprojection sum that inverts Eq. 1 (Sec. II-A), with the beam gate of
+Sec. II-C evaluated per term, and of its gradient with respect to the
+navigation and the sound speed. It shares no code with the HIP path.
+"""
+from .tdbp import (pixel_points, backproject, backproject_image, gated_term_count,
+                   gated_term_count_rows, vjp, sharpness, sharpness_cotangent)
+from .metrics import rel_l2, phase_error_mrad
+
+__all__ = ["pixel_points", "backproject", "backproject_image", "gated_term_count",
+           "gated_term_count_rows", "vjp", "sharpness", "sharpness_cotangent",
+           "rel_l2", "phase_error_mrad"]

@@ -1,0 +1,257 @@
+"""FP64 oracle: backprojection image, gated-term count and geometry gradient.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): nothing in the product
+path imports this module.
+
+Definition (Eq. 1 and its symbol list, Sec. II-A; per-ping integration with a
+field-of-view test, Sec. II-C; transmitter and receiver tested separately, the
+bistatic case of Sec. III-B). For a pixel centre p, ping i with transmitter T_i
+and receiver element e at R_ie:
+
+    d_T = |p - T_i|,   d_R = |p - R_ie|,   tau = (d_T + d_R) / c
+    u   = (tau - t0) * f_s,  n = floor(u),  w = u - n
+    L   = (1 - w) * E~[n] + w * E~[n+1]      E~[k] = echo[i, e, k] inside the record, else 0
+    g   = [|p_x - T_x| <= sin(theta) d_T] * [|p_x - R_x| <= sin(theta) d_R]   (g = 1 without a gate)
+    I(p) = sum_i sum_e  g * L * exp(+j 2 pi f_c tau)
+
+Readings where the paper is silent: linear interpolation in sample index with
+zero extension; t_k = t0 + k / f_s; echoes at complex baseband so the carrier
+phase is re-applied; no amplitude weighting; positions fixed per ping.
+
+Gradient (vector-Jacobian product) for a cotangent Gbar = dJ/dRe I + j dJ/dIm I:
+
+    dJ/dtheta = sum_p Re( conj(Gbar(p)) * sum_ie g * D_ie(p) * dtau_ie/dtheta )
+    D = [ f_s (E~[n+1] - E~[n]) + j 2 pi f_c L ] * exp(j 2 pi f_c tau)
+    dtau/dT_i = (T_i - p) / (c d_T),  dtau/dR_ie = (R_ie - p) / (c d_R),  dtau/dc = -tau / c
+
+The gate is held constant and the slope is that of the segment containing u.
+"""
+from __future__ import annotations
+
+import math
+import multiprocessing as mp
+import os
+
+import numpy as np
+
+
+def pixel_points(origin, spacing, n, index=None) -> np.ndarray:
+    """Pixel centres [N,3] float64: origin + index * spacing per axis, x fastest."""
+    nx, ny, nz = (int(v) for v in n)
+    if index is None:
+        index = np.arange(nx * ny * nz, dtype=np.int64)
+    index = np.asarray(index, dtype=np.int64)
+    ix = (index % nx).astype(np.float64)
+    iy = ((index // nx) % ny).astype(np.float64)
+    iz = (index // (nx * ny)).astype(np.float64)
+    pts = np.empty((index.size, 3), dtype=np.float64)
+    pts[:, 0] = origin[0] + ix * spacing[0]
+    pts[:, 1] = origin[1] + iy * spacing[1]
+    pts[:, 2] = origin[2] + iz * spacing[2]
+    return pts
+
+
+def _taps(row: np.ndarray, n: np.ndarray):
+    """E~[n] and E~[n+1] with zero outside the record."""
+    ns = row.shape[0]
+    a = np.zeros(n.shape, dtype=np.complex128)
+    b = np.zeros(n.shape, dtype=np.complex128)
+    ia = (n >= 0) & (n < ns)
+    ib = (n + 1 >= 0) & (n + 1 < ns)
+    a[ia] = row[n[ia]]
+    b[ib] = row[n[ib] + 1]
+    return a, b
+
+
+def _gate(dx: np.ndarray, d: np.ndarray, sin_g: float) -> np.ndarray:
+    return np.abs(dx) <= sin_g * d
+
+
+def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate):
+    P, E = rx.shape[0], rx.shape[1]
+    acc = np.zeros(pts.shape[0], dtype=np.complex128)
+    count = 0
+    sin_g = math.sin(gate) if gate > 0 else None
+    for i in range(P):
+        dT = np.sqrt(((pts - tx[i]) ** 2).sum(axis=1))
+        gT = _gate(pts[:, 0] - tx[i, 0], dT, sin_g) if sin_g is not None else None
+        for e in range(E):
+            R = rx[i, e]
+            dR = np.sqrt(((pts - R) ** 2).sum(axis=1))
+            tau = (dT + dR) / c
+            u = (tau - t0) * fs
+            nf = np.floor(u)
+            w = u - nf
+            a, b = _taps(echo[i, e], nf.astype(np.int64))
+            L = (1.0 - w) * a + w * b
+            term = L * np.exp(1j * 2.0 * np.pi * fc * tau)
+            if sin_g is not None:
+                g = gT & _gate(pts[:, 0] - R[0], dR, sin_g)
+                term = np.where(g, term, 0.0)
+                count += int(g.sum())
+            else:
+                count += pts.shape[0]
+            acc += term
+    return acc, count
+
+
+_SHARED = {}
+
+
+def _worker(args):
+    lo, hi = args
+    s = _SHARED
+    return _bp_chunk(s["echo"], s["tx"], s["rx"], s["c"], s["fc"], s["fs"], s["t0"],
+                     s["pts"][lo:hi], s["gate"])
+
+
+def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
+                workers=1, chunk=4096, return_count=False):
+    """Backprojected complex values at arbitrary points [N,3] (float64 in, complex128 out).
+
+    echo: complex [P,E,N_s]; tx: [P,3]; rx: [P,E,3]; gate_half_angle in radians
+    (0 = no gate). ``workers`` > 1 splits the points over forked processes.
+    """
+    echo = np.ascontiguousarray(np.asarray(echo).astype(np.complex128, copy=False))
+    tx = np.asarray(tx, dtype=np.float64)
+    rx = np.asarray(rx, dtype=np.float64)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    N = pts.shape[0]
+    spans = [(lo, min(N, lo + chunk)) for lo in range(0, N, chunk)]
+    out = np.zeros(N, dtype=np.complex128)
+    total = 0
+    if workers <= 1 or len(spans) <= 1:
+        for lo, hi in spans:
+            v, cnt = _bp_chunk(echo, tx, rx, float(c), fc, fs, t0, pts[lo:hi], gate_half_angle)
+            out[lo:hi] = v
+            total += cnt
+    else:
+        _SHARED.update(echo=echo, tx=tx, rx=rx, c=float(c), fc=fc, fs=fs, t0=t0, pts=pts,
+                       gate=gate_half_angle)
+        ctx = mp.get_context("fork")
+        with ctx.Pool(workers) as pool:
+            res = pool.map(_worker, spans, chunksize=1)
+        _SHARED.clear()
+        for (lo, hi), (v, cnt) in zip(spans, res):
+            out[lo:hi] = v
+            total += cnt
+    return (out, total) if return_count else out
+
+
+def backproject_image(echo, tx, rx, c, fc, fs, t0, origin, spacing, n, gate_half_angle=0.0,
+                      workers=1, return_count=False):
+    """Full image [nz, ny, nx] complex128 on the grid origin + index * spacing."""
+    pts = pixel_points(origin, spacing, n)
+    r = backproject(echo, tx, rx, c, fc, fs, t0, pts, gate_half_angle, workers=workers,
+                    return_count=return_count)
+    nx, ny, nz = (int(v) for v in n)
+    if return_count:
+        return r[0].reshape(nz, ny, nx), r[1]
+    return r.reshape(nz, ny, nx)
+
+
+def gated_term_count(tx, rx, points, gate_half_angle) -> int:
+    """Number of (pixel, ping, element) terms with g = 1, testing every term."""
+    tx = np.asarray(tx, dtype=np.float64)
+    rx = np.asarray(rx, dtype=np.float64)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    if gate_half_angle <= 0:
+        return pts.shape[0] * rx.shape[0] * rx.shape[1]
+    s = math.sin(gate_half_angle)
+    total = 0
+    for i in range(tx.shape[0]):
+        dT = np.sqrt(((pts - tx[i]) ** 2).sum(axis=1))
+        gT = _gate(pts[:, 0] - tx[i, 0], dT, s)
+        for e in range(rx.shape[1]):
+            dR = np.sqrt(((pts - rx[i, e]) ** 2).sum(axis=1))
+            total += int((gT & _gate(pts[:, 0] - rx[i, e, 0], dR, s)).sum())
+    return total
+
+
+def gated_term_count_rows(tx, rx, origin, spacing, n, gate_half_angle) -> int:
+    """Same count from per-row x-intervals of the cone (no per-term test).
+
+    For a row of pixels at fixed (y, z), |x - X| <= sin(theta) sqrt((x-X)^2 + rho^2)
+    is the interval |x - X| <= tan(theta) rho, with rho the (y, z) distance to X.
+    """
+    tx = np.asarray(tx, dtype=np.float64)
+    rx = np.asarray(rx, dtype=np.float64)
+    nx, ny, nz = (int(v) for v in n)
+    if gate_half_angle <= 0:
+        return nx * ny * nz * rx.shape[0] * rx.shape[1]
+    t = math.tan(gate_half_angle)
+    ys = origin[1] + np.arange(ny) * spacing[1]
+    zs = origin[2] + np.arange(nz) * spacing[2]
+    Y, Z = np.meshgrid(ys, zs, indexing="xy")
+    Y, Z = Y.ravel(), Z.ravel()
+    total = 0
+    for i in range(tx.shape[0]):
+        hT = t * np.hypot(Y - tx[i, 1], Z - tx[i, 2])
+        loT, hiT = tx[i, 0] - hT, tx[i, 0] + hT
+        for e in range(rx.shape[1]):
+            R = rx[i, e]
+            hR = t * np.hypot(Y - R[1], Z - R[2])
+            lo = np.maximum(loT, R[0] - hR)
+            hi = np.minimum(hiT, R[0] + hR)
+            ilo = np.maximum(np.ceil((lo - origin[0]) / spacing[0]), 0)
+            ihi = np.minimum(np.floor((hi - origin[0]) / spacing[0]), nx - 1)
+            total += int(np.clip(ihi - ilo + 1, 0, None).sum())
+    return total
+
+
+def vjp(echo, tx, rx, c, fc, fs, t0, points, gbar, gate_half_angle=0.0):
+    """Gradient of J w.r.t. (tx [P,3], rx [P,E,3], c) given Gbar at the points."""
+    echo = np.asarray(echo).astype(np.complex128, copy=False)
+    tx = np.asarray(tx, dtype=np.float64)
+    rx = np.asarray(rx, dtype=np.float64)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    gbar = np.asarray(gbar, dtype=np.complex128).reshape(-1)
+    P, E = rx.shape[0], rx.shape[1]
+    g_tx = np.zeros((P, 3))
+    g_rx = np.zeros((P, E, 3))
+    g_c = 0.0
+    sin_g = math.sin(gate_half_angle) if gate_half_angle > 0 else None
+    for i in range(P):
+        dT = np.sqrt(((pts - tx[i]) ** 2).sum(axis=1))
+        gT = _gate(pts[:, 0] - tx[i, 0], dT, sin_g) if sin_g is not None else None
+        for e in range(E):
+            R = rx[i, e]
+            dR = np.sqrt(((pts - R) ** 2).sum(axis=1))
+            tau = (dT + dR) / c
+            u = (tau - t0) * fs
+            nf = np.floor(u)
+            w = u - nf
+            a, b = _taps(echo[i, e], nf.astype(np.int64))
+            L = (1.0 - w) * a + w * b
+            ph = np.exp(1j * 2.0 * np.pi * fc * tau)
+            D = (fs * (b - a) + 1j * 2.0 * np.pi * fc * L) * ph
+            coef = np.real(np.conj(gbar) * D)
+            if sin_g is not None:
+                g = gT & _gate(pts[:, 0] - R[0], dR, sin_g)
+                coef = np.where(g, coef, 0.0)
+            g_tx[i] += ((coef / (c * dT))[:, None] * (tx[i] - pts)).sum(axis=0)
+            g_rx[i, e] += ((coef / (c * dR))[:, None] * (R - pts)).sum(axis=0)
+            g_c += float((coef * (-tau / c)).sum())
+    return g_tx, g_rx, g_c
+
+
+def sharpness(img) -> float:
+    """S = sum |I|^4 / (sum |I|^2)^2."""
+    m2 = np.abs(np.asarray(img, dtype=np.complex128)) ** 2
+    return float((m2 ** 2).sum() / m2.sum() ** 2)
+
+
+def sharpness_cotangent(img) -> np.ndarray:
+    """Gbar = dS/dRe I + j dS/dIm I = 4 I (|I|^2 / B^2 - A / B^3), A = sum|I|^4, B = sum|I|^2."""
+    I = np.asarray(img, dtype=np.complex128)
+    m2 = np.abs(I) ** 2
+    A = (m2 ** 2).sum()
+    B = m2.sum()
+    return 4.0 * I * (m2 / B ** 2 - A / B ** 3)
+
+
+def default_workers() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1

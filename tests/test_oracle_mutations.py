@@ -1,0 +1,58 @@
+"""The oracle's pins must reject plausible mistakes.
+
+Each case plants one slip in a private copy of the oracle's source (on the
+CPU, never in the HIP path) and checks that the brute-force pin (P1) or the
+lone-scatterer closed form (P2) rejects the mutated oracle.
+"""
+import inspect
+import math
+import types
+
+import numpy as np
+import pytest
+
+import oracle.tdbp as tdbp
+from tests.test_oracle_pins import _brute_mp, _tiny_geometry
+
+MUTATIONS = {
+    "phase_sign": ("np.exp(1j * 2.0 * np.pi * fc * tau)", "np.exp(-1j * 2.0 * np.pi * fc * tau)"),
+    "dropped_tx_leg": ("tau = (dT + dR) / c", "tau = (2.0 * dR) / c"),
+    "tap_off_by_one": ("b[ib] = row[n[ib] + 1]", "b[ib] = row[n[ib]]"),
+    "swapped_weights": ("L = (1.0 - w) * a + w * b", "L = w * a + (1.0 - w) * b"),
+    "gate_wrong_axis": ("g = gT & _gate(pts[:, 0] - R[0], dR, sin_g)", "g = gT & _gate(pts[:, 1] - R[1], dR, sin_g)"),
+    "rx_transposed": ("R = rx[i, e]\n            dR", "R = rx[e % rx.shape[0], i % rx.shape[1]]\n            dR"),
+    "t0_sign": ("u = (tau - t0) * fs", "u = (tau + t0) * fs"),
+    "tx_gate_dropped": ("g = gT & _gate", "g = _gate"),
+}
+
+
+def _mutant(old, new):
+    src = inspect.getsource(tdbp)
+    assert src.count(old) >= 1, old
+    mod = types.ModuleType("oracle_mutant")
+    exec(compile(src.replace(old, new), "oracle_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_reject_mutation(name):
+    old, new = MUTATIONS[name]
+    mod = _mutant(old, new)
+    rejected = False
+    for gate_deg, ns, t0 in [(12.0, 36, 1.5e-3), (12.0, 48, 4.95e-3)]:
+        g = _tiny_geometry(gate_deg=gate_deg, ns=ns, t0=t0, P=4, E=3)
+        pts = g["grid"].points()
+        ref = _brute_mp(g, pts)
+        got = mod.backproject(g["echo"], g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, g["gate"])
+        if np.linalg.norm(got - ref) > 1e-12 * np.linalg.norm(ref):
+            rejected = True
+            break
+    assert rejected, f"mutation {name} survived the brute-force pin"
+
+
+def test_unmutated_copy_passes():
+    mod = _mutant("import math", "import math")
+    g = _tiny_geometry(gate_deg=12.0, ns=36, P=4, E=3)
+    pts = g["grid"].points()
+    got = mod.backproject(g["echo"], g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, g["gate"])
+    assert np.linalg.norm(got - _brute_mp(g, pts)) <= 1e-12 * np.linalg.norm(got)
