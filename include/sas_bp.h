@@ -1,0 +1,174 @@
+/*
+ * sas_bp.h - time-domain backprojection (TDBP) for synthetic aperture sonar
+ * on AMD MI355X (gfx950). C ABI: plain pointers and sizes only.
+ *
+ * What is computed (Eq. 1 and the inversion it defines, Sec. II-A; beam test
+ * per pixel after block culling, Sec. II-C; transmitter and receiver tested
+ * separately, Sec. III-B). For every pixel centre p of a regular grid, every
+ * ping i and every receiver element e:
+ *
+ *   d_T = |p - T_i|,  d_R = |p - R_ie|,  tau = (d_T + d_R) / c
+ *   u   = (tau - t0) * f_s,  n = floor(u),  w = u - n
+ *   L   = (1 - w) * echo[i][e][n] + w * echo[i][e][n+1]   (samples outside
+ *         [0, n_sample) read as zero)
+ *   g   = [|p_x - T_x| <= sin(a) d_T] * [|p_x - R_x| <= sin(a) d_R]  (a = gate
+ *         half-angle about the broadside plane; g = 1 when a = 0)
+ *   I(p) = sum_i sum_e g * L * exp(+j 2 pi f_c tau)
+ *
+ * Positions are fixed during a ping (stop-and-hop). Echoes are range
+ * compressed and at complex baseband, so the carrier phase is re-applied.
+ * Axes are north-east-down (Sec. II-B): x along-track, y across, z down.
+ * A pixel centre is origin + index * spacing on each axis.
+ *
+ * Arithmetic: per tile of pixels and per (ping, element) the reference range
+ * and carrier phase are formed in FP64 on the GPU; per-pixel delay offsets,
+ * interpolation and accumulation run in FP32. Results agree with an FP64
+ * evaluation of the sum to about 1e-5 relative L2 for FP32 echoes.
+ *
+ * Ownership: the caller allocates and owns every array passed in (echoes,
+ * navigation, sound speed, images, gradients); they must stay valid until the
+ * work enqueued on the caller's stream has completed. A plan owns one device
+ * workspace slab sized when the plan is made, plus a captured HIP graph.
+ *
+ * Concurrency: a plan accepts one call in flight at a time; use one plan per
+ * concurrent stream. Calls are asynchronous on the given stream.
+ *
+ * Errors: every function returns a status code; nothing is thrown across the
+ * ABI. Arguments are checked on the host before anything is enqueued; a
+ * failed check leaves outputs untouched. sas_bp_last_error_detail() gives a
+ * thread-local message for the last failure on the calling thread.
+ * Navigation or a sound speed that is not finite, or c below the plan's c_min,
+ * is detected on the device: affected swaths produce zero images and the
+ * plan's sticky status becomes SAS_BP_ENAV (read with sas_bp_plan_status()).
+ */
+#ifndef SAS_BP_H
+#define SAS_BP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SAS_BP_ABI_VERSION 1
+
+typedef struct sas_bp_plan_s* sas_bp_plan_t;
+
+enum sas_bp_status {
+    SAS_BP_OK = 0,
+    SAS_BP_EINVAL = 1,        /* bad argument (size, pointer, alignment, value)   */
+    SAS_BP_EUNSUPPORTED = 2,  /* valid but not supported (dtype, tiling, size)    */
+    SAS_BP_ENOMEM = 3,        /* device allocation failed or workspace limit hit  */
+    SAS_BP_EDEVICE = 4,       /* HIP runtime error                                */
+    SAS_BP_ENAV = 5           /* device found non-finite navigation or bad c      */
+};
+
+/* Echo storage. Samples are complex, real part first.
+ *   C64    : float  [P][E][N_s][2]
+ *   F16X2  : half   [P][E][N_s][2], value = stored * echo_scale[i]
+ *   BF16X2 : bfloat16 [P][E][N_s][2], value = stored * echo_scale[i]
+ * Interpolation and accumulation are FP32 for every storage type. */
+enum sas_bp_echo_dtype {
+    SAS_BP_ECHO_C64 = 0,
+    SAS_BP_ECHO_F16X2 = 1,
+    SAS_BP_ECHO_BF16X2 = 2
+};
+
+/* One swath: acquisition constants and image grid. */
+typedef struct {
+    int32_t n_ping;         /* P >= 1                                          */
+    int32_t n_elem;         /* E, 1..256 receiver elements per ping            */
+    int32_t n_sample;       /* N_s, 2..2^31-1 samples per (ping, element)      */
+    int32_t echo_dtype;     /* enum sas_bp_echo_dtype                          */
+    int64_t n[3];           /* nx, ny, nz >= 1 (nz == 1: a 2D image)           */
+    double origin[3];       /* centre of pixel (0,0,0), metres                 */
+    double spacing[3];      /* > 0, metres; spacing[2] unused when nz == 1     */
+    double f_c;             /* carrier frequency re-applied as exp(+j2 pi f_c tau), Hz, >= 0 */
+    double f_s;             /* complex sample rate, Hz, > 0                    */
+    double t0;              /* time of sample 0 after transmit, s             */
+    double gate_half_angle; /* radians in [0, pi/2); 0 disables the beam gate */
+    double c_min;           /* smallest sound speed the plan must accept, m/s; 0 selects 1400 */
+} sas_bp_swath_desc;
+
+/* Plan options; a NULL options pointer selects every default. */
+typedef struct {
+    int32_t device;          /* HIP device ordinal                             */
+    int32_t tile_x, tile_y, tile_z; /* pixel tile shape; 0 = automatic         */
+    int32_t pings_per_chunk; /* pings staged in LDS per pass; 0 = automatic   */
+    int32_t use_graph;       /* 1 = replay a captured HIP graph (default), 0 = direct launches */
+    size_t workspace_limit;  /* bytes; 0 = unlimited                           */
+} sas_bp_options;
+
+/* Device pointers for one swath. All must be device memory. */
+typedef struct {
+    const void* echo;        /* [P][E][N_s] complex, layout per echo_dtype; 16-byte aligned */
+    const float* echo_scale; /* f32[P] for F16X2/BF16X2; ignored (may be NULL) for C64      */
+    const double* tx_pos;    /* f64[P][3]   transmitter position of each ping               */
+    const double* rx_pos;    /* f64[P][E][3] receiver positions                             */
+    const double* c;         /* f64[1] sound speed, read on the device at every call        */
+    void* image;             /* complex64 [nz][ny][nx] output (x fastest), overwritten      */
+} sas_bp_swath_io;
+
+/* Make a plan for n_swaths swaths (1..4096). Validates every descriptor,
+ * chooses the tiling and allocates the workspace. On success *out holds a new
+ * plan that the caller releases with sas_bp_destroy(). */
+int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths,
+                const sas_bp_options* options, sas_bp_plan_t* out);
+
+/* Workspace bytes sas_bp_plan() would allocate for these swaths (host only). */
+int sas_bp_workspace_size(const sas_bp_swath_desc* desc, int n_swaths,
+                          const sas_bp_options* options, size_t* bytes);
+
+/* Form the image of every swath (the sum above), one image per io entry.
+ * io has n_swaths entries matching the plan's descriptors. All swaths run in a
+ * single persistent launch. stream is a hipStream_t (NULL = default). */
+int sas_bp_image(sas_bp_plan_t plan, const sas_bp_swath_io* io, int n_swaths, void* stream);
+
+/* Vector-Jacobian product of the image with respect to the geometry.
+ * Given a cotangent Gbar per swath (complex64, image layout; Gbar =
+ * dJ/dRe I + j dJ/dIm I), writes
+ *   grad_tx[s] : f64[P][3]    dJ/dT_i
+ *   grad_rx[s] : f64[P][E][3] dJ/dR_ie
+ *   grad_c[s]  : f64[1]       dJ/dc
+ * using dI/dtau = [f_s (E[n+1] - E[n]) + j 2 pi f_c L] exp(j 2 pi f_c tau),
+ * dtau/dT = (T - p)/(c d_T), dtau/dR = (R - p)/(c d_R), dtau/dc = -tau/c
+ * (gate held fixed). Outputs are overwritten. Reduction order is fixed, so
+ * results are bitwise reproducible for a given plan. */
+int sas_bp_adjoint(sas_bp_plan_t plan, const sas_bp_swath_io* io,
+                   const void* const* grad_image, double* const* grad_tx,
+                   double* const* grad_rx, double* const* grad_c,
+                   int n_swaths, void* stream);
+
+/* Exact number of (pixel, ping, element) terms with g = 1 for each swath,
+ * from the same per-row cone intervals the image kernels use. Writes
+ * counts[s] (host memory) and synchronises the stream. */
+int sas_bp_useful_updates(sas_bp_plan_t plan, const sas_bp_swath_io* io, int n_swaths,
+                          void* stream, int64_t* counts);
+
+/* Image sharpness S = sum|I|^4 / (sum|I|^2)^2 over n_pix complex64 pixels
+ * (the autofocus objective) and, if grad_image is not NULL, its cotangent
+ * Gbar = 4 I (|I|^2/B^2 - A/B^3) with A = sum|I|^4, B = sum|I|^2. Sums are
+ * FP64 in a fixed order (bitwise reproducible). out_S is a device pointer to
+ * one double; the plan lends its workspace for the partial sums. Asynchronous. */
+int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, double* out_S,
+                     void* grad_image, void* stream);
+
+/* Sticky device-detected status of the plan (SAS_BP_OK or SAS_BP_ENAV);
+ * synchronises with the device and clears it. */
+int sas_bp_plan_status(sas_bp_plan_t plan);
+
+/* Chosen tiling, for reporting: tile_x, tile_y, tile_z, pings_per_chunk,
+ * window samples, LDS bytes per workgroup, workgroups launched. */
+int sas_bp_plan_info(sas_bp_plan_t plan, int64_t info[8]);
+
+void sas_bp_destroy(sas_bp_plan_t plan);
+
+const char* sas_bp_error_string(int status);
+const char* sas_bp_last_error_detail(void);
+int sas_bp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAS_BP_H */

@@ -1,0 +1,13 @@
+"""MI355X-native time-domain backprojection for synthetic aperture sonar.
+
+The computation lives in the HIP library ``libsas_bp.so`` (C ABI in
+``include/sas_bp.h``); this package is its binding. Importing it without the
+built library raises ``ImportError``: there is no CPU fallback.
+"""
+from .api import (Plan, SwathBuffers, swath_desc, sas_bp_plan, sas_bp_workspace_size, sas_bp_image,
+                  sas_bp_adjoint, sas_bp_useful_updates, sas_bp_sharpness, sas_bp_abi_version)
+from ._native import SasBpError
+
+__all__ = ["Plan", "SwathBuffers", "swath_desc", "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image",
+           "sas_bp_adjoint", "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_abi_version",
+           "SasBpError"]

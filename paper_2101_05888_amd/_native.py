@@ -1,0 +1,90 @@
+"""ctypes view of ``include/sas_bp.h``: structures and the exported functions.
+
+The library is loaded from this package directory (built in-tree by
+``paper_2101_05888_amd.build``). There is no fallback: importing this module
+without the library raises ``ImportError``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsas_bp.so")
+
+SAS_BP_OK, SAS_BP_EINVAL, SAS_BP_EUNSUPPORTED, SAS_BP_ENOMEM, SAS_BP_EDEVICE, SAS_BP_ENAV = range(6)
+ECHO_C64, ECHO_F16X2, ECHO_BF16X2 = 0, 1, 2
+
+EXPORTED = (
+    "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image", "sas_bp_adjoint",
+    "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_plan_status", "sas_bp_plan_info",
+    "sas_bp_destroy", "sas_bp_error_string", "sas_bp_last_error_detail", "sas_bp_abi_version",
+)
+
+
+class SwathDesc(C.Structure):
+    _fields_ = [
+        ("n_ping", C.c_int32), ("n_elem", C.c_int32), ("n_sample", C.c_int32), ("echo_dtype", C.c_int32),
+        ("n", C.c_int64 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
+        ("f_c", C.c_double), ("f_s", C.c_double), ("t0", C.c_double),
+        ("gate_half_angle", C.c_double), ("c_min", C.c_double),
+    ]
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("device", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
+        ("pings_per_chunk", C.c_int32), ("use_graph", C.c_int32), ("workspace_limit", C.c_size_t),
+    ]
+
+
+class SwathIO(C.Structure):
+    _fields_ = [
+        ("echo", C.c_void_p), ("echo_scale", C.c_void_p), ("tx_pos", C.c_void_p),
+        ("rx_pos", C.c_void_p), ("c", C.c_void_p), ("image", C.c_void_p),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"HIP library {LIB_PATH} is missing; build it with `python -m paper_2101_05888_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    lib.sas_bp_plan.argtypes = [C.POINTER(SwathDesc), C.c_int, C.POINTER(Options), C.POINTER(P)]
+    lib.sas_bp_workspace_size.argtypes = [C.POINTER(SwathDesc), C.c_int, C.POINTER(Options), C.POINTER(C.c_size_t)]
+    lib.sas_bp_image.argtypes = [P, C.POINTER(SwathIO), C.c_int, P]
+    lib.sas_bp_adjoint.argtypes = [P, C.POINTER(SwathIO), C.POINTER(P), C.POINTER(P), C.POINTER(P),
+                                   C.POINTER(P), C.c_int, P]
+    lib.sas_bp_useful_updates.argtypes = [P, C.POINTER(SwathIO), C.c_int, P, C.POINTER(C.c_int64)]
+    lib.sas_bp_sharpness.argtypes = [P, P, C.c_int64, P, P, P]
+    lib.sas_bp_plan_status.argtypes = [P]
+    lib.sas_bp_plan_info.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.sas_bp_destroy.argtypes = [P]
+    lib.sas_bp_destroy.restype = None
+    lib.sas_bp_error_string.argtypes = [C.c_int]
+    lib.sas_bp_error_string.restype = C.c_char_p
+    lib.sas_bp_last_error_detail.argtypes = []
+    lib.sas_bp_last_error_detail.restype = C.c_char_p
+    lib.sas_bp_abi_version.argtypes = []
+    for name in EXPORTED:
+        fn = getattr(lib, name)
+        if name not in ("sas_bp_destroy", "sas_bp_error_string", "sas_bp_last_error_detail"):
+            fn.restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+
+class SasBpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.sas_bp_error_string(status).decode()
+        detail = lib.sas_bp_last_error_detail().decode()
+        super().__init__(f"{where}: {msg} ({detail})" if detail else f"{where}: {msg}")
+
+
+def check(status: int, where: str) -> None:
+    if status != SAS_BP_OK:
+        raise SasBpError(status, where)

@@ -1,0 +1,198 @@
+"""Python binding of the C ABI, argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of the method: it checks tensor shapes, dtypes and devices, packs
+the ctypes structures and forwards device pointers and the current HIP stream.
+All computation happens in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native as N
+from ._native import check
+
+ECHO_DTYPES = {"c64": N.ECHO_C64, "f16": N.ECHO_F16X2, "bf16": N.ECHO_BF16X2}
+
+
+def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin: Sequence[float],
+               spacing: Sequence[float], f_c: float, f_s: float, t0: float = 0.0,
+               gate_half_angle: float = 0.0, echo_dtype: str = "c64", c_min: float = 0.0) -> N.SwathDesc:
+    d = N.SwathDesc()
+    d.n_ping, d.n_elem, d.n_sample = int(n_ping), int(n_elem), int(n_sample)
+    d.echo_dtype = ECHO_DTYPES[echo_dtype]
+    for a in range(3):
+        d.n[a] = int(n[a])
+        d.origin[a] = float(origin[a])
+        d.spacing[a] = float(spacing[a])
+    d.f_c, d.f_s, d.t0 = float(f_c), float(f_s), float(t0)
+    d.gate_half_angle, d.c_min = float(gate_half_angle), float(c_min)
+    return d
+
+
+def _options(device=0, tile=(0, 0, 0), pings_per_chunk=0, use_graph=True, workspace_limit=0) -> N.Options:
+    o = N.Options()
+    o.device = int(device)
+    o.tile_x, o.tile_y, o.tile_z = (int(v) for v in tile)
+    o.pings_per_chunk = int(pings_per_chunk)
+    o.use_graph = 1 if use_graph else 0
+    o.workspace_limit = int(workspace_limit)
+    return o
+
+
+class Plan:
+    """Owns a ``sas_bp_plan_t``; released by ``destroy()`` or garbage collection."""
+
+    def __init__(self, handle: int, descs: list, device: int):
+        self.handle = C.c_void_p(handle)
+        self.descs = descs
+        self.device = device
+
+    def info(self) -> dict:
+        arr = (C.c_int64 * 8)()
+        check(N.lib.sas_bp_plan_info(self.handle, arr), "sas_bp_plan_info")
+        keys = ("tile_x", "tile_y", "tile_z", "pings_per_chunk", "window", "lds_bytes", "grid", "tiles")
+        return dict(zip(keys, (int(v) for v in arr)))
+
+    def status(self) -> int:
+        return int(N.lib.sas_bp_plan_status(self.handle))
+
+    def destroy(self) -> None:
+        if self.handle is not None and self.handle.value:
+            N.lib.sas_bp_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def sas_bp_plan(descs: Sequence[N.SwathDesc], device: int = 0, tile=(0, 0, 0), pings_per_chunk: int = 0,
+                use_graph: bool = True, workspace_limit: int = 0) -> Plan:
+    descs = list(descs)
+    arr = (N.SwathDesc * len(descs))(*descs)
+    opt = _options(device, tile, pings_per_chunk, use_graph, workspace_limit)
+    out = C.c_void_p()
+    check(N.lib.sas_bp_plan(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_plan")
+    return Plan(out.value, descs, device)
+
+
+def sas_bp_workspace_size(descs: Sequence[N.SwathDesc], tile=(0, 0, 0), pings_per_chunk: int = 0) -> int:
+    descs = list(descs)
+    arr = (N.SwathDesc * len(descs))(*descs)
+    opt = _options(0, tile, pings_per_chunk)
+    out = C.c_size_t()
+    check(N.lib.sas_bp_workspace_size(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_workspace_size")
+    return int(out.value)
+
+
+@dataclasses.dataclass
+class SwathBuffers:
+    """Device tensors of one swath (see ``sas_bp_swath_io`` in the header)."""
+    echo: torch.Tensor                  # complex64 [P,E,N] or float16/bfloat16 [P,E,N,2]
+    tx: torch.Tensor                    # float64 [P,3]
+    rx: torch.Tensor                    # float64 [P,E,3]
+    c: torch.Tensor                     # float64 [1]
+    image: torch.Tensor                 # complex64 [nz,ny,nx]
+    echo_scale: Optional[torch.Tensor] = None   # float32 [P] for 16-bit echoes
+
+
+def _need(t: torch.Tensor, name: str, dtype, shape, device) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device (got {t.device})")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on device {t.device.index}, plan on {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _io(plan: Plan, bufs: Sequence[SwathBuffers]):
+    if len(bufs) != len(plan.descs):
+        raise ValueError(f"plan has {len(plan.descs)} swaths, got {len(bufs)} buffers")
+    arr = (N.SwathIO * len(bufs))()
+    for i, (d, b) in enumerate(zip(plan.descs, bufs)):
+        P, E, Ns = d.n_ping, d.n_elem, d.n_sample
+        if d.echo_dtype == N.ECHO_C64:
+            _need(b.echo, f"echo[{i}]", torch.complex64, (P, E, Ns), plan.device)
+        else:
+            dt = torch.float16 if d.echo_dtype == N.ECHO_F16X2 else torch.bfloat16
+            _need(b.echo, f"echo[{i}]", dt, (P, E, Ns, 2), plan.device)
+            _need(b.echo_scale, f"echo_scale[{i}]", torch.float32, (P,), plan.device)
+        _need(b.tx, f"tx[{i}]", torch.float64, (P, 3), plan.device)
+        _need(b.rx, f"rx[{i}]", torch.float64, (P, E, 3), plan.device)
+        _need(b.c, f"c[{i}]", torch.float64, (1,), plan.device)
+        _need(b.image, f"image[{i}]", torch.complex64, (d.n[2], d.n[1], d.n[0]), plan.device)
+        arr[i].echo = b.echo.data_ptr()
+        arr[i].echo_scale = b.echo_scale.data_ptr() if b.echo_scale is not None else None
+        arr[i].tx_pos = b.tx.data_ptr()
+        arr[i].rx_pos = b.rx.data_ptr()
+        arr[i].c = b.c.data_ptr()
+        arr[i].image = b.image.data_ptr()
+    return arr
+
+
+def _stream(device: int, stream=None) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def sas_bp_image(plan: Plan, bufs: Sequence[SwathBuffers], stream=None) -> None:
+    arr = _io(plan, bufs)
+    check(N.lib.sas_bp_image(plan.handle, arr, len(bufs), _stream(plan.device, stream)), "sas_bp_image")
+
+
+def sas_bp_adjoint(plan: Plan, bufs: Sequence[SwathBuffers], grad_images: Sequence[torch.Tensor],
+                   grad_tx: Sequence[torch.Tensor], grad_rx: Sequence[torch.Tensor],
+                   grad_c: Sequence[torch.Tensor], stream=None) -> None:
+    arr = _io(plan, bufs)
+    n = len(bufs)
+    for i, d in enumerate(plan.descs):
+        _need(grad_images[i], f"grad_image[{i}]", torch.complex64, (d.n[2], d.n[1], d.n[0]), plan.device)
+        _need(grad_tx[i], f"grad_tx[{i}]", torch.float64, (d.n_ping, 3), plan.device)
+        _need(grad_rx[i], f"grad_rx[{i}]", torch.float64, (d.n_ping, d.n_elem, 3), plan.device)
+        _need(grad_c[i], f"grad_c[{i}]", torch.float64, (1,), plan.device)
+    P = C.c_void_p
+    gi = (P * n)(*[t.data_ptr() for t in grad_images])
+    gt = (P * n)(*[t.data_ptr() for t in grad_tx])
+    gr = (P * n)(*[t.data_ptr() for t in grad_rx])
+    gc = (P * n)(*[t.data_ptr() for t in grad_c])
+    check(N.lib.sas_bp_adjoint(plan.handle, arr, gi, gt, gr, gc, n, _stream(plan.device, stream)),
+          "sas_bp_adjoint")
+
+
+def sas_bp_useful_updates(plan: Plan, bufs: Sequence[SwathBuffers], stream=None) -> list:
+    arr = _io(plan, bufs)
+    out = (C.c_int64 * len(bufs))()
+    check(N.lib.sas_bp_useful_updates(plan.handle, arr, len(bufs), _stream(plan.device, stream), out),
+          "sas_bp_useful_updates")
+    return [int(v) for v in out]
+
+
+def sas_bp_sharpness(plan: Plan, image: torch.Tensor, out_S: torch.Tensor,
+                     grad_image: Optional[torch.Tensor] = None, stream=None) -> None:
+    if image.dtype != torch.complex64 or not image.is_contiguous() or image.device.type != "cuda":
+        raise ValueError("image must be a contiguous complex64 device tensor")
+    _need(out_S, "out_S", torch.float64, (1,), plan.device)
+    if grad_image is not None:
+        _need(grad_image, "grad_image", torch.complex64, tuple(image.shape), plan.device)
+    check(N.lib.sas_bp_sharpness(plan.handle, image.data_ptr(), image.numel(), out_S.data_ptr(),
+                                 grad_image.data_ptr() if grad_image is not None else None,
+                                 _stream(plan.device, stream)), "sas_bp_sharpness")
+
+
+def sas_bp_abi_version() -> int:
+    return int(N.lib.sas_bp_abi_version())

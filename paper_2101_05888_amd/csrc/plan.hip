@@ -1,0 +1,687 @@
+// Plan, workspace slab, graph capture/replay and the exported C ABI.
+//
+// A plan is made once per set of swath shapes. It validates the descriptors on
+// the host, picks the tile shape and the pings staged per pass, sizes one
+// device slab for every buffer the kernels need (one allocation, the slab
+// scheme of Sec. II-C), and captures the launch sequence
+//     init -> cull -> cost order -> persistent image kernel
+// into a HIP graph. The per-swath pointers and constants live in the slab, so
+// the graph stays valid when callers pass new buffers or move the navigation
+// and sound speed (device memory read at every replay).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sas_bp.h"
+#include "tdbp_dev.h"
+
+namespace sasbp {
+typedef void (*ImageKernelFn)(Workspace, int);
+ImageKernelFn image_kernel_for(int K, int LZ, bool gate, int dt);
+int image_lds_bytes(int CP, int E, int W, int ROWS, bool gate);
+hipError_t launch_init(const Workspace& ws, hipStream_t st);
+hipError_t launch_cull(const Workspace& ws, int n_tiles, int TX, int TY, int TZ, int bucket_shift, hipStream_t st);
+hipError_t launch_order(const Workspace& ws, int n_tiles, int bucket_shift, hipStream_t st);
+hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int grid, int lds_bytes, hipStream_t st);
+hipError_t image_occupancy(ImageKernelFn fn, int lds_bytes, int* blocks_per_cu);
+hipError_t set_image_lds_limit(ImageKernelFn fn, int lds_bytes);
+
+typedef void (*AdjointKernelFn)(Workspace, int);
+AdjointKernelFn adjoint_kernel_for(int K, int LZ, bool gate, int dt);
+int adjoint_lds_bytes(int CP, int E, int W, int ROWS, bool gate);
+hipError_t launch_adjoint(AdjointKernelFn fn, const Workspace& ws, int n_tiles, int grid, int lds_bytes, hipStream_t st);
+hipError_t adjoint_occupancy(AdjointKernelFn fn, int lds_bytes, int* blocks_per_cu);
+hipError_t set_adjoint_lds_limit(AdjointKernelFn fn, int lds_bytes);
+hipError_t launch_adjoint_reduce(const Workspace& ws, int n_swaths, int max_p, hipStream_t st);
+hipError_t launch_count(const Workspace& ws, int s, int P, int E, int rows, unsigned long long* out, hipStream_t st);
+hipError_t launch_sharpness(const void* image, long long n, double* partials, double* out_S, void* grad,
+                            hipStream_t st);
+}  // namespace sasbp
+
+using namespace sasbp;
+
+namespace {
+
+thread_local std::string g_detail;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_detail = buf;
+  return status;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(SAS_BP_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));      \
+  } while (0)
+
+constexpr double kDefaultCmin = 1400.0;
+constexpr int kSharpPartials = 1024;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Tiling {
+  int K, LZ, TX, TY, TZ;
+};
+
+struct SwathPlan {
+  sas_bp_swath_desc d;
+  int ntx, nty, ntz, ntiles, tile0;
+  int W, CP;
+  double half_diag, c_min;
+};
+
+struct Layout {
+  size_t swaths, prange, order, counters, bucket, tile_swath, scratch, total;
+  size_t n_partials;   // adjoint records, allocated on the first adjoint call
+};
+
+}  // namespace
+
+struct sas_bp_plan_s {
+  int device = 0;
+  int n_swaths = 0;
+  int n_tiles = 0;
+  Tiling tiling{};
+  bool gate_any = false;
+  int dtype = 0;
+  int bucket_shift = 0;
+  int lds_bytes = 0, adj_lds_bytes = 0;
+  int grid = 0, adj_grid = 0;
+  int max_pe = 0;
+  int max_p = 0;
+  bool use_graph = true;
+  void* adj_buf = nullptr;   // adjoint partials + sound-speed partials
+  std::vector<SwathPlan> sw;
+  Layout lay{};
+  unsigned char* slab = nullptr;
+  Workspace ws{};
+  ImageKernelFn image_fn = nullptr;
+  AdjointKernelFn adjoint_fn = nullptr;
+  SwathDev* host_sw = nullptr;     // pinned mirror of ws.swaths
+  std::vector<SwathDev> last_sw;   // what the device copy currently holds
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate(const sas_bp_swath_desc* d, int i) {
+  if (d->n_ping < 1) return fail(SAS_BP_EINVAL, "swath %d: n_ping must be >= 1", i);
+  if (d->n_elem < 1 || d->n_elem > kMaxElem) return fail(SAS_BP_EINVAL, "swath %d: n_elem must be in [1, %d]", i, kMaxElem);
+  if (d->n_sample < 2) return fail(SAS_BP_EINVAL, "swath %d: n_sample must be >= 2", i);
+  if (d->echo_dtype < 0 || d->echo_dtype > 2) return fail(SAS_BP_EUNSUPPORTED, "swath %d: unknown echo dtype %d", i, d->echo_dtype);
+  for (int a = 0; a < 3; ++a) {
+    if (d->n[a] < 1) return fail(SAS_BP_EINVAL, "swath %d: n[%d] must be >= 1", i, a);
+    if (d->n[a] > (1 << 20)) return fail(SAS_BP_EUNSUPPORTED, "swath %d: n[%d] too large", i, a);
+    if (!finite(d->origin[a])) return fail(SAS_BP_EINVAL, "swath %d: origin[%d] not finite", i, a);
+    if (!(d->spacing[a] > 0.0) || !finite(d->spacing[a])) {
+      if (a < 2 || d->n[2] > 1) return fail(SAS_BP_EINVAL, "swath %d: spacing[%d] must be > 0", i, a);
+    }
+  }
+  if ((long long)d->n[0] * d->n[1] * d->n[2] > (1ll << 34)) return fail(SAS_BP_EUNSUPPORTED, "swath %d: image too large", i);
+  if (!(d->f_s > 0.0) || !finite(d->f_s)) return fail(SAS_BP_EINVAL, "swath %d: f_s must be > 0", i);
+  if (!(d->f_c >= 0.0) || !finite(d->f_c)) return fail(SAS_BP_EINVAL, "swath %d: f_c must be >= 0", i);
+  if (!finite(d->t0)) return fail(SAS_BP_EINVAL, "swath %d: t0 not finite", i);
+  if (!(d->gate_half_angle >= 0.0) || !(d->gate_half_angle < 1.5707963267948966))
+    return fail(SAS_BP_EINVAL, "swath %d: gate_half_angle must be in [0, pi/2)", i);
+  if (!(d->c_min >= 0.0) || !finite(d->c_min)) return fail(SAS_BP_EINVAL, "swath %d: c_min must be >= 0", i);
+  return SAS_BP_OK;
+}
+
+// Tile shape: 2D images use LZ = 1 (tiles of 8K x 32 pixels); 3D volumes
+// LZ = 4 (8K x 8 x 4 voxels). K from the options or from the image size, so
+// that small images still produce enough tiles to occupy the GPU.
+int choose_tiling(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, Tiling* t) {
+  bool any3d = false;
+  long long pix = 0;
+  for (int i = 0; i < n; ++i) {
+    any3d |= d[i].n[2] > 1;
+    pix += (long long)d[i].n[0] * d[i].n[1] * d[i].n[2];
+  }
+  int LZ = any3d ? 4 : 1;
+  int K = 4;
+  if (o && (o->tile_x || o->tile_y || o->tile_z)) {
+    const int tz = o->tile_z ? o->tile_z : LZ;
+    if (tz != 1 && tz != 2 && tz != 4) return fail(SAS_BP_EUNSUPPORTED, "tile_z must be 1, 2 or 4");
+    LZ = tz;
+    const int ty = kThreads / (kLX * LZ);
+    if (o->tile_y && o->tile_y != ty) return fail(SAS_BP_EUNSUPPORTED, "tile_y must be %d for tile_z %d", ty, LZ);
+    if (o->tile_x) {
+      if (o->tile_x != 16 && o->tile_x != 32 && o->tile_x != 64) return fail(SAS_BP_EUNSUPPORTED, "tile_x must be 16, 32 or 64");
+      K = o->tile_x / kLX;
+    }
+  } else if (pix < (1ll << 20)) {
+    K = 2;
+  }
+  if (!any3d && LZ != 1) {
+    // a 2D image tiled in z would waste lanes; allowed only when asked for explicitly
+  }
+  t->K = K;
+  t->LZ = LZ;
+  t->TX = kLX * K;
+  t->TY = kThreads / (kLX * LZ);
+  t->TZ = LZ;
+  return SAS_BP_OK;
+}
+
+constexpr int kLdsBudget = 64 * 1024;
+
+int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, const Tiling& t,
+                 std::vector<SwathPlan>* out, int* n_tiles) {
+  out->clear();
+  int tiles = 0;
+  const int rows = t.TY * t.TZ;
+  for (int i = 0; i < n; ++i) {
+    SwathPlan s;
+    s.d = d[i];
+    s.ntx = (int)((d[i].n[0] + t.TX - 1) / t.TX);
+    s.nty = (int)((d[i].n[1] + t.TY - 1) / t.TY);
+    s.ntz = (int)((d[i].n[2] + t.TZ - 1) / t.TZ);
+    const long long nt = (long long)s.ntx * s.nty * s.ntz;
+    if (nt + tiles > (1ll << 30)) return fail(SAS_BP_EUNSUPPORTED, "too many tiles");
+    s.ntiles = (int)nt;
+    s.tile0 = tiles;
+    tiles += s.ntiles;
+    const double ex = (t.TX - 1) * d[i].spacing[0];
+    const double ey = (t.TY - 1) * d[i].spacing[1];
+    const double ez = d[i].n[2] > 1 ? (t.TZ - 1) * d[i].spacing[2] : 0.0;
+    s.half_diag = 0.5 * std::sqrt(ex * ex + ey * ey + ez * ez);
+    s.c_min = d[i].c_min > 0.0 ? d[i].c_min : kDefaultCmin;
+    // window: delay offsets within the tile are bounded by +-2 r (triangle
+    // inequality on both legs), plus interpolation and rounding margin
+    s.W = (int)std::ceil(4.0 * s.half_diag * d[i].f_s / s.c_min) + 6;
+    if (s.W > 8192) return fail(SAS_BP_EUNSUPPORTED, "swath %d: tile spans %d samples; use a smaller tile", i, s.W);
+    int cp = (o && o->pings_per_chunk > 0) ? o->pings_per_chunk : 0;
+    const bool gate = d[i].gate_half_angle > 0.0;
+    if (cp == 0) {
+      cp = 1;
+      while (cp < 8 && image_lds_bytes(cp * 2, d[i].n_elem, s.W, rows, gate) <= kLdsBudget) cp *= 2;
+    }
+    if (image_lds_bytes(cp, d[i].n_elem, s.W, rows, gate) > 160 * 1024)
+      return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d pings x %d elements x %d samples exceed LDS", i, cp,
+                  d[i].n_elem, s.W);
+    s.CP = cp;
+    out->push_back(s);
+  }
+  *n_tiles = tiles;
+  return SAS_BP_OK;
+}
+
+Layout make_layout(int n_swaths, int n_tiles, size_t n_partials) {
+  Layout L{};
+  size_t o = 0;
+  L.swaths = o;     o = align_up(o + sizeof(SwathDev) * n_swaths);
+  L.prange = o;     o = align_up(o + sizeof(PingRange) * n_tiles);
+  L.order = o;      o = align_up(o + sizeof(int) * n_tiles);
+  L.counters = o;   o = align_up(o + sizeof(unsigned) * 16);
+  L.bucket = o;     o = align_up(o + sizeof(unsigned) * kBuckets);
+  L.tile_swath = o; o = align_up(o + sizeof(int) * n_tiles);
+  L.scratch = o;    o = align_up(o + sizeof(double) * (2 * kSharpPartials + 64));
+  L.n_partials = n_partials;
+  L.total = o;
+  return L;
+}
+
+// Adjoint partials: one record per (tile, ping, element) of the tile's ping range.
+size_t adjoint_partials(const std::vector<SwathPlan>& sw) {
+  size_t n = 0;
+  for (const auto& s : sw) n += (size_t)s.ntiles * s.d.n_ping * s.d.n_elem;
+  return n;
+}
+
+SwathDev make_dev(const SwathPlan& s) {
+  SwathDev v;
+  std::memset(&v, 0, sizeof v);
+  v.P = s.d.n_ping;
+  v.E = s.d.n_elem;
+  v.Ns = s.d.n_sample;
+  v.dtype = s.d.echo_dtype;
+  v.nx = (int)s.d.n[0];
+  v.ny = (int)s.d.n[1];
+  v.nz = (int)s.d.n[2];
+  v.ntx = s.ntx;
+  v.nty = s.nty;
+  v.ntz = s.ntz;
+  v.tile0 = s.tile0;
+  v.W = s.W;
+  v.CP = s.CP;
+  for (int a = 0; a < 3; ++a) {
+    v.o[a] = s.d.origin[a];
+    v.d[a] = (a == 2 && s.d.n[2] == 1 && !(s.d.spacing[2] > 0.0)) ? 1.0 : s.d.spacing[a];
+  }
+  v.fc = s.d.f_c;
+  v.fs = s.d.f_s;
+  v.t0 = s.d.t0;
+  v.tan_g = s.d.gate_half_angle > 0.0 ? std::tan(s.d.gate_half_angle) : 0.0;
+  v.sin_g = s.d.gate_half_angle > 0.0 ? std::sin(s.d.gate_half_angle) : 0.0;
+  v.c_min = s.c_min;
+  v.half_diag = s.half_diag;
+  return v;
+}
+
+int check_io(const sas_bp_plan_s* p, const sas_bp_swath_io* io, int n) {
+  if (!io) return fail(SAS_BP_EINVAL, "io is NULL");
+  if (n != p->n_swaths) return fail(SAS_BP_EINVAL, "plan has %d swaths, got %d", p->n_swaths, n);
+  for (int i = 0; i < n; ++i) {
+    const auto& s = p->sw[i];
+    if (!io[i].echo || !io[i].tx_pos || !io[i].rx_pos || !io[i].c || !io[i].image)
+      return fail(SAS_BP_EINVAL, "swath %d: NULL pointer", i);
+    if (((uintptr_t)io[i].echo & 15u) != 0) return fail(SAS_BP_EINVAL, "swath %d: echo not 16-byte aligned", i);
+    if (((uintptr_t)io[i].image & 7u) != 0) return fail(SAS_BP_EINVAL, "swath %d: image not 8-byte aligned", i);
+    if (((uintptr_t)io[i].tx_pos & 7u) || ((uintptr_t)io[i].rx_pos & 7u) || ((uintptr_t)io[i].c & 7u))
+      return fail(SAS_BP_EINVAL, "swath %d: navigation not 8-byte aligned", i);
+    if (s.d.echo_dtype != SAS_BP_ECHO_C64 && !io[i].echo_scale)
+      return fail(SAS_BP_EINVAL, "swath %d: echo_scale required for 16-bit echoes", i);
+  }
+  return SAS_BP_OK;
+}
+
+// Copy the per-swath descriptors (with the caller's pointers) to the slab if
+// they changed since the last call. The pinned staging buffer is reused only
+// after the previous copy has completed.
+int upload(sas_bp_plan_s* p, const std::vector<SwathDev>& v, hipStream_t st) {
+  if (v.size() == p->last_sw.size() && std::memcmp(v.data(), p->last_sw.data(), v.size() * sizeof(SwathDev)) == 0)
+    return SAS_BP_OK;
+  if (p->upload_pending) HIP_TRY(hipEventSynchronize(p->upload_done));
+  std::memcpy(p->host_sw, v.data(), v.size() * sizeof(SwathDev));
+  HIP_TRY(hipMemcpyAsync(p->ws.swaths, p->host_sw, v.size() * sizeof(SwathDev), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(p->upload_done, st));
+  p->upload_pending = true;
+  p->last_sw = v;
+  return SAS_BP_OK;
+}
+
+int enqueue_image(sas_bp_plan_s* p, hipStream_t st) {
+  HIP_TRY(launch_init(p->ws, st));
+  HIP_TRY(launch_cull(p->ws, p->n_tiles, p->tiling.TX, p->tiling.TY, p->tiling.TZ, p->bucket_shift, st));
+  HIP_TRY(launch_order(p->ws, p->n_tiles, p->bucket_shift, st));
+  HIP_TRY(launch_image(p->image_fn, p->ws, p->n_tiles, p->grid, p->lds_bytes, st));
+  return SAS_BP_OK;
+}
+
+int capture_graph(sas_bp_plan_s* p) {
+  HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_image(p, p->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+  if (rc != SAS_BP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(SAS_BP_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(SAS_BP_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  p->graph = g;
+  p->graph_exec = ex;
+  return SAS_BP_OK;
+}
+
+void release(sas_bp_plan_s* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->upload_done) {
+    (void)hipEventSynchronize(p->upload_done);
+    (void)hipEventDestroy(p->upload_done);
+  }
+  if (p->host_sw) (void)hipHostFree(p->host_sw);
+  if (p->adj_buf) (void)hipFree(p->adj_buf);
+  if (p->slab) (void)hipFree(p->slab);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int plan_sizes(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, Tiling* t,
+               std::vector<SwathPlan>* sw, int* n_tiles, Layout* lay) {
+  if (!desc) return fail(SAS_BP_EINVAL, "desc is NULL");
+  if (n < 1 || n > 4096) return fail(SAS_BP_EINVAL, "n_swaths must be in [1, 4096]");
+  for (int i = 0; i < n; ++i) {
+    int rc = validate(&desc[i], i);
+    if (rc) return rc;
+  }
+  int rc = choose_tiling(desc, n, o, t);
+  if (rc) return rc;
+  rc = build_swaths(desc, n, o, *t, sw, n_tiles);
+  if (rc) return rc;
+  *lay = make_layout(n, *n_tiles, adjoint_partials(*sw));
+  return SAS_BP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sas_bp_abi_version(void) { return SAS_BP_ABI_VERSION; }
+
+const char* sas_bp_error_string(int status) {
+  switch (status) {
+    case SAS_BP_OK: return "success";
+    case SAS_BP_EINVAL: return "invalid argument";
+    case SAS_BP_EUNSUPPORTED: return "unsupported configuration";
+    case SAS_BP_ENOMEM: return "out of device memory or over the workspace limit";
+    case SAS_BP_EDEVICE: return "HIP runtime error";
+    case SAS_BP_ENAV: return "non-finite navigation or sound speed below c_min";
+    default: return "unknown status";
+  }
+}
+
+const char* sas_bp_last_error_detail(void) { return g_detail.c_str(); }
+
+int sas_bp_workspace_size(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_options* options,
+                          size_t* bytes) {
+  if (!bytes) return fail(SAS_BP_EINVAL, "bytes is NULL");
+  Tiling t;
+  std::vector<SwathPlan> sw;
+  int n_tiles = 0;
+  Layout lay;
+  int rc = plan_sizes(desc, n_swaths, options, &t, &sw, &n_tiles, &lay);
+  if (rc) return rc;
+  *bytes = lay.total;
+  return SAS_BP_OK;
+}
+
+int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_options* options, sas_bp_plan_t* out) {
+  if (!out) return fail(SAS_BP_EINVAL, "out is NULL");
+  *out = nullptr;
+  Tiling t;
+  std::vector<SwathPlan> sw;
+  int n_tiles = 0;
+  Layout lay;
+  int rc = plan_sizes(desc, n_swaths, options, &t, &sw, &n_tiles, &lay);
+  if (rc) return rc;
+  if (options && options->workspace_limit && lay.total > options->workspace_limit)
+    return fail(SAS_BP_ENOMEM, "workspace needs %zu bytes, limit is %zu", lay.total, options->workspace_limit);
+  const int device = options ? options->device : 0;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev <= 0) return fail(SAS_BP_EDEVICE, "no HIP device");
+  if (device < 0 || device >= n_dev) return fail(SAS_BP_EINVAL, "device %d out of range", device);
+  DeviceGuard guard(device);
+
+  sas_bp_plan_s* p = new (std::nothrow) sas_bp_plan_s;
+  if (!p) return fail(SAS_BP_ENOMEM, "host allocation failed");
+  p->device = device;
+  p->n_swaths = n_swaths;
+  p->n_tiles = n_tiles;
+  p->tiling = t;
+  p->sw = sw;
+  p->lay = lay;
+  p->use_graph = options ? options->use_graph != 0 : true;
+  if (options && options->use_graph == 0) p->use_graph = false;
+  if (!options) p->use_graph = true;
+  p->dtype = sw[0].d.echo_dtype;
+  int max_pe = 1, max_lds = 0, max_adj_lds = 0;
+  for (const auto& s : sw) {
+    const bool gate = s.d.gate_half_angle > 0.0;
+    p->gate_any |= gate;
+    if (s.d.echo_dtype != p->dtype) {
+      release(p);
+      return fail(SAS_BP_EUNSUPPORTED, "all swaths of a plan must share one echo dtype");
+    }
+    max_pe = std::max(max_pe, s.d.n_ping * s.d.n_elem);
+    p->max_p = std::max(p->max_p, s.d.n_ping);
+  }
+  for (const auto& s : sw) {
+    max_lds = std::max(max_lds, image_lds_bytes(s.CP, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any));
+    max_adj_lds = std::max(max_adj_lds, adjoint_lds_bytes(s.CP, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any));
+  }
+  p->max_pe = max_pe;
+  int shift = 0;
+  while ((max_pe >> shift) >= kBuckets) ++shift;
+  p->bucket_shift = shift;
+  p->lds_bytes = max_lds;
+  p->adj_lds_bytes = max_adj_lds;
+  p->image_fn = image_kernel_for(t.K, t.LZ, p->gate_any, p->dtype);
+  p->adjoint_fn = adjoint_kernel_for(t.K, t.LZ, p->gate_any, p->dtype);
+  if (!p->image_fn || !p->adjoint_fn) {
+    release(p);
+    return fail(SAS_BP_EUNSUPPORTED, "no kernel for K=%d LZ=%d", t.K, t.LZ);
+  }
+  hipError_t e = set_image_lds_limit(p->image_fn, max_lds);
+  if (e == hipSuccess) e = set_adjoint_lds_limit(p->adjoint_fn, max_adj_lds);
+  int occ = 0, adj_occ = 0;
+  if (e == hipSuccess) e = image_occupancy(p->image_fn, max_lds, &occ);
+  if (e == hipSuccess) e = adjoint_occupancy(p->adjoint_fn, max_adj_lds, &adj_occ);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    release(p);
+    return fail(SAS_BP_EDEVICE, "kernel setup failed: %s", hipGetErrorString(e));
+  }
+  if (occ < 1 || adj_occ < 1) {
+    release(p);
+    return fail(SAS_BP_EUNSUPPORTED, "tiling needs %d bytes of LDS; no workgroup fits", max_lds);
+  }
+  p->grid = std::max(1, std::min(n_tiles, occ * prop.multiProcessorCount));
+  p->adj_grid = std::max(1, std::min(n_tiles, adj_occ * prop.multiProcessorCount));
+
+  e = hipMalloc(&p->slab, lay.total);
+  if (e != hipSuccess) {
+    p->slab = nullptr;
+    release(p);
+    return fail(SAS_BP_ENOMEM, "hipMalloc(%zu) failed: %s", lay.total, hipGetErrorString(e));
+  }
+  p->ws.swaths = reinterpret_cast<SwathDev*>(p->slab + lay.swaths);
+  p->ws.prange = reinterpret_cast<PingRange*>(p->slab + lay.prange);
+  p->ws.order = reinterpret_cast<int*>(p->slab + lay.order);
+  p->ws.counters = reinterpret_cast<unsigned*>(p->slab + lay.counters);
+  p->ws.bucket = reinterpret_cast<unsigned*>(p->slab + lay.bucket);
+  p->ws.tile_swath = reinterpret_cast<int*>(p->slab + lay.tile_swath);
+  p->ws.partials = nullptr;
+  p->ws.cpart = nullptr;
+  p->ws.scratch64 = reinterpret_cast<double*>(p->slab + lay.scratch);
+
+  std::vector<int> tile_swath(n_tiles);
+  for (int i = 0; i < n_swaths; ++i)
+    for (int k = 0; k < sw[i].ntiles; ++k) tile_swath[sw[i].tile0 + k] = i;
+  std::vector<unsigned> zeros(16, 0u);
+  e = hipMemcpy(p->ws.tile_swath, tile_swath.data(), sizeof(int) * n_tiles, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->ws.counters, zeros.data(), sizeof(unsigned) * 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&p->host_sw), sizeof(SwathDev) * n_swaths, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    release(p);
+    return fail(SAS_BP_EDEVICE, "plan setup failed: %s", hipGetErrorString(e));
+  }
+  if (p->use_graph) {
+    rc = capture_graph(p);
+    if (rc) {
+      release(p);
+      return rc;
+    }
+  }
+  *out = p;
+  return SAS_BP_OK;
+}
+
+int sas_bp_image(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swaths, void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  int rc = check_io(p, io, n_swaths);
+  if (rc) return rc;
+  DeviceGuard guard(p->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<SwathDev> v(n_swaths);
+  for (int i = 0; i < n_swaths; ++i) {
+    v[i] = make_dev(p->sw[i]);
+    v[i].echo = io[i].echo;
+    v[i].scale = io[i].echo_scale;
+    v[i].tx = io[i].tx_pos;
+    v[i].rx = io[i].rx_pos;
+    v[i].c = io[i].c;
+    v[i].image = reinterpret_cast<float2*>(io[i].image);
+  }
+  rc = upload(p, v, st);
+  if (rc) return rc;
+  if (p->use_graph) {
+    HIP_TRY(hipGraphLaunch(p->graph_exec, st));
+    return SAS_BP_OK;
+  }
+  return enqueue_image(p, st);
+}
+
+int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const* grad_image,
+                   double* const* grad_tx, double* const* grad_rx, double* const* grad_c, int n_swaths,
+                   void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  int rc = check_io(p, io, n_swaths);
+  if (rc) return rc;
+  if (!grad_image || !grad_tx || !grad_rx || !grad_c) return fail(SAS_BP_EINVAL, "gradient array is NULL");
+  for (int i = 0; i < n_swaths; ++i) {
+    if (!grad_image[i] || !grad_tx[i] || !grad_rx[i] || !grad_c[i])
+      return fail(SAS_BP_EINVAL, "swath %d: NULL gradient pointer", i);
+    if (((uintptr_t)grad_image[i] & 7u) || ((uintptr_t)grad_tx[i] & 7u) || ((uintptr_t)grad_rx[i] & 7u) ||
+        ((uintptr_t)grad_c[i] & 7u))
+      return fail(SAS_BP_EINVAL, "swath %d: gradient pointer not 8-byte aligned", i);
+  }
+  DeviceGuard guard(p->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<SwathDev> v(n_swaths);
+  long long off = 0;
+  for (int i = 0; i < n_swaths; ++i) {
+    v[i] = make_dev(p->sw[i]);
+    v[i].echo = io[i].echo;
+    v[i].scale = io[i].echo_scale;
+    v[i].tx = io[i].tx_pos;
+    v[i].rx = io[i].rx_pos;
+    v[i].c = io[i].c;
+    v[i].image = reinterpret_cast<float2*>(io[i].image);
+    v[i].gimage = reinterpret_cast<const float2*>(grad_image[i]);
+    v[i].grad_tx = grad_tx[i];
+    v[i].grad_rx = grad_rx[i];
+    v[i].grad_c = grad_c[i];
+    v[i].part_off = off;
+    off += (long long)p->sw[i].ntiles * p->sw[i].d.n_ping * p->sw[i].d.n_elem;
+  }
+  if (!p->adj_buf) {
+    const size_t bytes = sizeof(double) * ((size_t)p->lay.n_partials * kPartial + (size_t)n_swaths * p->max_p);
+    if (hipMalloc(&p->adj_buf, bytes) != hipSuccess) {
+      p->adj_buf = nullptr;
+      return fail(SAS_BP_ENOMEM, "adjoint workspace of %zu bytes could not be allocated", bytes);
+    }
+    p->ws.partials = reinterpret_cast<double*>(p->adj_buf);
+    p->ws.cpart = p->ws.partials + (size_t)p->lay.n_partials * kPartial;
+  }
+  rc = upload(p, v, st);
+  if (rc) return rc;
+  HIP_TRY(launch_init(p->ws, st));
+  HIP_TRY(launch_cull(p->ws, p->n_tiles, p->tiling.TX, p->tiling.TY, p->tiling.TZ, p->bucket_shift, st));
+  HIP_TRY(launch_order(p->ws, p->n_tiles, p->bucket_shift, st));
+  HIP_TRY(launch_adjoint(p->adjoint_fn, p->ws, p->n_tiles, p->adj_grid, p->adj_lds_bytes, st));
+  HIP_TRY(launch_adjoint_reduce(p->ws, n_swaths, p->max_p, st));
+  return SAS_BP_OK;
+}
+
+int sas_bp_useful_updates(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swaths, void* stream, int64_t* counts) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  if (!counts) return fail(SAS_BP_EINVAL, "counts is NULL");
+  int rc = check_io(p, io, n_swaths);
+  if (rc) return rc;
+  DeviceGuard guard(p->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<SwathDev> v(n_swaths);
+  for (int i = 0; i < n_swaths; ++i) {
+    v[i] = make_dev(p->sw[i]);
+    v[i].echo = io[i].echo;
+    v[i].scale = io[i].echo_scale;
+    v[i].tx = io[i].tx_pos;
+    v[i].rx = io[i].rx_pos;
+    v[i].c = io[i].c;
+    v[i].image = reinterpret_cast<float2*>(io[i].image);
+  }
+  rc = upload(p, v, st);
+  if (rc) return rc;
+  unsigned long long* dcount = reinterpret_cast<unsigned long long*>(p->ws.scratch64);
+  for (int i = 0; i < n_swaths; ++i) {
+    const auto& s = p->sw[i].d;
+    if (s.gate_half_angle <= 0.0) {
+      counts[i] = (int64_t)s.n[0] * s.n[1] * s.n[2] * s.n_ping * s.n_elem;
+      continue;
+    }
+    HIP_TRY(launch_count(p->ws, i, s.n_ping, s.n_elem, (int)(s.n[1] * s.n[2]), dcount, st));
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, dcount, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    counts[i] = (int64_t)h;
+  }
+  return SAS_BP_OK;
+}
+
+int sas_bp_sharpness(sas_bp_plan_t p, const void* image, int64_t n_pix, double* out_S, void* grad_image,
+                     void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  if (!image || !out_S) return fail(SAS_BP_EINVAL, "NULL pointer");
+  if (n_pix < 1) return fail(SAS_BP_EINVAL, "n_pix must be >= 1");
+  if (((uintptr_t)image & 7u) || ((uintptr_t)out_S & 7u) || ((uintptr_t)grad_image & 7u))
+    return fail(SAS_BP_EINVAL, "pointer not 8-byte aligned");
+  DeviceGuard guard(p->device);
+  HIP_TRY(launch_sharpness(image, (long long)n_pix, p->ws.scratch64 + 16, out_S, grad_image,
+                           reinterpret_cast<hipStream_t>(stream)));
+  return SAS_BP_OK;
+}
+
+int sas_bp_plan_status(sas_bp_plan_t p) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  DeviceGuard guard(p->device);
+  unsigned h = 0;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(&h, p->ws.counters + 1, sizeof h, hipMemcpyDeviceToHost));
+  const unsigned z = 0;
+  HIP_TRY(hipMemcpy(p->ws.counters + 1, &z, sizeof z, hipMemcpyHostToDevice));
+  return (h & kStatusNav) ? SAS_BP_ENAV : SAS_BP_OK;
+}
+
+int sas_bp_plan_info(sas_bp_plan_t p, int64_t info[8]) {
+  if (!p || !info) return fail(SAS_BP_EINVAL, "NULL argument");
+  info[0] = p->tiling.TX;
+  info[1] = p->tiling.TY;
+  info[2] = p->tiling.TZ;
+  info[3] = p->sw[0].CP;
+  info[4] = p->sw[0].W;
+  info[5] = p->lds_bytes;
+  info[6] = p->grid;
+  info[7] = p->n_tiles;
+  return SAS_BP_OK;
+}
+
+void sas_bp_destroy(sas_bp_plan_t p) { release(p); }
+
+}  // extern "C"

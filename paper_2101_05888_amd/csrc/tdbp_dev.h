@@ -1,0 +1,67 @@
+// Internal types shared by the TDBP kernels and the plan (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sasbp {
+
+// Threads per workgroup of the image and adjoint kernels: lanes are laid out
+// as LX (x) by LY (y) by LZ (z) with LX * LY * LZ == kThreads, and every lane
+// owns K pixels spaced LX apart along x. A tile is (LX*K) x LY x LZ pixels.
+constexpr int kThreads = 256;
+constexpr int kLX = 8;
+constexpr int kMaxElem = 256;
+
+// Per-swath constants and pointers, stored in the plan's workspace so that a
+// captured graph stays valid when the caller passes new buffers.
+struct SwathDev {
+  const void* echo;
+  const float* scale;
+  const double* tx;
+  const double* rx;
+  const double* c;
+  float2* image;
+  const float2* gimage;   // adjoint cotangent (complex64, image layout)
+  double* grad_tx;        // adjoint outputs
+  double* grad_rx;
+  double* grad_c;
+  int P, E, Ns, dtype;
+  int nx, ny, nz;
+  int ntx, nty, ntz;      // tiles per axis
+  int tile0;              // index of this swath's first tile in the global tile list
+  int W;                  // LDS window length per (ping, element), samples (without guard)
+  int CP;                 // pings staged per pass
+  double o[3], d[3];
+  double fc, fs, t0;
+  double tan_g, sin_g;    // gate: tan and sin of the half-angle (0 = off)
+  double c_min;
+  double half_diag;       // distance from a tile's centre to its farthest pixel centre
+  int64_t part_off;       // adjoint: offset of this swath's partials (in records)
+};
+
+// Per-tile ping interval found by the cull pass: pings outside [lo, hi] have
+// no (element, pixel) inside both cones. lo > hi means the tile is empty.
+struct PingRange {
+  int lo, hi;
+};
+
+// Workspace layout (byte offsets into the plan's slab).
+struct Workspace {
+  SwathDev* swaths;       // [n_swaths]
+  PingRange* prange;      // [n_tiles]
+  int* order;             // [n_tiles] processing order (largest cost first)
+  unsigned* counters;     // [0] work counter, [1] status word, [2..] sort scratch
+  unsigned* bucket;       // [kBuckets] histogram / cursors for the cost ordering
+  int* tile_swath;        // [n_tiles] swath of each tile
+  double* partials;       // adjoint: kPartial doubles per (tile, ping, element), allocated on first use
+  double* cpart;          // adjoint: per-(swath, ping) sound-speed partials
+  double* scratch64;      // sharpness partial sums, counters
+};
+
+constexpr int kBuckets = 64;
+constexpr int kPartial = 8;   // gR.xyz, gc, gT.xyz (element 0 only), pad
+
+enum : unsigned { kStatusOk = 0u, kStatusNav = 1u };
+
+}  // namespace sasbp

@@ -1,0 +1,324 @@
+// Image formation: cull -> cost ordering -> persistent backprojection.
+//
+// Backprojection (Eq. 1 inverted per pixel, Sec. II-A) with pixel-stationary
+// accumulation: a workgroup owns one tile of pixels at a time and keeps its
+// complex sums in registers across every ping, so each pixel is written once
+// (the paper's ping-outer loop re-reads and re-writes the image per ping).
+// Pixels are independent (Sec. II-A), so tiles need no atomics and any
+// processing order gives bitwise identical images.
+//
+// Per chunk of pings the workgroup
+//   1. forms the FP64 reference geometry of every (ping, element) and, with a
+//      beam gate, the exact per-row gate intervals (Sec. II-C; transmitter and
+//      receiver tested separately as in the bistatic case, Sec. III-B);
+//   2. copies each (ping, element)'s echo window into LDS with coalesced loads,
+//      zero-filling samples outside the record and converting FP16/BF16
+//      storage to FP32;
+//   3. updates K pixels per lane per (ping, element): FP32 delay offset,
+//      linear interpolation from LDS, carrier phase via the hardware sin/cos
+//      (which take revolutions), complex multiply-accumulate.
+#include "tdbp_geom.h"
+
+namespace sasbp {
+
+__global__ void init_kernel(Workspace ws) {
+  const int t = threadIdx.x;
+  if (t == 0) ws.counters[0] = 0u;
+  if (t < kBuckets) ws.bucket[t] = 0u;
+}
+
+// Conservative per-(tile, ping) test: can any pixel of the tile box lie inside
+// the transmit cone and the cone of some element, and can its delay fall in
+// the record? Keeps a superset of the exact set; the image kernel applies the
+// exact per-row test, so the cull never changes a pixel.
+__device__ __forceinline__ bool cone_may_hit(double tan_g, double xa, double xb, double ya, double yb,
+                                             double za, double zb, const double* X) {
+  const double dxm = fmax(0.0, fmax(xa - X[0], X[0] - xb));
+  const double dy = fmax(fabs(ya - X[1]), fabs(yb - X[1]));
+  const double dz = fmax(fabs(za - X[2]), fabs(zb - X[2]));
+  const double rho = sqrt(dy * dy + dz * dz);
+  return dxm <= tan_g * rho * (1.0 + 1e-9) + 1e-9;
+}
+
+__global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, int TY, int TZ, int bucket_shift) {
+  const int t = blockIdx.x;
+  const int s = __builtin_amdgcn_readfirstlane(ws.tile_swath[t]);
+  const SwathDev& sw = ws.swaths[s];
+  const int lt = t - sw.tile0;
+  const int ix = lt % sw.ntx, iy = (lt / sw.ntx) % sw.nty, iz = lt / (sw.ntx * sw.nty);
+  const double xa = sw.o[0] + (double)(ix * TX) * sw.d[0], xb = xa + (double)(TX - 1) * sw.d[0];
+  const double ya = sw.o[1] + (double)(iy * TY) * sw.d[1], yb = ya + (double)(TY - 1) * sw.d[1];
+  const double za = sw.o[2] + (double)(iz * TZ) * sw.d[2], zb = za + (double)(TZ - 1) * sw.d[2];
+  const double C[3] = {0.5 * (xa + xb), 0.5 * (ya + yb), 0.5 * (za + zb)};
+  const double c = *sw.c;
+  const bool c_ok = isfinite(c) && c >= sw.c_min;
+  __shared__ int s_lo, s_hi;
+  if (threadIdx.x == 0) { s_lo = 0x7fffffff; s_hi = -1; }
+  __syncthreads();
+  if (c_ok) {
+    for (int p = threadIdx.x; p < sw.P; p += blockDim.x) {
+      const double* T = sw.tx + (size_t)p * 3;
+      bool hit = true;
+      // record test: the two-way delay of the tile lies within [dT0+dR0 - 2r, dT0+dR0 + 2r]
+      const double u0 = C[0] - T[0], u1 = C[1] - T[1], u2 = C[2] - T[2];
+      const double dT = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+      bool in_record = false;
+      bool rx_hit = false;
+      for (int e = 0; e < sw.E; ++e) {
+        const double* R = sw.rx + ((size_t)p * sw.E + e) * 3;
+        const double v0 = C[0] - R[0], v1 = C[1] - R[1], v2 = C[2] - R[2];
+        const double dR = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+        const double ulo = ((dT + dR - 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
+        const double uhi = ((dT + dR + 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
+        const bool rec_e = (uhi >= -2.0) && (ulo <= (double)sw.Ns + 1.0);
+        const bool gate_e = sw.tan_g > 0.0 ? cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, R) : true;
+        in_record |= rec_e && gate_e;
+        rx_hit |= gate_e;
+      }
+      if (sw.tan_g > 0.0) hit = cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, T) && rx_hit;
+      // non-finite navigation makes every comparison false; keep such pings so
+      // that the image kernel can flag them
+      const bool bad = !(isfinite(dT));
+      if ((hit && in_record) || bad) {
+        atomicMin(&s_lo, p);
+        atomicMax(&s_hi, p);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    PingRange pr;
+    pr.lo = s_lo;
+    pr.hi = s_hi;
+    if (!c_ok) { pr.lo = 1; pr.hi = 0; atomicOr(&ws.counters[1], kStatusNav); }
+    ws.prange[t] = pr;
+    const long long npe = (pr.hi >= pr.lo) ? (long long)(pr.hi - pr.lo + 1) * sw.E : 0;
+    int b = (int)(npe >> bucket_shift);
+    b = b > kBuckets - 1 ? kBuckets - 1 : b;
+    atomicAdd(&ws.bucket[b], 1u);
+  }
+}
+
+// Single-workgroup counting sort of the tiles by cost bucket, largest first
+// (longest-processing-time order for the persistent kernel). The order inside
+// a bucket depends on atomics; it affects only scheduling, never a pixel.
+__global__ __launch_bounds__(kThreads) void order_kernel(Workspace ws, int n_tiles, int bucket_shift) {
+  __shared__ unsigned cursor[kBuckets];
+  if (threadIdx.x == 0) {
+    unsigned run = 0;
+    for (int b = kBuckets - 1; b >= 0; --b) {
+      cursor[b] = run;
+      run += ws.bucket[b];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const PingRange pr = ws.prange[t];
+    const int s = ws.tile_swath[t];
+    const long long npe = (pr.hi >= pr.lo) ? (long long)(pr.hi - pr.lo + 1) * ws.swaths[s].E : 0;
+    int b = (int)(npe >> bucket_shift);
+    b = b > kBuckets - 1 ? kBuckets - 1 : b;
+    const unsigned slot = atomicAdd(&cursor[b], 1u);
+    ws.order[slot] = t;
+  }
+}
+
+template <int K, int LZ, bool GATE, int DT>
+__global__ __launch_bounds__(kThreads) void image_kernel(Workspace ws, int n_tiles) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  constexpr int LY = kThreads / (kLX * LZ);
+  constexpr int TX = kLX * K, TY = LY, TZ = LZ, ROWS = LY * LZ;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lx = tid % kLX, ly = (tid / kLX) % LY, lz = tid / (kLX * LY);
+  const int row = ly + LY * lz;
+  __shared__ int s_item;
+
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_item = (int)atomicAdd(&ws.counters[0], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    if (item >= n_tiles) break;
+    const int t = __builtin_amdgcn_readfirstlane(ws.order[item]);
+    const int s = __builtin_amdgcn_readfirstlane(ws.tile_swath[t]);
+    const SwathDev& sw = ws.swaths[s];
+    const int E = sw.E, W = sw.W, CP = sw.CP;
+    const int lt = t - sw.tile0;
+    const int tix = lt % sw.ntx, tiy = (lt / sw.ntx) % sw.nty, tiz = lt / (sw.ntx * sw.nty);
+    const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
+    double C[3];
+    C[0] = tile_centre(sw, 0, x0, TX);
+    C[1] = tile_centre(sw, 1, y0, TY);
+    C[2] = tile_centre(sw, 2, z0, TZ);
+    const double c = *sw.c;
+    const float fs_c = (float)(sw.fs / c);
+    const float fc_c = (float)(sw.fc / c);
+    const PingRange pr = ws.prange[t];
+    const LdsLayout L = lds_layout(CP, E, W, ROWS, GATE);
+    TxRec* ltx = reinterpret_cast<TxRec*>(lds + L.off_tx);
+    RxRec* lrx = reinterpret_cast<RxRec*>(lds + L.off_rx);
+    int* ln0 = reinterpret_cast<int*>(lds + L.off_n0);
+    int* lrows = reinterpret_cast<int*>(lds + L.off_rows);
+    float2* lwin = reinterpret_cast<float2*>(lds + L.off_win);
+
+    // per-lane pixel offsets from the tile centre (exact multiples of the spacing)
+    const float sx = (float)sw.d[0], sy = (float)sw.d[1], sz = (float)sw.d[2];
+    float dx[K], dsq[K];
+    const float dyl = (float)(2 * ly - (TY - 1)) * 0.5f * sy;
+    const float dzl = (float)(2 * lz - (TZ - 1)) * 0.5f * sz;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      dx[k] = (float)(2 * (lx + kLX * k) - (TX - 1)) * 0.5f * sx;
+      dsq[k] = dx[k] * dx[k] + dyl * dyl + dzl * dzl;
+    }
+    float accr[K], acci[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { accr[k] = 0.0f; acci[k] = 0.0f; }
+    const float szero = (float)W;   // window guard: two zero samples at [W, W+1]
+
+    for (int p0 = pr.lo; p0 <= pr.hi; p0 += CP) {
+      const int cp = min(CP, pr.hi - p0 + 1);
+      __syncthreads();
+      prepare_chunk<TX, LY, LZ, GATE, DT>(lds, ws, sw, c, C, p0, cp, x0, y0, z0, L, tid, lane, wave);
+      // 3. accumulate
+      for (int slot = 0; slot < cp; ++slot) {
+        const TxRec tr = ltx[slot];
+        const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
+        float dT[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float num = fmaf(tr.ux2, dx[k], tyz + dsq[k]);
+          const float sq = __builtin_amdgcn_sqrtf(tr.d0sq + num);
+          dT[k] = num * __builtin_amdgcn_rcpf(tr.d0 + sq);
+        }
+        for (int e = 0; e < E; ++e) {
+          const int r = slot * E + e;
+          const RxRec rec = lrx[r];
+          const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(rec.flags));
+          if (f & kFlagSkip) continue;
+          const bool test = GATE && !(f & kFlagFull);
+          int da = 0, span = 0;
+          if (test) {
+            const int v = lrows[r * ROWS + row];
+            const int a = row_lo(v), b = row_hi(v);
+            da = lx - a;
+            span = b - a;
+          }
+          const float ryz = fmaf(rec.uy2, dyl, rec.uz2 * dzl);
+          const float2* win = lwin + (size_t)r * (W + 2);
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const float num = fmaf(rec.ux2, dx[k], ryz + dsq[k]);
+            const float sq = __builtin_amdgcn_sqrtf(rec.d0sq + num);
+            const float dR = num * __builtin_amdgcn_rcpf(rec.d0 + sq);
+            const float D = dT[k] + dR;
+            float sidx = fmaf(D, fs_c, rec.s0);
+            const float cyc = __builtin_amdgcn_fractf(fmaf(D, fc_c, rec.phi0));
+            if (test) {
+              const bool in = (unsigned)(da + kLX * k) <= (unsigned)span;
+              sidx = in ? sidx : szero;
+            }
+            const float sn = __builtin_amdgcn_sinf(cyc);
+            const float cs = __builtin_amdgcn_cosf(cyc);
+            int n = (int)sidx;
+            n = n < 0 ? 0 : (n > W ? W : n);
+            const float w = __builtin_amdgcn_fractf(sidx);
+            const float2 a = win[n];
+            const float2 b = win[n + 1];
+            const float vr = fmaf(w, b.x - a.x, a.x);
+            const float vi = fmaf(w, b.y - a.y, a.y);
+            accr[k] = fmaf(vr, cs, accr[k]);
+            accr[k] = fmaf(-vi, sn, accr[k]);
+            acci[k] = fmaf(vr, sn, acci[k]);
+            acci[k] = fmaf(vi, cs, acci[k]);
+          }
+        }
+      }
+    }
+    // write the tile once
+    const int iy = y0 + ly, iz = z0 + lz;
+    if (iy < sw.ny && iz < sw.nz) {
+      float2* out = sw.image + ((size_t)iz * sw.ny + iy) * (size_t)sw.nx;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int ix = x0 + lx + kLX * k;
+        if (ix < sw.nx) out[ix] = make_float2(accr[k], acci[k]);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ dispatch ---
+
+typedef void (*ImageKernelFn)(Workspace, int);
+
+template <int K, int LZ, bool G>
+static ImageKernelFn pick_dt(int dt) {
+  switch (dt) {
+    case 0: return image_kernel<K, LZ, G, 0>;
+    case 1: return image_kernel<K, LZ, G, 1>;
+    default: return image_kernel<K, LZ, G, 2>;
+  }
+}
+
+template <int K, int LZ>
+static ImageKernelFn pick_gate(bool gate, int dt) {
+  return gate ? pick_dt<K, LZ, true>(dt) : pick_dt<K, LZ, false>(dt);
+}
+
+template <int K>
+static ImageKernelFn pick_lz(int lz, bool gate, int dt) {
+  switch (lz) {
+    case 1: return pick_gate<K, 1>(gate, dt);
+    case 2: return pick_gate<K, 2>(gate, dt);
+    case 4: return pick_gate<K, 4>(gate, dt);
+    default: return nullptr;
+  }
+}
+
+ImageKernelFn image_kernel_for(int K, int LZ, bool gate, int dt) {
+  switch (K) {
+    case 2: return pick_lz<2>(LZ, gate, dt);
+    case 4: return pick_lz<4>(LZ, gate, dt);
+    case 8: return pick_lz<8>(LZ, gate, dt);
+    default: return nullptr;
+  }
+}
+
+int image_lds_bytes(int CP, int E, int W, int ROWS, bool gate) {
+  return lds_layout(CP, E, W, ROWS, gate).bytes;
+}
+
+hipError_t launch_init(const Workspace& ws, hipStream_t st) {
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(64), 0, st, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_cull(const Workspace& ws, int n_tiles, int TX, int TY, int TZ, int bucket_shift,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(cull_kernel, dim3(n_tiles), dim3(kThreads), 0, st, ws, TX, TY, TZ, bucket_shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const Workspace& ws, int n_tiles, int bucket_shift, hipStream_t st) {
+  hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kThreads), 0, st, ws, n_tiles, bucket_shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int grid, int lds_bytes,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds_bytes, st, ws, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t image_occupancy(ImageKernelFn fn, int lds_bytes, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds_bytes);
+}
+
+hipError_t set_image_lds_limit(ImageKernelFn fn, int lds_bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             lds_bytes);
+}
+
+}  // namespace sasbp

@@ -1,0 +1,74 @@
+"""Shared test plumbing: scenario -> C-ABI descriptors/buffers, oracle calls."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import torch
+
+import oracle
+from synth import Scenario, synthesize_echo, quantize_echo, dequantize_echo
+
+# FP32 path bounds against the FP64 oracle (relative L2 over the compared
+# pixels; phase over pixels within 30 dB of the reference peak).
+FP32_REL_L2 = 1e-4
+FP32_PHASE_MRAD = 10.0
+# 16-bit echo storage, error against the oracle on the original FP32 echo.
+# Derivation: per-component relative rounding ~u/sqrt(3) of the ping's peak
+# with u = 2^-11 (FP16) or 2^-8 (BF16) gives about 2.8e-4 and 2.3e-3 relative
+# L2 for these scenes; the bounds leave a factor of ~2-3.
+F16_REL_L2, F16_PHASE_MRAD = 1e-3, 30.0
+BF16_REL_L2, BF16_PHASE_MRAD = 5e-3, 100.0
+
+
+def workers() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def desc_for(api, scn: Scenario, echo_dtype: str = "c64", c_min: float = 0.0):
+    g = scn.grid
+    return api.swath_desc(scn.n_ping, scn.n_elem, scn.n_sample, g.n, g.origin, g.spacing,
+                          scn.fc, scn.fs, scn.t0, scn.gate_half_angle, echo_dtype, c_min)
+
+
+def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scale=None,
+                tx=None, rx=None, c=None):
+    g = scn.grid
+    dev = torch.device(device)
+    tx = scn.tx if tx is None else tx
+    rx = scn.rx if rx is None else rx
+    return api.SwathBuffers(
+        echo=echo.to(dev).contiguous(),
+        tx=torch.as_tensor(np.ascontiguousarray(tx), dtype=torch.float64, device=dev),
+        rx=torch.as_tensor(np.ascontiguousarray(rx), dtype=torch.float64, device=dev),
+        c=torch.tensor([scn.c if c is None else c], dtype=torch.float64, device=dev),
+        image=torch.zeros((g.n[2], g.n[1], g.n[0]), dtype=torch.complex64, device=dev),
+        echo_scale=None if echo_scale is None else echo_scale.to(dev).contiguous(),
+    )
+
+
+def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_scale=None, **plan_kw):
+    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype)], **plan_kw)
+    buf = buffers_for(api, scn, echo, echo_scale=echo_scale)
+    api.sas_bp_image(plan, [buf])
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    return buf.image.cpu().numpy(), plan, buf
+
+
+def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None):
+    g = scn.grid
+    pts = oracle.pixel_points(g.origin, g.spacing, g.n, index)
+    return oracle.backproject(echo_np, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
+                              scn.gate_half_angle, workers=workers())
+
+
+def report(name, img, ref):
+    r = oracle.rel_l2(img, ref)
+    ph = oracle.phase_error_mrad(img, ref)
+    print(f"[{name}] rel_l2={r:.3e} max_phase={ph:.3f} mrad", flush=True)
+    return r, ph

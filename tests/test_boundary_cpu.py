@@ -1,0 +1,102 @@
+"""The C-ABI library on a host without a GPU: it loads, exports every symbol
+the header declares, and rejects bad arguments before touching a device."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sas_bp.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(sas_bp_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2101_05888_amd import _native as N
+    names = _declared()
+    assert "sas_bp_plan" in names and "sas_bp_image" in names and "sas_bp_adjoint" in names
+    for n in names:
+        assert hasattr(N.lib, n), n
+    assert set(N.EXPORTED) == set(names)
+
+
+def test_abi_version_and_error_strings():
+    from paper_2101_05888_amd import _native as N
+    assert N.lib.sas_bp_abi_version() == 1
+    for s in range(6):
+        assert N.lib.sas_bp_error_string(s)
+    assert N.lib.sas_bp_error_string(99) == b"unknown status"
+
+
+def _desc(api, **kw):
+    base = dict(n_ping=64, n_elem=8, n_sample=4096, n=(256, 256, 1), origin=(2.8, 20.0, 0.0),
+                spacing=(0.015, 0.015, 0.015), f_c=100e3, f_s=80e3)
+    base.update(kw)
+    return api.swath_desc(**base)
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(n_ping=0), 1), (dict(n_elem=0), 1), (dict(n_elem=300), 1), (dict(n_sample=1), 1),
+    (dict(n=(0, 5, 1)), 1), (dict(spacing=(0.0, 0.015, 0.015)), 1), (dict(f_s=0.0), 1),
+    (dict(f_s=math.nan), 1), (dict(f_c=-1.0), 1), (dict(t0=math.inf), 1),
+    (dict(gate_half_angle=2.0), 1), (dict(gate_half_angle=-0.1), 1), (dict(c_min=-1.0), 1),
+    (dict(origin=(math.nan, 0.0, 0.0)), 1), (dict(n=(4096, 4096, 2048)), 2),
+])
+def test_host_validation(bad, status):
+    import paper_2101_05888_amd as api
+    with pytest.raises(api.SasBpError) as ei:
+        api.sas_bp_workspace_size([_desc(api, **bad)])
+    assert ei.value.status == status
+
+
+def test_bad_dtype_and_tile_are_unsupported():
+    import paper_2101_05888_amd as api
+    d = _desc(api)
+    d.echo_dtype = 7
+    with pytest.raises(api.SasBpError) as ei:
+        api.sas_bp_workspace_size([d])
+    assert ei.value.status == 2
+    with pytest.raises(api.SasBpError) as ei:
+        api.sas_bp_workspace_size([_desc(api)], tile=(24, 0, 0))
+    assert ei.value.status == 2
+
+
+def test_workspace_size_scales_with_tiles():
+    import paper_2101_05888_amd as api
+    a = api.sas_bp_workspace_size([_desc(api)])
+    b = api.sas_bp_workspace_size([_desc(api, n=(2048, 2048, 1))])
+    assert 0 < a < b
+
+
+def test_plan_without_device_reports_device_error():
+    import torch
+    import paper_2101_05888_amd as api
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(api.SasBpError) as ei:
+        api.sas_bp_plan([_desc(api)])
+    assert ei.value.status == 4
+
+
+def test_null_arguments_rejected():
+    from paper_2101_05888_amd import _native as N
+    assert N.lib.sas_bp_plan(None, 1, None, None) == 1
+    assert N.lib.sas_bp_image(None, None, 1, None) == 1
+    assert N.lib.sas_bp_plan_status(None) == 1
+    out = C.c_size_t()
+    assert N.lib.sas_bp_workspace_size(None, 1, None, C.byref(out)) == 1
+
+
+def test_product_path_has_no_oracle_or_cpu_fallback():
+    # the package must not import the oracle or the input generator
+    pkg = os.path.join(ROOT, "paper_2101_05888_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            src = open(os.path.join(pkg, fn)).read()
+            assert "import oracle" not in src and "from oracle" not in src, fn
+            assert "import synth" not in src and "from synth" not in src, fn
