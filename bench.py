@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: time-domain backprojection throughput on one MI355X.
+
+Workload (the operational-size stripmap swath): 512 pings at 0.3 m spacing,
+32 receivers at 3.75 cm pitch, 16384 complex samples per (ping, receiver)
+(c = 1500 m/s, f_c = 100 kHz, B = 20 kHz, f_s = 80 kHz), a 4096 x 4096 pixel
+image at 1.5 cm spacing over 20-81.4 m ground range, every receiver's
+contribution gated to +-10 deg about broadside; 2000 point targets plus 1e5
+weak speckle scatterers plus noise at 20 dB SNR, all seeded and synthetic.
+
+A step is one call of ``sas_bp_image``: the captured graph runs the cull, the
+cost ordering and the persistent image kernel over the whole swath, with the
+echo cube, navigation and image already resident in HBM. The metric counts
+useful pixel-ping-element updates (terms inside both beam cones), the count
+coming from the library and checked against the oracle in the tests.
+
+Printed: one JSON line (metric, value, roofline of the image kernel, the
+FP16/BF16 echo forms with their speed-up and error, and the FP64 oracle timed
+on the host cores on a bounded pixel sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3           # MI355X FP32 vector peak (256 CU x 2.4 GHz)
+METRIC = "pixel·ping·element updates/s; mixed vs FP32 at ≤1e-4 rel-L2 vs FP64 oracle"
+
+
+def flops_per_update(n_elem: int) -> float:
+    """Algorithmic FLOPs of one (pixel, ping, element) term of the sum.
+
+    d_R = |p - R| (3 sub, 3 mul, 2 add, sqrt: 9), tau = (d_T + d_R) / c (2),
+    u = (tau - t0) f_s (2), floor and fraction (2), complex lerp a + w (b - a)
+    (6), carrier argument and sin/cos (3), complex multiply (6) and accumulate
+    (2): 32, plus the transmitter leg d_T (9) shared by the E elements.
+    """
+    return 32.0 + 9.0 / n_elem
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_steps(fn, steps: int, warmup: int) -> float:
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def cpu_baseline_leg(scn, echo_cpu: np.ndarray, images: dict, sample: int) -> dict:
+    """Time the FP64 oracle on a seeded pixel sample on the host cores and
+    compare every GPU form with it on the same pixels."""
+    import oracle
+    from synth import subset_indices
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    idx = subset_indices(scn, sample)
+    g = scn.grid
+    pts = oracle.pixel_points(g.origin, g.spacing, g.n, idx)
+    t0 = time.perf_counter()
+    ref, useful = oracle.backproject(echo_cpu, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
+                                     scn.gate_half_angle, workers=workers, return_count=True)
+    dt = time.perf_counter() - t0
+    acc = {}
+    for name, img in images.items():
+        got = img.reshape(-1)[idx]
+        acc[name] = {"rel_l2": oracle.rel_l2(got, ref),
+                     "max_phase_mrad": oracle.phase_error_mrad(got, ref),
+                     "p99_phase_mrad": oracle.phase_error_mrad(got, ref, stat="p99")}
+    return {"value": useful / dt, "unit": "updates/s", "cores": workers, "kind": "oracle",
+            "sample": f"{sample} seeded pixels of the same swath, all 512x32 (ping, element) terms "
+                      f"evaluated and gated ({useful} useful updates) in {dt:.1f} s",
+            "seconds": dt, "useful_updates": int(useful), "accuracy": acc}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device visible"}), flush=True)
+        return 3
+    if args.profile:
+        args.no_cpu_baseline = True
+
+    import paper_2101_05888_amd as api
+    from synth import make_config, synthesize_echo, quantize_echo
+
+    scn = make_config("c2")
+    log("synthesizing echoes")
+    t = time.perf_counter()
+    echo = synthesize_echo(scn, device="cuda", dtype=torch.complex64)
+    torch.cuda.synchronize()
+    log(f"synthesized {tuple(echo.shape)} in {time.perf_counter() - t:.1f} s")
+    g = scn.grid
+
+    def make(echo_t, kind="c64", scale=None):
+        d = api.swath_desc(scn.n_ping, scn.n_elem, scn.n_sample, g.n, g.origin, g.spacing, scn.fc, scn.fs,
+                           scn.t0, scn.gate_half_angle, kind)
+        plan = api.sas_bp_plan([d])
+        buf = api.SwathBuffers(
+            echo=echo_t, tx=torch.as_tensor(scn.tx, device="cuda"), rx=torch.as_tensor(scn.rx, device="cuda"),
+            c=torch.tensor([scn.c], dtype=torch.float64, device="cuda"),
+            image=torch.empty((g.n[2], g.n[1], g.n[0]), dtype=torch.complex64, device="cuda"),
+            echo_scale=scale)
+        return plan, buf
+
+    if args.profile:
+        # calibration for HBM byte counters: a plain copy of exactly 256 MiB
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    plan, buf = make(echo)
+    useful = api.sas_bp_useful_updates(plan, [buf])[0]
+    nominal = scn.nominal_updates()
+    info = plan.info()
+    log(f"plan {info}; useful updates {useful} of {nominal}")
+    ms = time_steps(lambda: api.sas_bp_image(plan, [buf]), args.steps, args.warmup)
+    if plan.status() != 0:
+        log("device reported bad navigation")
+        return 4
+    value = useful / (ms * 1e-3)
+    log(f"fp32: {ms:.3f} ms/step, {value:.4e} useful updates/s")
+    fpu = flops_per_update(scn.n_elem)
+    achieved = value * fpu / 1e12
+    images = {"fp32": buf.image.cpu().numpy()}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "stripmap swath 4096x4096 px at 1.5 cm, 512 pings x 32 receivers, "
+                               "16384 samples, +-10 deg tx/rx gate, 2000 targets + 1e5 speckle",
+                   "pings": scn.n_ping, "elements": scn.n_elem, "samples": scn.n_sample,
+                   "pixels": g.n_pix, "useful_updates": int(useful), "nominal_updates": int(nominal),
+                   "tile": [info["tile_x"], info["tile_y"], info["tile_z"]],
+                   "pings_per_chunk": info["pings_per_chunk"], "grid": info["grid"]},
+        "nominal_updates_per_s": nominal / (ms * 1e-3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "flops_per_update": fpu, "kernel": "image_kernel (graph: cull + order + image)"},
+    }
+
+    if not args.no_mixed:
+        mixed = {}
+        for kind in ("f16", "bf16"):
+            q, scale = quantize_echo(echo, kind)
+            p2, b2 = make(q, kind, scale.cuda())
+            ms2 = time_steps(lambda: api.sas_bp_image(p2, [b2]), args.steps, args.warmup)
+            mixed[kind] = {"value": useful / (ms2 * 1e-3), "ms_per_step": ms2, "speedup_vs_fp32": ms / ms2}
+            images[kind] = b2.image.cpu().numpy()
+            log(f"{kind}: {ms2:.3f} ms/step ({ms / ms2:.3f}x)")
+            p2.destroy()
+            del q, b2
+        out["mixed"] = mixed
+
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host cores")
+        echo_cpu = echo.cpu().numpy()
+        cb = cpu_baseline_leg(scn, echo_cpu, images, args.cpu_sample)
+        acc = cb.pop("accuracy")
+        out["cpu_baseline"] = cb
+        out["accuracy_vs_oracle"] = acc
+        for kind in out.get("mixed", {}):
+            out["mixed"][kind].update(acc.get(kind, {}))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -96,6 +96,7 @@ typedef struct {
     int32_t device;          /* HIP device ordinal                             */
     int32_t tile_x, tile_y, tile_z; /* pixel tile shape; 0 = automatic         */
     int32_t pings_per_chunk; /* pings staged in LDS per pass; 0 = automatic   */
+    int32_t threads;         /* threads per workgroup (256 or 512); 0 = automatic */
     int32_t use_graph;       /* 1 = replay a captured HIP graph (default), 0 = direct launches */
     size_t workspace_limit;  /* bytes; 0 = unlimited                           */
 } sas_bp_options;
@@ -159,7 +160,8 @@ int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, doubl
 int sas_bp_plan_status(sas_bp_plan_t plan);
 
 /* Chosen tiling, for reporting: tile_x, tile_y, tile_z, pings_per_chunk,
- * window samples, LDS bytes per workgroup, workgroups launched. */
+ * window samples, LDS bytes per workgroup, workgroups launched, threads per
+ * workgroup. */
 int sas_bp_plan_info(sas_bp_plan_t plan, int64_t info[8]);
 
 void sas_bp_destroy(sas_bp_plan_t plan);

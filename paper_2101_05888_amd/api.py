@@ -35,11 +35,13 @@ def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin
     return d
 
 
-def _options(device=0, tile=(0, 0, 0), pings_per_chunk=0, use_graph=True, workspace_limit=0) -> N.Options:
+def _options(device=0, tile=(0, 0, 0), pings_per_chunk=0, use_graph=True, workspace_limit=0,
+             threads=0) -> N.Options:
     o = N.Options()
     o.device = int(device)
     o.tile_x, o.tile_y, o.tile_z = (int(v) for v in tile)
     o.pings_per_chunk = int(pings_per_chunk)
+    o.threads = int(threads)
     o.use_graph = 1 if use_graph else 0
     o.workspace_limit = int(workspace_limit)
     return o
@@ -56,7 +58,7 @@ class Plan:
     def info(self) -> dict:
         arr = (C.c_int64 * 8)()
         check(N.lib.sas_bp_plan_info(self.handle, arr), "sas_bp_plan_info")
-        keys = ("tile_x", "tile_y", "tile_z", "pings_per_chunk", "window", "lds_bytes", "grid", "tiles")
+        keys = ("tile_x", "tile_y", "tile_z", "pings_per_chunk", "window", "lds_bytes", "grid", "threads")
         return dict(zip(keys, (int(v) for v in arr)))
 
     def status(self) -> int:
@@ -75,19 +77,20 @@ class Plan:
 
 
 def sas_bp_plan(descs: Sequence[N.SwathDesc], device: int = 0, tile=(0, 0, 0), pings_per_chunk: int = 0,
-                use_graph: bool = True, workspace_limit: int = 0) -> Plan:
+                use_graph: bool = True, workspace_limit: int = 0, threads: int = 0) -> Plan:
     descs = list(descs)
     arr = (N.SwathDesc * len(descs))(*descs)
-    opt = _options(device, tile, pings_per_chunk, use_graph, workspace_limit)
+    opt = _options(device, tile, pings_per_chunk, use_graph, workspace_limit, threads)
     out = C.c_void_p()
     check(N.lib.sas_bp_plan(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_plan")
     return Plan(out.value, descs, device)
 
 
-def sas_bp_workspace_size(descs: Sequence[N.SwathDesc], tile=(0, 0, 0), pings_per_chunk: int = 0) -> int:
+def sas_bp_workspace_size(descs: Sequence[N.SwathDesc], tile=(0, 0, 0), pings_per_chunk: int = 0,
+                          threads: int = 0) -> int:
     descs = list(descs)
     arr = (N.SwathDesc * len(descs))(*descs)
-    opt = _options(0, tile, pings_per_chunk)
+    opt = _options(0, tile, pings_per_chunk, threads=threads)
     out = C.c_size_t()
     check(N.lib.sas_bp_workspace_size(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_workspace_size")
     return int(out.value)

@@ -24,20 +24,22 @@
 
 namespace sasbp {
 typedef void (*ImageKernelFn)(Workspace, int);
-ImageKernelFn image_kernel_for(int K, int LZ, bool gate, int dt);
+ImageKernelFn image_kernel_for(int layout, bool gate, int dt);
 int image_lds_bytes(int CP, int E, int W, int ROWS, bool gate);
 hipError_t launch_init(const Workspace& ws, hipStream_t st);
 hipError_t launch_cull(const Workspace& ws, int n_tiles, int TX, int TY, int TZ, int bucket_shift, hipStream_t st);
 hipError_t launch_order(const Workspace& ws, int n_tiles, int bucket_shift, hipStream_t st);
-hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int grid, int lds_bytes, hipStream_t st);
-hipError_t image_occupancy(ImageKernelFn fn, int lds_bytes, int* blocks_per_cu);
+hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads, int lds_bytes,
+                        hipStream_t st);
+hipError_t image_occupancy(ImageKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu);
 hipError_t set_image_lds_limit(ImageKernelFn fn, int lds_bytes);
 
 typedef void (*AdjointKernelFn)(Workspace, int);
-AdjointKernelFn adjoint_kernel_for(int K, int LZ, bool gate, int dt);
-int adjoint_lds_bytes(int CP, int E, int W, int ROWS, bool gate);
-hipError_t launch_adjoint(AdjointKernelFn fn, const Workspace& ws, int n_tiles, int grid, int lds_bytes, hipStream_t st);
-hipError_t adjoint_occupancy(AdjointKernelFn fn, int lds_bytes, int* blocks_per_cu);
+AdjointKernelFn adjoint_kernel_for(int layout, bool gate, int dt);
+int adjoint_lds_bytes(int CP, int E, int W, int ROWS, bool gate, int threads);
+hipError_t launch_adjoint(AdjointKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads, int lds_bytes,
+                          hipStream_t st);
+hipError_t adjoint_occupancy(AdjointKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu);
 hipError_t set_adjoint_lds_limit(AdjointKernelFn fn, int lds_bytes);
 hipError_t launch_adjoint_reduce(const Workspace& ws, int n_swaths, int max_p, hipStream_t st);
 hipError_t launch_count(const Workspace& ws, int s, int P, int E, int rows, unsigned long long* out, hipStream_t st);
@@ -75,8 +77,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Tiling {
-  int K, LZ, TX, TY, TZ;
+  int layout, K, LX, LY, LZ, TX, TY, TZ, NT;
 };
+
+constexpr int kLdsMax = 160 * 1024;
 
 struct SwathPlan {
   sas_bp_swath_desc d;
@@ -148,9 +152,11 @@ int validate(const sas_bp_swath_desc* d, int i) {
   return SAS_BP_OK;
 }
 
-// Tile shape: 2D images use LZ = 1 (tiles of 8K x 32 pixels); 3D volumes
-// LZ = 4 (8K x 8 x 4 voxels). K from the options or from the image size, so
-// that small images still produce enough tiles to occupy the GPU.
+// Tile shape from the lane-layout menu. An explicit tile (and optionally the
+// threads per workgroup) must match a menu entry; otherwise 2D images use
+// 64 x 32 pixel tiles on 512 threads (16 x 32 on 256 threads for small images,
+// so that they still give enough tiles to occupy the GPU) and 3D volumes use
+// 32 x 8 x 4 voxel tiles on 256 threads.
 int choose_tiling(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, Tiling* t) {
   bool any3d = false;
   long long pix = 0;
@@ -158,29 +164,33 @@ int choose_tiling(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, Ti
     any3d |= d[i].n[2] > 1;
     pix += (long long)d[i].n[0] * d[i].n[1] * d[i].n[2];
   }
-  int LZ = any3d ? 4 : 1;
-  int K = 4;
-  if (o && (o->tile_x || o->tile_y || o->tile_z)) {
-    const int tz = o->tile_z ? o->tile_z : LZ;
-    if (tz != 1 && tz != 2 && tz != 4) return fail(SAS_BP_EUNSUPPORTED, "tile_z must be 1, 2 or 4");
-    LZ = tz;
-    const int ty = kThreads / (kLX * LZ);
-    if (o->tile_y && o->tile_y != ty) return fail(SAS_BP_EUNSUPPORTED, "tile_y must be %d for tile_z %d", ty, LZ);
-    if (o->tile_x) {
-      if (o->tile_x != 16 && o->tile_x != 32 && o->tile_x != 64) return fail(SAS_BP_EUNSUPPORTED, "tile_x must be 16, 32 or 64");
-      K = o->tile_x / kLX;
+  int layout = any3d ? 6 : (pix < (1ll << 20) ? 0 : 2);
+  if (o && (o->tile_x || o->tile_y || o->tile_z || o->threads)) {
+    layout = -1;
+    for (int l = 0; l < kNumLayouts && layout < 0; ++l) {
+      const LaneLayout& L = kLayouts[l];
+      const int tx = L.LX * L.K, ty = L.LY, tz = L.LZ, nt = L.LX * L.LY * L.LZ;
+      if (o->tile_x && o->tile_x != tx) continue;
+      if (o->tile_y && o->tile_y != ty) continue;
+      if (o->tile_z && o->tile_z != tz) continue;
+      if (!o->tile_z && (tz > 1) != any3d) continue;
+      if (o->threads && o->threads != nt) continue;
+      layout = l;
     }
-  } else if (pix < (1ll << 20)) {
-    K = 2;
+    if (layout < 0)
+      return fail(SAS_BP_EUNSUPPORTED, "no tiling with tile %dx%dx%d and %d threads", o->tile_x, o->tile_y,
+                  o->tile_z, o->threads);
   }
-  if (!any3d && LZ != 1) {
-    // a 2D image tiled in z would waste lanes; allowed only when asked for explicitly
-  }
-  t->K = K;
-  t->LZ = LZ;
-  t->TX = kLX * K;
-  t->TY = kThreads / (kLX * LZ);
-  t->TZ = LZ;
+  const LaneLayout& L = kLayouts[layout];
+  t->layout = layout;
+  t->K = L.K;
+  t->LX = L.LX;
+  t->LY = L.LY;
+  t->LZ = L.LZ;
+  t->TX = L.LX * L.K;
+  t->TY = L.LY;
+  t->TZ = L.LZ;
+  t->NT = L.LX * L.LY * L.LZ;
   return SAS_BP_OK;
 }
 
@@ -217,7 +227,7 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
       cp = 1;
       while (cp < 8 && image_lds_bytes(cp * 2, d[i].n_elem, s.W, rows, gate) <= kLdsBudget) cp *= 2;
     }
-    if (image_lds_bytes(cp, d[i].n_elem, s.W, rows, gate) > 160 * 1024)
+    if (image_lds_bytes(cp, d[i].n_elem, s.W, rows, gate) > kLdsMax - 1024)
       return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d pings x %d elements x %d samples exceed LDS", i, cp,
                   d[i].n_elem, s.W);
     s.CP = cp;
@@ -315,7 +325,7 @@ int enqueue_image(sas_bp_plan_s* p, hipStream_t st) {
   HIP_TRY(launch_init(p->ws, st));
   HIP_TRY(launch_cull(p->ws, p->n_tiles, p->tiling.TX, p->tiling.TY, p->tiling.TZ, p->bucket_shift, st));
   HIP_TRY(launch_order(p->ws, p->n_tiles, p->bucket_shift, st));
-  HIP_TRY(launch_image(p->image_fn, p->ws, p->n_tiles, p->grid, p->lds_bytes, st));
+  HIP_TRY(launch_image(p->image_fn, p->ws, p->n_tiles, p->grid, p->tiling.NT, p->lds_bytes, st));
   return SAS_BP_OK;
 }
 
@@ -431,6 +441,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   if (options && options->workspace_limit && lay.total > options->workspace_limit)
     return fail(SAS_BP_ENOMEM, "workspace needs %zu bytes, limit is %zu", lay.total, options->workspace_limit);
   const int device = options ? options->device : 0;
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
   int n_dev = 0;
   if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev <= 0) return fail(SAS_BP_EDEVICE, "no HIP device");
   if (device < 0 || device >= n_dev) return fail(SAS_BP_EINVAL, "device %d out of range", device);
@@ -461,7 +472,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   }
   for (const auto& s : sw) {
     max_lds = std::max(max_lds, image_lds_bytes(s.CP, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any));
-    max_adj_lds = std::max(max_adj_lds, adjoint_lds_bytes(s.CP, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any));
+    max_adj_lds = std::max(max_adj_lds, adjoint_lds_bytes(s.CP, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any, t.NT));
   }
   p->max_pe = max_pe;
   int shift = 0;
@@ -469,20 +480,26 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->bucket_shift = shift;
   p->lds_bytes = max_lds;
   p->adj_lds_bytes = max_adj_lds;
-  p->image_fn = image_kernel_for(t.K, t.LZ, p->gate_any, p->dtype);
-  p->adjoint_fn = adjoint_kernel_for(t.K, t.LZ, p->gate_any, p->dtype);
+  p->image_fn = image_kernel_for(t.layout, p->gate_any, p->dtype);
+  p->adjoint_fn = adjoint_kernel_for(t.layout, p->gate_any, p->dtype);
   if (!p->image_fn || !p->adjoint_fn) {
     release(p);
-    return fail(SAS_BP_EUNSUPPORTED, "no kernel for K=%d LZ=%d", t.K, t.LZ);
+    return fail(SAS_BP_EUNSUPPORTED, "no kernel for tiling %d", t.layout);
   }
-  hipError_t e = set_image_lds_limit(p->image_fn, max_lds);
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, device);
+  if (e == hipSuccess && (size_t)std::max(max_lds, max_adj_lds) + 1024 > prop.sharedMemPerBlock) {
+    release(p);
+    return fail(SAS_BP_EUNSUPPORTED, "tiling needs %d bytes of LDS, the device allows %zu per workgroup",
+                std::max(max_lds, max_adj_lds), (size_t)prop.sharedMemPerBlock);
+  }
+  if (e == hipSuccess) e = set_image_lds_limit(p->image_fn, max_lds);
   if (e == hipSuccess) e = set_adjoint_lds_limit(p->adjoint_fn, max_adj_lds);
   int occ = 0, adj_occ = 0;
-  if (e == hipSuccess) e = image_occupancy(p->image_fn, max_lds, &occ);
-  if (e == hipSuccess) e = adjoint_occupancy(p->adjoint_fn, max_adj_lds, &adj_occ);
-  hipDeviceProp_t prop;
-  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
+  if (e == hipSuccess) e = image_occupancy(p->image_fn, t.NT, max_lds, &occ);
+  if (e == hipSuccess) e = adjoint_occupancy(p->adjoint_fn, t.NT, max_adj_lds, &adj_occ);
   if (e != hipSuccess) {
+    (void)hipGetLastError();
     release(p);
     return fail(SAS_BP_EDEVICE, "kernel setup failed: %s", hipGetErrorString(e));
   }
@@ -535,6 +552,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
 
 int sas_bp_image(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swaths, void* stream) {
   if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   DeviceGuard guard(p->device);
@@ -562,6 +580,7 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
                    double* const* grad_tx, double* const* grad_rx, double* const* grad_c, int n_swaths,
                    void* stream) {
   if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   if (!grad_image || !grad_tx || !grad_rx || !grad_c) return fail(SAS_BP_EINVAL, "gradient array is NULL");
@@ -605,13 +624,14 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
   HIP_TRY(launch_init(p->ws, st));
   HIP_TRY(launch_cull(p->ws, p->n_tiles, p->tiling.TX, p->tiling.TY, p->tiling.TZ, p->bucket_shift, st));
   HIP_TRY(launch_order(p->ws, p->n_tiles, p->bucket_shift, st));
-  HIP_TRY(launch_adjoint(p->adjoint_fn, p->ws, p->n_tiles, p->adj_grid, p->adj_lds_bytes, st));
+  HIP_TRY(launch_adjoint(p->adjoint_fn, p->ws, p->n_tiles, p->adj_grid, p->tiling.NT, p->adj_lds_bytes, st));
   HIP_TRY(launch_adjoint_reduce(p->ws, n_swaths, p->max_p, st));
   return SAS_BP_OK;
 }
 
 int sas_bp_useful_updates(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swaths, void* stream, int64_t* counts) {
   if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
   if (!counts) return fail(SAS_BP_EINVAL, "counts is NULL");
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
@@ -648,6 +668,7 @@ int sas_bp_useful_updates(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swat
 int sas_bp_sharpness(sas_bp_plan_t p, const void* image, int64_t n_pix, double* out_S, void* grad_image,
                      void* stream) {
   if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
   if (!image || !out_S) return fail(SAS_BP_EINVAL, "NULL pointer");
   if (n_pix < 1) return fail(SAS_BP_EINVAL, "n_pix must be >= 1");
   if (((uintptr_t)image & 7u) || ((uintptr_t)out_S & 7u) || ((uintptr_t)grad_image & 7u))
@@ -678,7 +699,7 @@ int sas_bp_plan_info(sas_bp_plan_t p, int64_t info[8]) {
   info[4] = p->sw[0].W;
   info[5] = p->lds_bytes;
   info[6] = p->grid;
-  info[7] = p->n_tiles;
+  info[7] = p->tiling.NT;
   return SAS_BP_OK;
 }
 

@@ -32,18 +32,20 @@ __device__ __forceinline__ float wave_sum(float v) {
 __host__ __device__ inline int adjoint_red_offset(int CP, int E, int W, int ROWS, bool gate) {
   return (lds_layout(CP, E, W, ROWS, gate).bytes + 15) & ~15;
 }
-__host__ __device__ inline int adjoint_bytes(int CP, int E, int W, int ROWS, bool gate) {
-  return adjoint_red_offset(CP, E, W, ROWS, gate) + CP * E * 4 * 6 * 4 + CP * 4 * 4 * 4;
+__host__ __device__ inline int adjoint_bytes(int CP, int E, int W, int ROWS, bool gate, int NW) {
+  return adjoint_red_offset(CP, E, W, ROWS, gate) + CP * E * NW * 6 * 4 + CP * NW * 4 * 4;
 }
 
-template <int K, int LZ, bool GATE, int DT>
-__global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_tiles) {
+template <int L, bool GATE, int DT>
+__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) void adjoint_kernel(Workspace ws,
+                                                                                                   int n_tiles) {
   extern __shared__ __align__(16) unsigned char lds[];
-  constexpr int LY = kThreads / (kLX * LZ);
-  constexpr int TX = kLX * K, TY = LY, TZ = LZ, ROWS = LY * LZ;
+  constexpr int K = kLayouts[L].K, LX = kLayouts[L].LX, LY = kLayouts[L].LY, LZ = kLayouts[L].LZ;
+  constexpr int NT = LX * LY * LZ, NW = NT / 64;
+  constexpr int TX = LX * K, TY = LY, TZ = LZ, ROWS = LY * LZ;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int lx = tid % kLX, ly = (tid / kLX) % LY, lz = tid / (kLX * LY);
+  const int lx = tid % LX, ly = (tid / LX) % LY, lz = tid / (LX * LY);
   const int row = ly + LY * lz;
   __shared__ int s_item;
 
@@ -70,13 +72,13 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_t
     const float fsf = (float)sw.fs;
     const float tpf = (float)(2.0 * 3.14159265358979323846 * sw.fc);
     const PingRange pr = ws.prange[t];
-    const LdsLayout L = lds_layout(CP, E, W, ROWS, GATE);
-    const TxRec* ltx = reinterpret_cast<const TxRec*>(lds + L.off_tx);
-    const RxRec* lrx = reinterpret_cast<const RxRec*>(lds + L.off_rx);
-    const int* lrows = reinterpret_cast<const int*>(lds + L.off_rows);
-    const float2* lwin = reinterpret_cast<const float2*>(lds + L.off_win);
+    const LdsLayout Ld = lds_layout(CP, E, W, ROWS, GATE);
+    const TxRec* ltx = reinterpret_cast<const TxRec*>(lds + Ld.off_tx);
+    const RxRec* lrx = reinterpret_cast<const RxRec*>(lds + Ld.off_rx);
+    const int* lrows = reinterpret_cast<const int*>(lds + Ld.off_rows);
+    const float4* lwin = reinterpret_cast<const float4*>(lds + Ld.off_win);
     float* red = reinterpret_cast<float*>(lds + adjoint_red_offset(CP, E, W, ROWS, GATE));
-    float* redt = red + CP * E * 4 * 6;
+    float* redt = red + CP * E * NW * 6;
 
     const float sx = (float)sw.d[0], sy = (float)sw.d[1], sz = (float)sw.d[2];
     float dx[K], dsq[K], gr[K], gi[K];
@@ -85,9 +87,9 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_t
     const int iy = y0 + ly, iz = z0 + lz;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      dx[k] = (float)(2 * (lx + kLX * k) - (TX - 1)) * 0.5f * sx;
+      dx[k] = (float)(2 * (lx + LX * k) - (TX - 1)) * 0.5f * sx;
       dsq[k] = dx[k] * dx[k] + dyl * dyl + dzl * dzl;
-      const int ix = x0 + lx + kLX * k;
+      const int ix = x0 + lx + LX * k;
       float2 g = make_float2(0.0f, 0.0f);
       if (ix < sw.nx && iy < sw.ny && iz < sw.nz) g = sw.gimage[((size_t)iz * sw.ny + iy) * (size_t)sw.nx + ix];
       gr[k] = g.x;
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_t
     for (int p0 = pr.lo; p0 <= pr.hi; p0 += CP) {
       const int cp = min(CP, pr.hi - p0 + 1);
       __syncthreads();
-      prepare_chunk<TX, LY, LZ, GATE, DT>(lds, ws, sw, c, C, p0, cp, x0, y0, z0, L, tid, lane, wave);
+      prepare_chunk<NT, TX, LY, LZ, GATE, DT>(lds, ws, sw, c, C, p0, cp, x0, y0, z0, Ld, tid, lane, wave);
       for (int slot = 0; slot < cp; ++slot) {
         const TxRec tr = ltx[slot];
         const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_t
         for (int e = 0; e < E; ++e) {
           const int r = slot * E + e;
           const RxRec rec = lrx[r];
-          const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(rec.flags));
+          const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(rec.q0.w));
           float S0 = 0.0f, Sx = 0.0f, C0 = 0.0f, C1 = 0.0f;
           if (!(f & kFlagSkip)) {
             const bool test = GATE && !(f & kFlagFull);
@@ -124,35 +126,36 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_t
               da = lx - a;
               span = b - a;
             }
-            const float ryz = fmaf(rec.uy2, dyl, rec.uz2 * dzl);
-            const float2* win = lwin + (size_t)r * (W + 2);
+            const float ryz = fmaf(rec.q0.y, dyl, rec.q0.z * dzl);
+            const float d0 = rec.q1.w;
+            const float d0sq = d0 * d0;
+            const float4* win = lwin + (size_t)r * (W + 1);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-              const float num = fmaf(rec.ux2, dx[k], ryz + dsq[k]);
-              const float sq = __builtin_amdgcn_sqrtf(rec.d0sq + num);
-              const float dR = num * __builtin_amdgcn_rcpf(rec.d0 + sq);
+              const float num = fmaf(rec.q0.x, dx[k], ryz + dsq[k]);
+              const float sq = __builtin_amdgcn_sqrtf(d0sq + num);
+              const float dR = num * __builtin_amdgcn_rcpf(d0 + sq);
               const float D = dT[k] + dR;
-              float sidx = fmaf(D, fs_c, rec.s0);
-              const float cyc = __builtin_amdgcn_fractf(fmaf(D, fc_c, rec.phi0));
+              float sidx = fmaf(D, fs_c, rec.q1.x);
+              const float cyc = fmaf(D, fc_c, rec.q1.y);
               if (test) {
-                const bool in = (unsigned)(da + kLX * k) <= (unsigned)span;
+                const bool in = (unsigned)(da + LX * k) <= (unsigned)span;
                 sidx = in ? sidx : szero;
               }
+              sidx = __builtin_amdgcn_fmed3f(sidx, 0.0f, szero);
+              const int n = (int)sidx;
+              const float w = __builtin_amdgcn_fractf(sidx);
               const float sn = __builtin_amdgcn_sinf(cyc);
               const float cs = __builtin_amdgcn_cosf(cyc);
-              int n = (int)sidx;
-              n = n < 0 ? 0 : (n > W ? W : n);
-              const float w = __builtin_amdgcn_fractf(sidx);
-              const float2 a = win[n];
-              const float2 b = win[n + 1];
-              const float dar = b.x - a.x, dai = b.y - a.y;
-              const float Lr = fmaf(w, dar, a.x), Li = fmaf(w, dai, a.y);
+              const float4 v = win[n];
+              const float dar = v.z, dai = v.w;
+              const float Lr = fmaf(w, dar, v.x), Li = fmaf(w, dai, v.y);
               const float Xr = fmaf(fsf, dar, -tpf * Li);
               const float Xi = fmaf(fsf, dai, tpf * Lr);
               const float Dr = fmaf(Xr, cs, -Xi * sn);
               const float Di = fmaf(Xr, sn, Xi * cs);
               const float coef = fmaf(gr[k], Dr, gi[k] * Di);
-              const float q = coef * __builtin_amdgcn_rcpf(rec.d0 + dR);
+              const float q = coef * __builtin_amdgcn_rcpf(d0 + dR);
               S0 += q;
               Sx = fmaf(q, dx[k], Sx);
               C0 += coef;
@@ -165,11 +168,11 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_t
             const float v0 = wave_sum(S0), v1 = wave_sum(Sx), v2 = wave_sum(Sy), v3 = wave_sum(Sz);
             const float v4 = wave_sum(C0), v5 = wave_sum(C1);
             if (lane == 0) {
-              float* o = red + ((size_t)r * 4 + wave) * 6;
+              float* o = red + ((size_t)r * NW + wave) * 6;
               o[0] = v0; o[1] = v1; o[2] = v2; o[3] = v3; o[4] = v4; o[5] = v5;
             }
           } else if (lane == 0) {
-            float* o = red + ((size_t)r * 4 + wave) * 6;
+            float* o = red + ((size_t)r * NW + wave) * 6;
             o[0] = o[1] = o[2] = o[3] = o[4] = o[5] = 0.0f;
           }
         }
@@ -183,18 +186,18 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_t
         }
         const float t0 = wave_sum(T0), t1 = wave_sum(Tx), t2 = wave_sum(T0 * dyl), t3 = wave_sum(T0 * dzl);
         if (lane == 0) {
-          float* o = redt + ((size_t)slot * 4 + wave) * 4;
+          float* o = redt + ((size_t)slot * NW + wave) * 4;
           o[0] = t0; o[1] = t1; o[2] = t2; o[3] = t3;
         }
       }
       __syncthreads();
       // FP64 partials of this chunk: fixed order over the four waves
-      for (int r = tid; r < cp * E; r += kThreads) {
+      for (int r = tid; r < cp * E; r += NT) {
         const int slot = r / E, e = r - slot * E;
         const int p = p0 + slot;
         double a[6] = {0, 0, 0, 0, 0, 0};
-        for (int w = 0; w < 4; ++w)
-          for (int j = 0; j < 6; ++j) a[j] += (double)red[((size_t)r * 4 + w) * 6 + j];
+        for (int w = 0; w < NW; ++w)
+          for (int j = 0; j < 6; ++j) a[j] += (double)red[((size_t)r * NW + w) * 6 + j];
         const double* T = sw.tx + (size_t)p * 3;
         const double* R = sw.rx + ((size_t)p * E + e) * 3;
         const double uR0 = C[0] - R[0], uR1 = C[1] - R[1], uR2 = C[2] - R[2];
@@ -209,8 +212,8 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(Workspace ws, int n_t
         out[3] = -(tau * a[4] + a[5] / c) / c;
         if (e == 0) {
           double b[4] = {0, 0, 0, 0};
-          for (int w = 0; w < 4; ++w)
-            for (int j = 0; j < 4; ++j) b[j] += (double)redt[((size_t)slot * 4 + w) * 4 + j];
+          for (int w = 0; w < NW; ++w)
+            for (int j = 0; j < 4; ++j) b[j] += (double)redt[((size_t)slot * NW + w) * 4 + j];
           out[4] = -(uT0 * b[0] + b[1]) / c;
           out[5] = -(uT1 * b[0] + b[2]) / c;
           out[6] = -(uT2 * b[0] + b[3]) / c;
@@ -368,47 +371,49 @@ __global__ __launch_bounds__(kThreads) void sharp_grad_kernel(const float2* img,
 
 typedef void (*AdjointKernelFn)(Workspace, int);
 
-template <int K, int LZ, bool G>
-static AdjointKernelFn adj_dt(int dt) {
+template <int L>
+static AdjointKernelFn adjoint_for_layout(bool gate, int dt) {
+  if (gate) {
+    switch (dt) {
+      case 0: return adjoint_kernel<L, true, 0>;
+      case 1: return adjoint_kernel<L, true, 1>;
+      default: return adjoint_kernel<L, true, 2>;
+    }
+  }
   switch (dt) {
-    case 0: return adjoint_kernel<K, LZ, G, 0>;
-    case 1: return adjoint_kernel<K, LZ, G, 1>;
-    default: return adjoint_kernel<K, LZ, G, 2>;
+    case 0: return adjoint_kernel<L, false, 0>;
+    case 1: return adjoint_kernel<L, false, 1>;
+    default: return adjoint_kernel<L, false, 2>;
   }
 }
-template <int K, int LZ>
-static AdjointKernelFn adj_gate(bool g, int dt) {
-  return g ? adj_dt<K, LZ, true>(dt) : adj_dt<K, LZ, false>(dt);
-}
-template <int K>
-static AdjointKernelFn adj_lz(int lz, bool g, int dt) {
-  switch (lz) {
-    case 1: return adj_gate<K, 1>(g, dt);
-    case 2: return adj_gate<K, 2>(g, dt);
-    case 4: return adj_gate<K, 4>(g, dt);
+
+AdjointKernelFn adjoint_kernel_for(int layout, bool gate, int dt) {
+  switch (layout) {
+    case 0: return adjoint_for_layout<0>(gate, dt);
+    case 1: return adjoint_for_layout<1>(gate, dt);
+    case 2: return adjoint_for_layout<2>(gate, dt);
+    case 3: return adjoint_for_layout<3>(gate, dt);
+    case 4: return adjoint_for_layout<4>(gate, dt);
+    case 5: return adjoint_for_layout<5>(gate, dt);
+    case 6: return adjoint_for_layout<6>(gate, dt);
+    case 7: return adjoint_for_layout<7>(gate, dt);
+    case 8: return adjoint_for_layout<8>(gate, dt);
     default: return nullptr;
   }
 }
 
-AdjointKernelFn adjoint_kernel_for(int K, int LZ, bool gate, int dt) {
-  switch (K) {
-    case 2: return adj_lz<2>(LZ, gate, dt);
-    case 4: return adj_lz<4>(LZ, gate, dt);
-    case 8: return adj_lz<8>(LZ, gate, dt);
-    default: return nullptr;
-  }
+int adjoint_lds_bytes(int CP, int E, int W, int ROWS, bool gate, int threads) {
+  return adjoint_bytes(CP, E, W, ROWS, gate, threads / 64);
 }
 
-int adjoint_lds_bytes(int CP, int E, int W, int ROWS, bool gate) { return adjoint_bytes(CP, E, W, ROWS, gate); }
-
-hipError_t launch_adjoint(AdjointKernelFn fn, const Workspace& ws, int n_tiles, int grid, int lds_bytes,
+hipError_t launch_adjoint(AdjointKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads, int lds_bytes,
                           hipStream_t st) {
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds_bytes, st, ws, n_tiles);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds_bytes, st, ws, n_tiles);
   return hipGetLastError();
 }
 
-hipError_t adjoint_occupancy(AdjointKernelFn fn, int lds_bytes, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds_bytes);
+hipError_t adjoint_occupancy(AdjointKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, threads, lds_bytes);
 }
 
 hipError_t set_adjoint_lds_limit(AdjointKernelFn fn, int lds_bytes) {

@@ -6,11 +6,25 @@
 
 namespace sasbp {
 
-// Threads per workgroup of the image and adjoint kernels: lanes are laid out
-// as LX (x) by LY (y) by LZ (z) with LX * LY * LZ == kThreads, and every lane
-// owns K pixels spaced LX apart along x. A tile is (LX*K) x LY x LZ pixels.
-constexpr int kThreads = 256;
-constexpr int kLX = 8;
+// Lane layouts of the image and adjoint kernels: a workgroup of
+// LX * LY * LZ threads (256 or 512) owns a tile of (LX * K) x LY x LZ pixels;
+// lane (lx, ly, lz) owns the K pixels lx + LX k of row (ly, lz).
+struct LaneLayout {
+  int K, LX, LY, LZ;
+};
+constexpr LaneLayout kLayouts[] = {
+    {2, 8, 32, 1},   // 0: 16 x 32,     256 threads
+    {4, 8, 32, 1},   // 1: 32 x 32,     256
+    {8, 8, 32, 1},   // 2: 64 x 32,     256
+    {4, 16, 32, 1},  // 3: 64 x 32,     512
+    {8, 16, 32, 1},  // 4: 128 x 32,    512
+    {4, 8, 64, 1},   // 5: 32 x 64,     512
+    {4, 8, 8, 4},    // 6: 32 x 8 x 4,  256
+    {4, 8, 16, 4},   // 7: 32 x 16 x 4, 512
+    {8, 8, 8, 4},    // 8: 64 x 8 x 4,  256
+};
+constexpr int kNumLayouts = sizeof(kLayouts) / sizeof(kLayouts[0]);
+constexpr int kThreads = 256;    // helper kernels (cull, order, count, sharpness)
 constexpr int kMaxElem = 256;
 
 // Per-swath constants and pointers, stored in the plan's workspace so that a

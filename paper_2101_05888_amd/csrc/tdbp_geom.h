@@ -1,37 +1,45 @@
 // Device-side pieces shared by the image and adjoint kernels: the FP64
-// reference geometry of a (tile, ping, element), the exact per-row beam-gate
-// intervals, and the staging of echo windows into LDS.
+// reference geometry of a (tile, ping, element), the beam-gate classification
+// and exact per-row gate intervals, and the staging of echo windows into LDS.
 //
 // Delay model (Eq. 1, Sec. II-A): tau = (|p - T| + |p - R|) / c. Inside a tile
 // with centre C, a pixel is p = C + delta. With u = C - X for an apex X (the
-// transmitter or a receiver) and d0 = |u|,
-//     |p - X| - d0 = num / (d0 + sqrt(d0^2 + num)),   num = 2 u.delta + |delta|^2,
-// which has no cancellation, so the offset is accurate in FP32 while C, d0,
-// the reference delay and its carrier phase are formed in FP64. Absolute
+// transmitter or a receiver), d0 = |u| and num = 2 u.delta + |delta|^2,
+//     |p - X| - d0 = sqrt(d0^2 + num) - d0 = num / (d0 + sqrt(d0^2 + num)),
+// a form without cancellation, so the offset is accurate in FP32 while C, d0,
+// the reference delay and its carrier phase are formed in FP64 (absolute
 // ranges of tens of metres against a 1.5 cm wavelength would lose the phase in
-// FP32.
+// FP32). For the receiver leg, evaluated once per (pixel, ping, element), the
+// offset is the Taylor series of d0 (sqrt(1 + y) - 1), y = num / d0^2, in
+// powers of num through num^5 whenever an FP64 bound on the truncation error
+// over the whole tile is below 1e-8 m (0.004 mrad of two-way phase at 1.5 cm);
+// otherwise the exact form above is used. The choice is per
+// (tile, ping, element) and uniform across the workgroup.
 #pragma once
 
 #include "tdbp_dev.h"
 
 namespace sasbp {
 
-// One receiver record per (ping, element), 8 floats = 32 bytes:
-//   [0..2] 2 u_R (x, y, z)   [3] d0_R   [4] d0_R^2
-//   [5] s0: reference delay in samples relative to the window start
-//   [6] phi0: frac(f_c * tau_ref), cycles
-//   [7] flags (bit pattern): 1 = no pixel of the tile is gated in, 2 = every pixel is
+// Receiver record per (ping, element), 12 floats = three 16-byte LDS reads:
+//   q0: 2 u_R (x, y, z), flags
+//   q1: s0 = reference delay in samples from the window start,
+//       phi0 = frac(f_c tau_ref) in cycles, a5, d0_R
+//   q2: a1..a4
+// with Delta_R ~= num (a1 + num (a2 + num (a3 + num (a4 + num a5)))).
 struct RxRec {
-  float ux2, uy2, uz2, d0, d0sq, s0, phi0, flags;
+  float4 q0, q1, q2;
 };
-// One transmitter record per ping.
+// Transmitter record per ping: 2 u_T (x, y, z), d0_T, d0_T^2.
 struct TxRec {
   float ux2, uy2, uz2, d0, d0sq, pad0, pad1, pad2;
 };
 
-constexpr unsigned kFlagSkip = 1u;
-constexpr unsigned kFlagFull = 2u;
-constexpr int kEmptyRow = 30000;   // encodes an empty gate interval (never matches a local x)
+constexpr unsigned kFlagSkip = 1u;   // no pixel of the tile is gated in (or bad navigation)
+constexpr unsigned kFlagFull = 2u;   // every pixel of the tile is gated in
+constexpr unsigned kFlagPoly = 4u;   // receiver offset by the degree-5 series
+constexpr int kEmptyRow = 30000;     // encodes an empty gate interval (never matches a local x)
+constexpr double kPolyTol = 1e-8;    // metres, bound on the series truncation error
 
 __device__ __forceinline__ double tile_centre(const SwathDev& sw, int a, int first, int extent) {
   return sw.o[a] + ((double)first + 0.5 * (double)(extent - 1)) * sw.d[a];
@@ -41,8 +49,33 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
-// Receiver record and window start for (ping p, element e) of the tile centred at C.
-// Returns false if the navigation is not finite.
+// Beam-gate class of the tile box for one cone apex X (Sec. II-C, with the
+// transmitter and the receiver tested separately as in Sec. III-B). The cone
+// |x - X_x| <= tan(g) rho, rho the (y, z) distance to X; over an axis-aligned
+// box |x - X_x| and rho vary independently, so
+//   out: min |dx| > tan(g) max rho,   in: max |dx| <= tan(g) min rho.
+// Margins keep "in" and "out" strictly away from the cone surface; anything
+// closer is "partial" and decided per row.
+enum { kGateOut = 0, kGateIn = 1, kGatePartial = 2 };
+
+__device__ __forceinline__ int gate_class(double tan2, double x, double y, double z, double bx0, double bx1,
+                                          double by0, double by1, double bz0, double bz1) {
+  // squared form: out iff dxmin^2 > tan^2 rmax^2, in iff dxmax^2 <= tan^2 rmin^2
+  const double dxmin = fmax(0.0, fmax(bx0 - x, x - bx1));
+  const double dxmax = fmax(fabs(bx0 - x), fabs(bx1 - x));
+  const double dymin = fmax(0.0, fmax(by0 - y, y - by1));
+  const double dymax = fmax(fabs(by0 - y), fabs(by1 - y));
+  const double dzmin = fmax(0.0, fmax(bz0 - z, z - bz1));
+  const double dzmax = fmax(fabs(bz0 - z), fabs(bz1 - z));
+  const double r2min = dymin * dymin + dzmin * dzmin;
+  const double r2max = dymax * dymax + dzmax * dzmax;
+  if (dxmin * dxmin > tan2 * r2max * (1.0 + 1e-11) + 1e-18) return kGateOut;
+  if (dxmax * dxmax <= tan2 * r2min * (1.0 - 1e-11) - 1e-18) return kGateIn;
+  return kGatePartial;
+}
+
+// Receiver record and window start for (ping p, element e) of the tile centred
+// at C. Returns false if the navigation is not finite (record marked skip).
 __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double c, const double C[3], int p, int e,
                                                RxRec* rec, int* n0_out) {
   const double* T = sw.tx + (size_t)p * 3;
@@ -62,14 +95,25 @@ __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double c, con
   if (nstart > 1.0e9) nstart = 1.0e9;
   const int n0 = (int)nstart;
   const double cyc = sw.fc * tau;
-  rec->ux2 = (float)(2.0 * uR0);
-  rec->uy2 = (float)(2.0 * uR1);
-  rec->uz2 = (float)(2.0 * uR2);
-  rec->d0 = (float)d0R;
-  rec->d0sq = (float)(d0R * d0R);
-  rec->s0 = (float)(uref - (double)n0);
-  rec->phi0 = (float)(cyc - floor(cyc));
-  rec->flags = __uint_as_float(ok ? 0u : kFlagSkip);
+  unsigned flags = ok ? 0u : kFlagSkip;
+  // series bound over the tile: |num| <= 2 d0 r + r^2, remainder of
+  // sqrt(1+y) - 1 after y^5 at most (21/1024) |y|^6 / (1 - |y|)
+  const double r = sw.half_diag;
+  const double y = (2.0 * d0R * r + r * r) / (d0R * d0R);
+  double a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0;
+  const double y3 = y * y * y;
+  if (ok && y < 0.5 && d0R * (21.0 / 1024.0) * (y3 * y3) <= kPolyTol * (1.0 - y)) {
+    flags |= kFlagPoly;
+    const double i1 = 1.0 / d0R, i2 = i1 * i1;
+    a1 = 0.5 * i1;
+    a2 = -0.125 * i1 * i2;
+    a3 = 0.0625 * i1 * i2 * i2;
+    a4 = -(5.0 / 128.0) * i1 * i2 * i2 * i2;
+    a5 = (7.0 / 256.0) * i1 * i2 * i2 * i2 * i2;
+  }
+  rec->q0 = make_float4((float)(2.0 * uR0), (float)(2.0 * uR1), (float)(2.0 * uR2), __uint_as_float(flags));
+  rec->q1 = make_float4((float)(uref - (double)n0), (float)(cyc - floor(cyc)), (float)a5, (float)d0R);
+  rec->q2 = make_float4((float)a1, (float)a2, (float)a3, (float)a4);
   *n0_out = n0;
   return ok;
 }
@@ -125,8 +169,10 @@ __device__ __forceinline__ float2 load_sample(const void* base, size_t idx, int 
 }
 
 // LDS layout for a chunk of CP pings with E elements and window length W:
-//   TxRec  tx[CP]            RxRec rx[CP][E]          int n0[CP][E]
-//   int    rows[CP][E][ROWS] (gate only)              float2 win[CP][E][W+2]
+//   TxRec tx[CP]   RxRec rx[CP][E]   int n0[CP][E]   int rows[CP][E][ROWS] (gate only)
+//   float4 win[CP][E][W+1]: {E[n], E[n+1] - E[n]} for n < W, entry W all zero
+// (interpolation is then one 16-byte read and two FMAs; gated-out pixels read
+// the zero entry).
 struct LdsLayout {
   int off_tx, off_rx, off_n0, off_rows, off_win, bytes;
 };
@@ -139,16 +185,49 @@ __host__ __device__ inline LdsLayout lds_layout(int CP, int E, int W, int ROWS, 
   L.off_n0 = o;   o += CP * E * 4;
   L.off_rows = o; o += gate ? CP * E * ROWS * 4 : 0;
   o = (o + 15) & ~15;
-  L.off_win = o;  o += CP * E * (W + 2) * 8;
+  L.off_win = o;  o += CP * E * (W + 1) * 16;
   L.bytes = o;
   return L;
 }
 
+// FP64 receiver records and gate classes of one chunk (threads stride over
+// the (ping, element) pairs).
+template <int NT>
+__device__ __forceinline__ void build_records(RxRec* lrx, int* ln0, const Workspace& ws, const SwathDev& sw,
+                                                        double c, const double* C, int p0, int cp, int tid,
+                                                        bool gate_on, double bx0, double bx1, double by0,
+                                                        double by1, double bz0, double bz1) {
+  const int E = sw.E;
+  const double tan2 = sw.tan_g * sw.tan_g;
+#pragma unroll 1
+  for (int r = tid; r < cp * E; r += NT) {
+    const int slot = r / E, e = r - slot * E;
+    const int p = p0 + slot;
+    RxRec rec;
+    int n0;
+    if (!make_rx_record(sw, c, C, p, e, &rec, &n0)) atomicOr(&ws.counters[1], kStatusNav);
+    unsigned f = __float_as_uint(rec.q0.w);
+    if (!gate_on) {
+      f |= kFlagFull;
+    } else {
+      const double* T = sw.tx + (size_t)p * 3;
+      const double* R = sw.rx + ((size_t)p * E + e) * 3;
+      const int gt = gate_class(tan2, T[0], T[1], T[2], bx0, bx1, by0, by1, bz0, bz1);
+      const int gr = gt == kGateOut ? kGateOut : gate_class(tan2, R[0], R[1], R[2], bx0, bx1, by0, by1, bz0, bz1);
+      if (gt == kGateOut || gr == kGateOut) f |= kFlagSkip;
+      else if (gt == kGateIn && gr == kGateIn) f |= kFlagFull;
+    }
+    rec.q0.w = __uint_as_float(f);
+    lrx[r] = rec;
+    ln0[r] = n0;
+  }
+}
+
 // Steps 1-2 of a chunk of pings, shared by the image and adjoint kernels:
-// FP64 reference records, exact gate rows and (ping, element) flags, then the
-// echo windows in LDS. Ends with a barrier; the caller must have passed a
-// barrier since the previous chunk's last read of LDS.
-template <int TX, int LY, int LZ, bool GATE, int DT>
+// FP64 records, gate classes and exact rows of partial records, then the echo
+// windows in LDS. Ends with a barrier; the caller must have passed a barrier
+// since the previous chunk's last read of LDS.
+template <int NT, int TX, int LY, int LZ, bool GATE, int DT>
 __device__ __forceinline__ void prepare_chunk(unsigned char* lds, const Workspace& ws, const SwathDev& sw, double c,
                                               const double C[3], int p0, int cp, int x0, int y0, int z0,
                                               const LdsLayout& L, int tid, int lane, int wave) {
@@ -158,22 +237,24 @@ __device__ __forceinline__ void prepare_chunk(unsigned char* lds, const Workspac
   RxRec* lrx = reinterpret_cast<RxRec*>(lds + L.off_rx);
   int* ln0 = reinterpret_cast<int*>(lds + L.off_n0);
   int* lrows = reinterpret_cast<int*>(lds + L.off_rows);
-  float2* lwin = reinterpret_cast<float2*>(lds + L.off_win);
-  // 1. FP64 reference geometry
-  for (int r = tid; r < cp * E; r += kThreads) {
-    const int slot = r / E, e = r - slot * E;
-    RxRec rec;
-    int n0;
-    if (!make_rx_record(sw, c, C, p0 + slot, e, &rec, &n0)) atomicOr(&ws.counters[1], kStatusNav);
-    lrx[r] = rec;
-    ln0[r] = n0;
-  }
-  for (int r = tid; r < cp; r += kThreads) make_tx_record(sw, C, p0 + r, &ltx[r]);
-  // a swath without a gate inside a plan whose kernel gates: every pixel is in
+  float4* lwin = reinterpret_cast<float4*>(lds + L.off_win);
   const bool gate_on = GATE && sw.tan_g > 0.0;
+  // pixel-centre box of the tile (uniform)
+  const double bx0 = sw.o[0] + (double)x0 * sw.d[0], bx1 = bx0 + (double)(TX - 1) * sw.d[0];
+  const double by0 = sw.o[1] + (double)y0 * sw.d[1], by1 = by0 + (double)(LY - 1) * sw.d[1];
+  const double bz0 = sw.o[2] + (double)z0 * sw.d[2], bz1 = bz0 + (double)(LZ - 1) * sw.d[2];
+  // 1. FP64 records and gate classes
+  build_records<NT>(lrx, ln0, ws, sw, c, C, p0, cp, tid, gate_on, bx0, bx1, by0, by1, bz0, bz1);
+#pragma unroll 1
+  for (int r = tid; r < cp; r += NT) make_tx_record(sw, C, p0 + r, &ltx[r]);
+  __syncthreads();
   if (gate_on) {
-    for (int q = tid; q < cp * E * ROWS; q += kThreads) {
+    // exact rows of the partial records
+#pragma unroll 1
+    for (int q = tid; q < cp * E * ROWS; q += NT) {
       const int pe = q / ROWS, rr = q - pe * ROWS;
+      const unsigned f = __float_as_uint(lrx[pe].q0.w);
+      if (f & (kFlagSkip | kFlagFull)) continue;
       const int slot = pe / E, e = pe - slot * E;
       const int ry = rr % LY, rz = rr / LY;
       const double y = sw.o[1] + (double)(y0 + ry) * sw.d[1];
@@ -181,46 +262,37 @@ __device__ __forceinline__ void prepare_chunk(unsigned char* lds, const Workspac
       lrows[q] = gate_row(sw, p0 + slot, e, y, z, x0, TX);
     }
   }
-  __syncthreads();
-  if (GATE && !gate_on) {
-    for (int r = tid; r < cp * E; r += kThreads)
-      lrx[r].flags = __uint_as_float(__float_as_uint(lrx[r].flags) | kFlagFull);
-    __syncthreads();
-  }
-  if (gate_on) {
-    // (ping, element) flags from the row intervals: skip / full tile
-    for (int r = tid; r < cp * E; r += kThreads) {
-      bool any = false, all = true;
-      for (int rr = 0; rr < ROWS; ++rr) {
-        const int v = lrows[r * ROWS + rr];
-        const int a = row_lo(v), b = row_hi(v);
-        const bool nonempty = a <= b;
-        any |= nonempty;
-        all &= nonempty && a == 0 && b == TX - 1;
-      }
-      unsigned f = __float_as_uint(lrx[r].flags);
-      if (!any) f |= kFlagSkip;
-      if (all) f |= kFlagFull;
-      lrx[r].flags = __uint_as_float(f);
-    }
-    __syncthreads();
-  }
-  // 2. echo windows -> LDS
-  for (int r = wave; r < cp * E; r += kThreads / 64) {
-    const unsigned f = __float_as_uint(lrx[r].flags);
+  // 2. echo windows -> LDS: entry k holds E[n0+k] and E[n0+k+1] - E[n0+k]
+#pragma unroll 1
+  for (int r = wave; r < cp * E; r += NT / 64) {
+    const unsigned f = __float_as_uint(lrx[r].q0.w);
     if (f & kFlagSkip) continue;
     const int slot = r / E, e = r - slot * E;
     const int p = p0 + slot;
     const int n0 = ln0[r];
     const size_t rowbase = ((size_t)p * E + e) * (size_t)sw.Ns;
     const float scale = DT == 0 ? 1.0f : sw.scale[p];
-    float2* dst = lwin + (size_t)r * (W + 2);
-    for (int k = lane; k < W + 2; k += 64) {
-      const int n = n0 + k;
-      float2 v = make_float2(0.0f, 0.0f);
-      if (k < W && n >= 0 && n < sw.Ns) v = load_sample(sw.echo, rowbase + (size_t)n, DT, scale);
-      dst[k] = v;
+    float4* dst = lwin + (size_t)r * (W + 1);
+    if (n0 >= 0 && n0 + W < sw.Ns) {
+      // whole window inside the record: no per-sample checks
+      const size_t base = rowbase + (size_t)n0;
+#pragma unroll 2
+      for (int k = lane; k < W; k += 64) {
+        const float2 a = load_sample(sw.echo, base + k, DT, scale);
+        const float2 b = load_sample(sw.echo, base + k + 1, DT, scale);
+        dst[k] = make_float4(a.x, a.y, b.x - a.x, b.y - a.y);
+      }
+    } else {
+#pragma unroll 1
+      for (int k = lane; k < W; k += 64) {
+        const int n = n0 + k;
+        float2 a = make_float2(0.0f, 0.0f), b = make_float2(0.0f, 0.0f);
+        if (n >= 0 && n < sw.Ns) a = load_sample(sw.echo, rowbase + (size_t)n, DT, scale);
+        if (n + 1 >= 0 && n + 1 < sw.Ns) b = load_sample(sw.echo, rowbase + (size_t)n + 1, DT, scale);
+        dst[k] = make_float4(a.x, a.y, b.x - a.x, b.y - a.y);
+      }
     }
+    if (lane == 0) dst[W] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
   __syncthreads();
 }

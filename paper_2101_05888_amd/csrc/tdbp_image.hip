@@ -123,14 +123,74 @@ __global__ __launch_bounds__(kThreads) void order_kernel(Workspace ws, int n_til
   }
 }
 
-template <int K, int LZ, bool GATE, int DT>
-__global__ __launch_bounds__(kThreads) void image_kernel(Workspace ws, int n_tiles) {
+// One (ping, element) record applied to the K pixels of a lane. POLY selects
+// the series form of the receiver-leg offset, TEST the per-pixel gate test of
+// a partially gated record; both are uniform over the workgroup.
+template <int K, int LX, bool POLY, bool TEST>
+__device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __restrict__ win, const float* dx,
+                                           const float* dsq, const float* dT, float dyl, float dzl, float fs_c,
+                                           float fc_c, float szero, int da, int span, float* accr, float* acci) {
+  const float ryz = fmaf(rec.q0.y, dyl, rec.q0.z * dzl);
+  const float d0 = rec.q1.w;
+  const float d0sq = d0 * d0;
+  // phase 1: delays, sample positions and carrier phases of the K pixels
+  float sidx[K], cyc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float num = fmaf(rec.q0.x, dx[k], ryz + dsq[k]);
+    float D;   // two-way path offset from the (tile, ping, element) reference, metres
+    if (POLY) {
+      float h = fmaf(rec.q1.z, num, rec.q2.w);
+      h = fmaf(h, num, rec.q2.z);
+      h = fmaf(h, num, rec.q2.y);
+      h = fmaf(h, num, rec.q2.x);
+      D = fmaf(h, num, dT[k]);
+    } else {
+      const float sq = __builtin_amdgcn_sqrtf(d0sq + num);
+      D = fmaf(num, __builtin_amdgcn_rcpf(d0 + sq), dT[k]);
+    }
+    float si = fmaf(D, fs_c, rec.q1.x);
+    cyc[k] = fmaf(D, fc_c, rec.q1.y);   // the hardware sin/cos take revolutions
+    if (TEST) {
+      const bool in = (unsigned)(da + LX * k) <= (unsigned)span;
+      si = in ? si : szero;
+    }
+    sidx[k] = __builtin_amdgcn_fmed3f(si, 0.0f, szero);
+  }
+  // phase 2: every window read in flight at once
+  float4 v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = win[(int)sidx[k]];
+  // phase 3: carrier phasors while the reads land
+  float sn[K], cs[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    sn[k] = __builtin_amdgcn_sinf(cyc[k]);
+    cs[k] = __builtin_amdgcn_cosf(cyc[k]);
+  }
+  // phase 4: interpolate and accumulate
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float w = __builtin_amdgcn_fractf(sidx[k]);
+    const float vr = fmaf(w, v[k].z, v[k].x);
+    const float vi = fmaf(w, v[k].w, v[k].y);
+    accr[k] = fmaf(vr, cs[k], accr[k]);
+    accr[k] = fmaf(-vi, sn[k], accr[k]);
+    acci[k] = fmaf(vr, sn[k], acci[k]);
+    acci[k] = fmaf(vi, cs[k], acci[k]);
+  }
+}
+
+template <int L, bool GATE, int DT>
+__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) void image_kernel(Workspace ws,
+                                                                                                 int n_tiles) {
   extern __shared__ __align__(16) unsigned char lds[];
-  constexpr int LY = kThreads / (kLX * LZ);
-  constexpr int TX = kLX * K, TY = LY, TZ = LZ, ROWS = LY * LZ;
+  constexpr int K = kLayouts[L].K, LX = kLayouts[L].LX, LY = kLayouts[L].LY, LZ = kLayouts[L].LZ;
+  constexpr int NT = LX * LY * LZ;
+  constexpr int TX = LX * K, TY = LY, TZ = LZ, ROWS = LY * LZ;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int lx = tid % kLX, ly = (tid / kLX) % LY, lz = tid / (kLX * LY);
+  const int lx = tid % LX, ly = (tid / LX) % LY, lz = tid / (LX * LY);
   const int row = ly + LY * lz;
   __shared__ int s_item;
 
@@ -155,12 +215,11 @@ __global__ __launch_bounds__(kThreads) void image_kernel(Workspace ws, int n_til
     const float fs_c = (float)(sw.fs / c);
     const float fc_c = (float)(sw.fc / c);
     const PingRange pr = ws.prange[t];
-    const LdsLayout L = lds_layout(CP, E, W, ROWS, GATE);
-    TxRec* ltx = reinterpret_cast<TxRec*>(lds + L.off_tx);
-    RxRec* lrx = reinterpret_cast<RxRec*>(lds + L.off_rx);
-    int* ln0 = reinterpret_cast<int*>(lds + L.off_n0);
-    int* lrows = reinterpret_cast<int*>(lds + L.off_rows);
-    float2* lwin = reinterpret_cast<float2*>(lds + L.off_win);
+    const LdsLayout Ld = lds_layout(CP, E, W, ROWS, GATE);
+    const TxRec* ltx = reinterpret_cast<const TxRec*>(lds + Ld.off_tx);
+    const RxRec* lrx = reinterpret_cast<const RxRec*>(lds + Ld.off_rx);
+    const int* lrows = reinterpret_cast<const int*>(lds + Ld.off_rows);
+    const float4* lwin = reinterpret_cast<const float4*>(lds + Ld.off_win);
 
     // per-lane pixel offsets from the tile centre (exact multiples of the spacing)
     const float sx = (float)sw.d[0], sy = (float)sw.d[1], sz = (float)sw.d[2];
@@ -169,19 +228,18 @@ __global__ __launch_bounds__(kThreads) void image_kernel(Workspace ws, int n_til
     const float dzl = (float)(2 * lz - (TZ - 1)) * 0.5f * sz;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      dx[k] = (float)(2 * (lx + kLX * k) - (TX - 1)) * 0.5f * sx;
+      dx[k] = (float)(2 * (lx + LX * k) - (TX - 1)) * 0.5f * sx;
       dsq[k] = dx[k] * dx[k] + dyl * dyl + dzl * dzl;
     }
     float accr[K], acci[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) { accr[k] = 0.0f; acci[k] = 0.0f; }
-    const float szero = (float)W;   // window guard: two zero samples at [W, W+1]
+    const float szero = (float)W;   // the window's all-zero entry
 
     for (int p0 = pr.lo; p0 <= pr.hi; p0 += CP) {
       const int cp = min(CP, pr.hi - p0 + 1);
       __syncthreads();
-      prepare_chunk<TX, LY, LZ, GATE, DT>(lds, ws, sw, c, C, p0, cp, x0, y0, z0, L, tid, lane, wave);
-      // 3. accumulate
+      prepare_chunk<NT, TX, LY, LZ, GATE, DT>(lds, ws, sw, c, C, p0, cp, x0, y0, z0, Ld, tid, lane, wave);
       for (int slot = 0; slot < cp; ++slot) {
         const TxRec tr = ltx[slot];
         const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
@@ -194,44 +252,24 @@ __global__ __launch_bounds__(kThreads) void image_kernel(Workspace ws, int n_til
         }
         for (int e = 0; e < E; ++e) {
           const int r = slot * E + e;
-          const RxRec rec = lrx[r];
-          const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(rec.flags));
+          const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(lrx[r].q0.w));
           if (f & kFlagSkip) continue;
-          const bool test = GATE && !(f & kFlagFull);
-          int da = 0, span = 0;
-          if (test) {
+          const RxRec rec = lrx[r];
+          const float4* win = lwin + (size_t)r * (W + 1);
+          if (!GATE || (f & kFlagFull)) {
+            if (f & kFlagPoly)
+              accumulate<K, LX, true, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
+            else
+              accumulate<K, LX, false, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
+          } else {
             const int v = lrows[r * ROWS + row];
             const int a = row_lo(v), b = row_hi(v);
-            da = lx - a;
-            span = b - a;
-          }
-          const float ryz = fmaf(rec.uy2, dyl, rec.uz2 * dzl);
-          const float2* win = lwin + (size_t)r * (W + 2);
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const float num = fmaf(rec.ux2, dx[k], ryz + dsq[k]);
-            const float sq = __builtin_amdgcn_sqrtf(rec.d0sq + num);
-            const float dR = num * __builtin_amdgcn_rcpf(rec.d0 + sq);
-            const float D = dT[k] + dR;
-            float sidx = fmaf(D, fs_c, rec.s0);
-            const float cyc = __builtin_amdgcn_fractf(fmaf(D, fc_c, rec.phi0));
-            if (test) {
-              const bool in = (unsigned)(da + kLX * k) <= (unsigned)span;
-              sidx = in ? sidx : szero;
-            }
-            const float sn = __builtin_amdgcn_sinf(cyc);
-            const float cs = __builtin_amdgcn_cosf(cyc);
-            int n = (int)sidx;
-            n = n < 0 ? 0 : (n > W ? W : n);
-            const float w = __builtin_amdgcn_fractf(sidx);
-            const float2 a = win[n];
-            const float2 b = win[n + 1];
-            const float vr = fmaf(w, b.x - a.x, a.x);
-            const float vi = fmaf(w, b.y - a.y, a.y);
-            accr[k] = fmaf(vr, cs, accr[k]);
-            accr[k] = fmaf(-vi, sn, accr[k]);
-            acci[k] = fmaf(vr, sn, acci[k]);
-            acci[k] = fmaf(vi, cs, acci[k]);
+            if (f & kFlagPoly)
+              accumulate<K, LX, true, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a,
+                                            accr, acci);
+            else
+              accumulate<K, LX, false, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a,
+                                             accr, acci);
           }
         }
       }
@@ -242,7 +280,7 @@ __global__ __launch_bounds__(kThreads) void image_kernel(Workspace ws, int n_til
       float2* out = sw.image + ((size_t)iz * sw.ny + iy) * (size_t)sw.nx;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int ix = x0 + lx + kLX * k;
+        const int ix = x0 + lx + LX * k;
         if (ix < sw.nx) out[ix] = make_float2(accr[k], acci[k]);
       }
     }
@@ -253,35 +291,33 @@ __global__ __launch_bounds__(kThreads) void image_kernel(Workspace ws, int n_til
 
 typedef void (*ImageKernelFn)(Workspace, int);
 
-template <int K, int LZ, bool G>
-static ImageKernelFn pick_dt(int dt) {
+template <int L>
+static ImageKernelFn image_for_layout(bool gate, int dt) {
+  if (gate) {
+    switch (dt) {
+      case 0: return image_kernel<L, true, 0>;
+      case 1: return image_kernel<L, true, 1>;
+      default: return image_kernel<L, true, 2>;
+    }
+  }
   switch (dt) {
-    case 0: return image_kernel<K, LZ, G, 0>;
-    case 1: return image_kernel<K, LZ, G, 1>;
-    default: return image_kernel<K, LZ, G, 2>;
+    case 0: return image_kernel<L, false, 0>;
+    case 1: return image_kernel<L, false, 1>;
+    default: return image_kernel<L, false, 2>;
   }
 }
 
-template <int K, int LZ>
-static ImageKernelFn pick_gate(bool gate, int dt) {
-  return gate ? pick_dt<K, LZ, true>(dt) : pick_dt<K, LZ, false>(dt);
-}
-
-template <int K>
-static ImageKernelFn pick_lz(int lz, bool gate, int dt) {
-  switch (lz) {
-    case 1: return pick_gate<K, 1>(gate, dt);
-    case 2: return pick_gate<K, 2>(gate, dt);
-    case 4: return pick_gate<K, 4>(gate, dt);
-    default: return nullptr;
-  }
-}
-
-ImageKernelFn image_kernel_for(int K, int LZ, bool gate, int dt) {
-  switch (K) {
-    case 2: return pick_lz<2>(LZ, gate, dt);
-    case 4: return pick_lz<4>(LZ, gate, dt);
-    case 8: return pick_lz<8>(LZ, gate, dt);
+ImageKernelFn image_kernel_for(int layout, bool gate, int dt) {
+  switch (layout) {
+    case 0: return image_for_layout<0>(gate, dt);
+    case 1: return image_for_layout<1>(gate, dt);
+    case 2: return image_for_layout<2>(gate, dt);
+    case 3: return image_for_layout<3>(gate, dt);
+    case 4: return image_for_layout<4>(gate, dt);
+    case 5: return image_for_layout<5>(gate, dt);
+    case 6: return image_for_layout<6>(gate, dt);
+    case 7: return image_for_layout<7>(gate, dt);
+    case 8: return image_for_layout<8>(gate, dt);
     default: return nullptr;
   }
 }
@@ -306,14 +342,14 @@ hipError_t launch_order(const Workspace& ws, int n_tiles, int bucket_shift, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int grid, int lds_bytes,
+hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads, int lds_bytes,
                         hipStream_t st) {
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), lds_bytes, st, ws, n_tiles);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds_bytes, st, ws, n_tiles);
   return hipGetLastError();
 }
 
-hipError_t image_occupancy(ImageKernelFn fn, int lds_bytes, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds_bytes);
+hipError_t image_occupancy(ImageKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, threads, lds_bytes);
 }
 
 hipError_t set_image_lds_limit(ImageKernelFn fn, int lds_bytes) {
