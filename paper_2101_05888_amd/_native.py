@@ -1,8 +1,8 @@
 """ctypes view of ``include/sas_bp.h``: structures and the exported functions.
 
 The library is loaded from this package directory (built in-tree by
-``paper_2101_05888_amd.build``). There is no fallback: importing this module
-without the library raises ``ImportError``.
+``paper_2101_05888_amd.build``) on first use. There is no fallback: any call
+into the library when it has not been built raises ``ImportError``.
 """
 from __future__ import annotations
 
@@ -75,14 +75,22 @@ def _load():
     return lib
 
 
-lib = _load()
+_LIB = None
+
+
+def lib():
+    """The loaded HIP library (loaded on first call)."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
 
 
 class SasBpError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        msg = lib.sas_bp_error_string(status).decode()
-        detail = lib.sas_bp_last_error_detail().decode()
+        msg = lib().sas_bp_error_string(status).decode()
+        detail = lib().sas_bp_last_error_detail().decode()
         super().__init__(f"{where}: {msg} ({detail})" if detail else f"{where}: {msg}")
 
 

@@ -57,16 +57,16 @@ class Plan:
 
     def info(self) -> dict:
         arr = (C.c_int64 * 8)()
-        check(N.lib.sas_bp_plan_info(self.handle, arr), "sas_bp_plan_info")
+        check(N.lib().sas_bp_plan_info(self.handle, arr), "sas_bp_plan_info")
         keys = ("tile_x", "tile_y", "tile_z", "pings_per_chunk", "window", "lds_bytes", "grid", "threads")
         return dict(zip(keys, (int(v) for v in arr)))
 
     def status(self) -> int:
-        return int(N.lib.sas_bp_plan_status(self.handle))
+        return int(N.lib().sas_bp_plan_status(self.handle))
 
     def destroy(self) -> None:
         if self.handle is not None and self.handle.value:
-            N.lib.sas_bp_destroy(self.handle)
+            N.lib().sas_bp_destroy(self.handle)
         self.handle = None
 
     def __del__(self):
@@ -82,7 +82,7 @@ def sas_bp_plan(descs: Sequence[N.SwathDesc], device: int = 0, tile=(0, 0, 0), p
     arr = (N.SwathDesc * len(descs))(*descs)
     opt = _options(device, tile, pings_per_chunk, use_graph, workspace_limit, threads)
     out = C.c_void_p()
-    check(N.lib.sas_bp_plan(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_plan")
+    check(N.lib().sas_bp_plan(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_plan")
     return Plan(out.value, descs, device)
 
 
@@ -92,7 +92,7 @@ def sas_bp_workspace_size(descs: Sequence[N.SwathDesc], tile=(0, 0, 0), pings_pe
     arr = (N.SwathDesc * len(descs))(*descs)
     opt = _options(0, tile, pings_per_chunk, threads=threads)
     out = C.c_size_t()
-    check(N.lib.sas_bp_workspace_size(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_workspace_size")
+    check(N.lib().sas_bp_workspace_size(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_workspace_size")
     return int(out.value)
 
 
@@ -155,7 +155,7 @@ def _stream(device: int, stream=None) -> C.c_void_p:
 
 def sas_bp_image(plan: Plan, bufs: Sequence[SwathBuffers], stream=None) -> None:
     arr = _io(plan, bufs)
-    check(N.lib.sas_bp_image(plan.handle, arr, len(bufs), _stream(plan.device, stream)), "sas_bp_image")
+    check(N.lib().sas_bp_image(plan.handle, arr, len(bufs), _stream(plan.device, stream)), "sas_bp_image")
 
 
 def sas_bp_adjoint(plan: Plan, bufs: Sequence[SwathBuffers], grad_images: Sequence[torch.Tensor],
@@ -173,14 +173,14 @@ def sas_bp_adjoint(plan: Plan, bufs: Sequence[SwathBuffers], grad_images: Sequen
     gt = (P * n)(*[t.data_ptr() for t in grad_tx])
     gr = (P * n)(*[t.data_ptr() for t in grad_rx])
     gc = (P * n)(*[t.data_ptr() for t in grad_c])
-    check(N.lib.sas_bp_adjoint(plan.handle, arr, gi, gt, gr, gc, n, _stream(plan.device, stream)),
+    check(N.lib().sas_bp_adjoint(plan.handle, arr, gi, gt, gr, gc, n, _stream(plan.device, stream)),
           "sas_bp_adjoint")
 
 
 def sas_bp_useful_updates(plan: Plan, bufs: Sequence[SwathBuffers], stream=None) -> list:
     arr = _io(plan, bufs)
     out = (C.c_int64 * len(bufs))()
-    check(N.lib.sas_bp_useful_updates(plan.handle, arr, len(bufs), _stream(plan.device, stream), out),
+    check(N.lib().sas_bp_useful_updates(plan.handle, arr, len(bufs), _stream(plan.device, stream), out),
           "sas_bp_useful_updates")
     return [int(v) for v in out]
 
@@ -192,10 +192,10 @@ def sas_bp_sharpness(plan: Plan, image: torch.Tensor, out_S: torch.Tensor,
     _need(out_S, "out_S", torch.float64, (1,), plan.device)
     if grad_image is not None:
         _need(grad_image, "grad_image", torch.complex64, tuple(image.shape), plan.device)
-    check(N.lib.sas_bp_sharpness(plan.handle, image.data_ptr(), image.numel(), out_S.data_ptr(),
+    check(N.lib().sas_bp_sharpness(plan.handle, image.data_ptr(), image.numel(), out_S.data_ptr(),
                                  grad_image.data_ptr() if grad_image is not None else None,
                                  _stream(plan.device, stream)), "sas_bp_sharpness")
 
 
 def sas_bp_abi_version() -> int:
-    return int(N.lib.sas_bp_abi_version())
+    return int(N.lib().sas_bp_abi_version())

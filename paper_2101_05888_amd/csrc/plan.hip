@@ -19,11 +19,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sas_bp.h"
+#include "sas_bp.h"
 #include "tdbp_dev.h"
 
 namespace sasbp {
-typedef void (*ImageKernelFn)(Workspace, int);
+typedef void (*ImageKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
 ImageKernelFn image_kernel_for(int layout, bool gate, int dt);
 int image_lds_bytes(int CP, int E, int W, int ROWS, bool gate);
 hipError_t launch_init(const Workspace& ws, hipStream_t st);
@@ -34,7 +34,7 @@ hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int 
 hipError_t image_occupancy(ImageKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu);
 hipError_t set_image_lds_limit(ImageKernelFn fn, int lds_bytes);
 
-typedef void (*AdjointKernelFn)(Workspace, int);
+typedef void (*AdjointKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
 AdjointKernelFn adjoint_kernel_for(int layout, bool gate, int dt);
 int adjoint_lds_bytes(int CP, int E, int W, int ROWS, bool gate, int threads);
 hipError_t launch_adjoint(AdjointKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads, int lds_bytes,
@@ -218,8 +218,12 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
     s.half_diag = 0.5 * std::sqrt(ex * ex + ey * ey + ez * ez);
     s.c_min = d[i].c_min > 0.0 ? d[i].c_min : kDefaultCmin;
     // window: delay offsets within the tile are bounded by +-2 r (triangle
-    // inequality on both legs), plus interpolation and rounding margin
-    s.W = (int)std::ceil(4.0 * s.half_diag * d[i].f_s / s.c_min) + 6;
+    // inequality on both legs). With the window start rounded down by up to
+    // spl - 1 samples to the staging load width (spl = 2 complex FP32 or 4
+    // complex 16-bit samples), entries up to 4 r f_s / c + spl + 2 are read;
+    // one more entry of margin for FP32 rounding of the sample position.
+    const int spl = d[i].echo_dtype == SAS_BP_ECHO_C64 ? 2 : 4;
+    s.W = (int)std::ceil(4.0 * s.half_diag * d[i].f_s / s.c_min) + spl + 4;
     if (s.W > 8192) return fail(SAS_BP_EUNSUPPORTED, "swath %d: tile spans %d samples; use a smaller tile", i, s.W);
     int cp = (o && o->pings_per_chunk > 0) ? o->pings_per_chunk : 0;
     const bool gate = d[i].gate_half_angle > 0.0;

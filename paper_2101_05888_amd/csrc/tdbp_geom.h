@@ -76,7 +76,7 @@ __device__ __forceinline__ int gate_class(double tan2, double x, double y, doubl
 
 // Receiver record and window start for (ping p, element e) of the tile centred
 // at C. Returns false if the navigation is not finite (record marked skip).
-__device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double c, const double C[3], int p, int e,
+__device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c, const double C[3], int p, int e,
                                                RxRec* rec, int* n0_out) {
   const double* T = sw.tx + (size_t)p * 3;
   const double* R = sw.rx + ((size_t)p * sw.E + e) * 3;
@@ -87,24 +87,28 @@ __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double c, con
   const double d0T = sqrt(uT0 * uT0 + uT1 * uT1 + uT2 * uT2);
   const double d0R = sqrt(uR0 * uR0 + uR1 * uR1 + uR2 * uR2);
   const bool ok = finite3(tx0, tx1, tx2) && finite3(rx0, rx1, rx2);
-  const double tau = (d0T + d0R) / c;
+  const double tau = (d0T + d0R) * inv_c;
   const double uref = (tau - sw.t0) * sw.fs;
-  const double span = 2.0 * sw.half_diag * sw.fs / c;
+  const double span = 2.0 * sw.half_diag * sw.fs * inv_c;
   double nstart = floor(uref - span) - 2.0;
   if (!(nstart > -1.0e9)) nstart = -1.0e9;          // also maps NaN to a harmless value
   if (nstart > 1.0e9) nstart = 1.0e9;
-  const int n0 = (int)nstart;
+  // window start on a multiple of the samples per 16-byte load (2 complex
+  // FP32 samples, 4 complex 16-bit samples) so that staging loads are aligned
+  const int spl = sw.dtype == 0 ? 2 : 4;
+  int n0 = (int)nstart;
+  n0 -= ((n0 % spl) + spl) % spl;
   const double cyc = sw.fc * tau;
   unsigned flags = ok ? 0u : kFlagSkip;
   // series bound over the tile: |num| <= 2 d0 r + r^2, remainder of
   // sqrt(1+y) - 1 after y^5 at most (21/1024) |y|^6 / (1 - |y|)
   const double r = sw.half_diag;
-  const double y = (2.0 * d0R * r + r * r) / (d0R * d0R);
+  const double i1 = 1.0 / d0R, i2 = i1 * i1;
+  const double y = (2.0 * d0R * r + r * r) * i2;
   double a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0;
   const double y3 = y * y * y;
   if (ok && y < 0.5 && d0R * (21.0 / 1024.0) * (y3 * y3) <= kPolyTol * (1.0 - y)) {
     flags |= kFlagPoly;
-    const double i1 = 1.0 / d0R, i2 = i1 * i1;
     a1 = 0.5 * i1;
     a2 = -0.125 * i1 * i2;
     a3 = 0.0625 * i1 * i2 * i2;
@@ -199,13 +203,14 @@ __device__ __forceinline__ void build_records(RxRec* lrx, int* ln0, const Worksp
                                                         double by1, double bz0, double bz1) {
   const int E = sw.E;
   const double tan2 = sw.tan_g * sw.tan_g;
+  const double inv_c = 1.0 / c;
 #pragma unroll 1
   for (int r = tid; r < cp * E; r += NT) {
     const int slot = r / E, e = r - slot * E;
     const int p = p0 + slot;
     RxRec rec;
     int n0;
-    if (!make_rx_record(sw, c, C, p, e, &rec, &n0)) atomicOr(&ws.counters[1], kStatusNav);
+    if (!make_rx_record(sw, inv_c, C, p, e, &rec, &n0)) atomicOr(&ws.counters[1], kStatusNav);
     unsigned f = __float_as_uint(rec.q0.w);
     if (!gate_on) {
       f |= kFlagFull;
@@ -221,6 +226,113 @@ __device__ __forceinline__ void build_records(RxRec* lrx, int* ln0, const Worksp
     lrx[r] = rec;
     ln0[r] = n0;
   }
+}
+
+
+// Samples of one 16-byte load: 2 complex FP32 samples, or 4 complex 16-bit
+// samples dequantised with the ping's scale.
+template <int DT>
+__device__ __forceinline__ void unpack16(const uint4 q, float scale, float2* s) {
+  if (DT == 0) {
+    s[0] = make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
+    s[1] = make_float2(__uint_as_float(q.z), __uint_as_float(q.w));
+  } else if (DT == 1) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const h2 v = __builtin_bit_cast(h2, w[i]);
+      s[i] = make_float2((float)v.x * scale, (float)v.y * scale);
+    }
+  } else {
+    const unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      s[i] = make_float2(__uint_as_float(w[i] << 16) * scale, __uint_as_float(w[i] & 0xffff0000u) * scale);
+  }
+}
+
+__device__ __forceinline__ float2 load_guarded(const SwathDev& sw, size_t rowbase, int n, int dt, float scale) {
+  if (n < 0 || n >= sw.Ns) return make_float2(0.0f, 0.0f);
+  return load_sample(sw.echo, rowbase + (size_t)n, dt, scale);
+}
+
+// Echo windows of a chunk into LDS. Entry k of window r holds E[n0+k] and
+// E[n0+k+1] - E[n0+k] (k < W); entry W is zero. Work is split into jobs of
+// 64 lanes x one 16-byte load each; every wave issues the loads of B jobs
+// before consuming any, and takes E[n+1] for its last sample from the next
+// lane. Samples outside the record read as zero.
+template <int NT, int DT>
+__device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, const int* ln0, const SwathDev& sw,
+                                              int p0, int cp, int tid, int lane, int wave) {
+  constexpr int NW = NT / 64;
+  constexpr int SPL = DT == 0 ? 2 : 4;      // samples per lane per load
+  constexpr int JS = 64 * SPL;              // samples per job
+  constexpr int B = 8;                      // jobs in flight per wave
+  const int E = sw.E, W = sw.W;
+  const int J = (W + JS) / JS;              // jobs per window (samples 0..W)
+  const int njobs = cp * E * J;
+  const bool aligned = (sw.Ns % SPL) == 0;
+  const char* echo = reinterpret_cast<const char*>(sw.echo);
+  constexpr int SB = DT == 0 ? 8 : 4;       // bytes per sample
+#pragma unroll 1
+  for (int j0 = wave; j0 < njobs; j0 += NW * B) {
+    uint4 q[B];
+    float2 tail[B];                         // lane 63: the sample after the job
+    bool fast[B];
+    // issue every load of the batch before using any
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = j0 + b * NW;
+      fast[b] = false;
+      tail[b] = make_float2(0.0f, 0.0f);
+      if (j >= njobs) continue;
+      const int r = j / J, part = j - r * J;
+      if (__float_as_uint(lrx[r].q0.w) & kFlagSkip) continue;
+      const int slot = r / E, e = r - slot * E;
+      const int p = p0 + slot;
+      const int first = ln0[r] + part * JS;       // sample index of the job's first lane
+      const size_t rowbase = ((size_t)p * E + e) * (size_t)sw.Ns;
+      if (aligned && first >= 0 && first + JS < sw.Ns) {
+        fast[b] = true;
+        q[b] = *reinterpret_cast<const uint4*>(echo + (rowbase + (size_t)(first + SPL * lane)) * SB);
+        if (lane == 63) tail[b] = load_sample(sw.echo, rowbase + (size_t)(first + JS), DT, 1.0f);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = j0 + b * NW;
+      if (j >= njobs) continue;
+      const int r = j / J, part = j - r * J;
+      if (__float_as_uint(lrx[r].q0.w) & kFlagSkip) continue;
+      const int slot = r / E, e = r - slot * E;
+      const int p = p0 + slot;
+      const size_t rowbase = ((size_t)p * E + e) * (size_t)sw.Ns;
+      const float scale = DT == 0 ? 1.0f : sw.scale[p];
+      const int k0 = part * JS + SPL * lane;      // window index of this lane's first sample
+      const int n = ln0[r] + k0;
+      float2 s[SPL + 1];
+      if (fast[b]) {
+        unpack16<DT>(q[b], scale, s);
+      } else {
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) s[i] = load_guarded(sw, rowbase, n + i, DT, scale);
+      }
+      s[SPL].x = __shfl_down(s[0].x, 1, 64);
+      s[SPL].y = __shfl_down(s[0].y, 1, 64);
+      if (lane == 63) {
+        s[SPL] = fast[b] ? make_float2(tail[b].x * scale, tail[b].y * scale)
+                         : load_guarded(sw, rowbase, n + SPL, DT, scale);
+      }
+      float4* dst = lwin + (size_t)r * (W + 1);
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        const int k = k0 + i;
+        if (k < W) dst[k] = make_float4(s[i].x, s[i].y, s[i + 1].x - s[i].x, s[i + 1].y - s[i].y);
+      }
+    }
+  }
+  for (int r = tid; r < cp * E; r += NT) lwin[(size_t)r * (W + 1) + W] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // Steps 1-2 of a chunk of pings, shared by the image and adjoint kernels:
@@ -262,38 +374,8 @@ __device__ __forceinline__ void prepare_chunk(unsigned char* lds, const Workspac
       lrows[q] = gate_row(sw, p0 + slot, e, y, z, x0, TX);
     }
   }
-  // 2. echo windows -> LDS: entry k holds E[n0+k] and E[n0+k+1] - E[n0+k]
-#pragma unroll 1
-  for (int r = wave; r < cp * E; r += NT / 64) {
-    const unsigned f = __float_as_uint(lrx[r].q0.w);
-    if (f & kFlagSkip) continue;
-    const int slot = r / E, e = r - slot * E;
-    const int p = p0 + slot;
-    const int n0 = ln0[r];
-    const size_t rowbase = ((size_t)p * E + e) * (size_t)sw.Ns;
-    const float scale = DT == 0 ? 1.0f : sw.scale[p];
-    float4* dst = lwin + (size_t)r * (W + 1);
-    if (n0 >= 0 && n0 + W < sw.Ns) {
-      // whole window inside the record: no per-sample checks
-      const size_t base = rowbase + (size_t)n0;
-#pragma unroll 2
-      for (int k = lane; k < W; k += 64) {
-        const float2 a = load_sample(sw.echo, base + k, DT, scale);
-        const float2 b = load_sample(sw.echo, base + k + 1, DT, scale);
-        dst[k] = make_float4(a.x, a.y, b.x - a.x, b.y - a.y);
-      }
-    } else {
-#pragma unroll 1
-      for (int k = lane; k < W; k += 64) {
-        const int n = n0 + k;
-        float2 a = make_float2(0.0f, 0.0f), b = make_float2(0.0f, 0.0f);
-        if (n >= 0 && n < sw.Ns) a = load_sample(sw.echo, rowbase + (size_t)n, DT, scale);
-        if (n + 1 >= 0 && n + 1 < sw.Ns) b = load_sample(sw.echo, rowbase + (size_t)n + 1, DT, scale);
-        dst[k] = make_float4(a.x, a.y, b.x - a.x, b.y - a.y);
-      }
-    }
-    if (lane == 0) dst[W] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  }
+  // 2. echo windows -> LDS
+  stage_windows<NT, DT>(lwin, lrx, ln0, sw, p0, cp, tid, lane, wave);
   __syncthreads();
 }
 

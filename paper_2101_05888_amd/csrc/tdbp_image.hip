@@ -181,9 +181,12 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
   }
 }
 
+// The read-only tables are separate restrict-qualified arguments so that the
+// compiler may read them through the scalar cache.
 template <int L, bool GATE, int DT>
-__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) void image_kernel(Workspace ws,
-                                                                                                 int n_tiles) {
+__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) void image_kernel(
+    Workspace ws, const SwathDev* __restrict__ swaths, const int* __restrict__ order,
+    const int* __restrict__ tile_swath, const PingRange* __restrict__ prange, int n_tiles) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int K = kLayouts[L].K, LX = kLayouts[L].LX, LY = kLayouts[L].LY, LZ = kLayouts[L].LZ;
   constexpr int NT = LX * LY * LZ;
@@ -200,9 +203,9 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(s_item);
     if (item >= n_tiles) break;
-    const int t = __builtin_amdgcn_readfirstlane(ws.order[item]);
-    const int s = __builtin_amdgcn_readfirstlane(ws.tile_swath[t]);
-    const SwathDev& sw = ws.swaths[s];
+    const int t = __builtin_amdgcn_readfirstlane(order[item]);
+    const int s = __builtin_amdgcn_readfirstlane(tile_swath[t]);
+    const SwathDev& sw = swaths[s];
     const int E = sw.E, W = sw.W, CP = sw.CP;
     const int lt = t - sw.tile0;
     const int tix = lt % sw.ntx, tiy = (lt / sw.ntx) % sw.nty, tiz = lt / (sw.ntx * sw.nty);
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
     const double c = *sw.c;
     const float fs_c = (float)(sw.fs / c);
     const float fc_c = (float)(sw.fc / c);
-    const PingRange pr = ws.prange[t];
+    const PingRange pr = prange[t];
     const LdsLayout Ld = lds_layout(CP, E, W, ROWS, GATE);
     const TxRec* ltx = reinterpret_cast<const TxRec*>(lds + Ld.off_tx);
     const RxRec* lrx = reinterpret_cast<const RxRec*>(lds + Ld.off_rx);
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
 
 // ------------------------------------------------------------ dispatch ---
 
-typedef void (*ImageKernelFn)(Workspace, int);
+typedef void (*ImageKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
 
 template <int L>
 static ImageKernelFn image_for_layout(bool gate, int dt) {
@@ -344,7 +347,8 @@ hipError_t launch_order(const Workspace& ws, int n_tiles, int bucket_shift, hipS
 
 hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads, int lds_bytes,
                         hipStream_t st) {
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds_bytes, st, ws, n_tiles);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds_bytes, st, ws, (const SwathDev*)ws.swaths,
+                     (const int*)ws.order, (const int*)ws.tile_swath, (const PingRange*)ws.prange, n_tiles);
   return hipGetLastError();
 }
 

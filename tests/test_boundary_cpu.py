@@ -21,16 +21,16 @@ def test_library_exports_every_declared_symbol():
     names = _declared()
     assert "sas_bp_plan" in names and "sas_bp_image" in names and "sas_bp_adjoint" in names
     for n in names:
-        assert hasattr(N.lib, n), n
+        assert hasattr(N.lib(), n), n
     assert set(N.EXPORTED) == set(names)
 
 
 def test_abi_version_and_error_strings():
     from paper_2101_05888_amd import _native as N
-    assert N.lib.sas_bp_abi_version() == 1
+    assert N.lib().sas_bp_abi_version() == 1
     for s in range(6):
-        assert N.lib.sas_bp_error_string(s)
-    assert N.lib.sas_bp_error_string(99) == b"unknown status"
+        assert N.lib().sas_bp_error_string(s)
+    assert N.lib().sas_bp_error_string(99) == b"unknown status"
 
 
 def _desc(api, **kw):
@@ -85,11 +85,11 @@ def test_plan_without_device_reports_device_error():
 
 def test_null_arguments_rejected():
     from paper_2101_05888_amd import _native as N
-    assert N.lib.sas_bp_plan(None, 1, None, None) == 1
-    assert N.lib.sas_bp_image(None, None, 1, None) == 1
-    assert N.lib.sas_bp_plan_status(None) == 1
+    assert N.lib().sas_bp_plan(None, 1, None, None) == 1
+    assert N.lib().sas_bp_image(None, None, 1, None) == 1
+    assert N.lib().sas_bp_plan_status(None) == 1
     out = C.c_size_t()
-    assert N.lib.sas_bp_workspace_size(None, 1, None, C.byref(out)) == 1
+    assert N.lib().sas_bp_workspace_size(None, 1, None, C.byref(out)) == 1
 
 
 def test_product_path_has_no_oracle_or_cpu_fallback():
