@@ -11,9 +11,10 @@ Sec. II-C evaluated per term, and of its gradient with respect to the
 navigation and the sound speed. It shares no code with the HIP path.
 """
 from .tdbp import (pixel_points, backproject, backproject_image, gated_term_count,
-                   gated_term_count_rows, vjp, sharpness, sharpness_cotangent)
+                   gated_term_count_rows, vjp, vjp_segment_bound, sharpness,
+                   sharpness_cotangent)
 from .metrics import rel_l2, phase_error_mrad
 
 __all__ = ["pixel_points", "backproject", "backproject_image", "gated_term_count",
-           "gated_term_count_rows", "vjp", "sharpness", "sharpness_cotangent",
+           "gated_term_count_rows", "vjp", "vjp_segment_bound", "sharpness", "sharpness_cotangent",
            "rel_l2", "phase_error_mrad"]

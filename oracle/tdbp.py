@@ -235,6 +235,56 @@ def vjp(echo, tx, rx, c, fc, fs, t0, points, gbar, gate_half_angle=0.0):
     return g_tx, g_rx, g_c
 
 
+def vjp_segment_bound(echo, tx, rx, c, fc, fs, t0, points, gbar, gate_half_angle=0.0, delta=1e-4):
+    """Largest change of ``vjp`` that choosing the other interpolation segment
+    can make for terms whose sample position u lies within ``delta`` samples of
+    an integer (the derivative of the linear interpolator jumps there, so an
+    implementation whose u carries a rounding error up to ``delta`` may take
+    either slope). Returns non-negative (b_tx [P,3], b_rx [P,E,3], b_c).
+
+    For such a term with m = round(u), the slopes left and right of sample m
+    are s_l = E~[m] - E~[m-1] and s_r = E~[m+1] - E~[m]; the two choices of D
+    differ by at most f_s |s_r - s_l| + 2 pi f_c delta (|s_l| + |s_r|) (the
+    second part bounds the change of L over the rounding interval). Each term's
+    bound is |Gbar| times that, times |dtau/dtheta| per component.
+    """
+    echo = np.asarray(echo).astype(np.complex128, copy=False)
+    tx = np.asarray(tx, dtype=np.float64)
+    rx = np.asarray(rx, dtype=np.float64)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    gbar = np.asarray(gbar, dtype=np.complex128).reshape(-1)
+    P, E = rx.shape[0], rx.shape[1]
+    b_tx = np.zeros((P, 3))
+    b_rx = np.zeros((P, E, 3))
+    b_c = 0.0
+    sin_g = math.sin(gate_half_angle) if gate_half_angle > 0 else None
+    for i in range(P):
+        dT = np.sqrt(((pts - tx[i]) ** 2).sum(axis=1))
+        gT = _gate(pts[:, 0] - tx[i, 0], dT, sin_g) if sin_g is not None else None
+        for e in range(E):
+            R = rx[i, e]
+            dR = np.sqrt(((pts - R) ** 2).sum(axis=1))
+            tau = (dT + dR) / c
+            u = (tau - t0) * fs
+            m = np.round(u)
+            near = np.abs(u - m) < delta
+            if sin_g is not None:
+                near &= gT & _gate(pts[:, 0] - R[0], dR, sin_g)
+            if not near.any():
+                continue
+            mi = m[near].astype(np.int64)
+            em1, e0 = _taps(echo[i, e], mi - 1)
+            _, e1 = _taps(echo[i, e], mi)
+            sl, sr = e0 - em1, e1 - e0
+            dD = fs * np.abs(sr - sl) + 2.0 * np.pi * fc * delta * (np.abs(sl) + np.abs(sr))
+            q = np.abs(gbar[near]) * dD
+            p = pts[near]
+            b_tx[i] += ((q / (c * dT[near]))[:, None] * np.abs(tx[i] - p)).sum(axis=0)
+            b_rx[i, e] += ((q / (c * dR[near]))[:, None] * np.abs(R - p)).sum(axis=0)
+            b_c += float((q * tau[near] / c).sum())
+    return b_tx, b_rx, b_c
+
+
 def sharpness(img) -> float:
     """S = sum |I|^4 / (sum |I|^2)^2."""
     m2 = np.abs(np.asarray(img, dtype=np.complex128)) ** 2

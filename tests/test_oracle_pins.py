@@ -301,6 +301,39 @@ def test_p7_gradient_with_gate_and_record_edge():
     assert np.linalg.norm(g_tx - fd) <= 1e-4 * np.linalg.norm(fd)
 
 
+def test_p7_segment_bound_equals_the_jump_at_a_sample():
+    # One monostatic term with u on either side of sample m = 20; the echo is 0
+    # at samples 19 and 20 and 1 at 21, so the slope is 0 left of m and 1 right
+    # of it. With Gbar = exp(j 2 pi f_c tau), Re(conj(Gbar) D) jumps by exactly
+    # f_s, so dJ/dc jumps by f_s tau / c and dJ/dT by f_s |T - p| / (c d_T).
+    c, fc, fs = 1500.0, 9e3, 10e3
+    echo = np.zeros((1, 1, 40), dtype=np.complex128)
+    echo[0, 0, 21] = 1.0
+    tx = np.zeros((1, 3))
+    rx = np.zeros((1, 1, 3))
+    m, eps = 20, 1e-7
+    out = {}
+    for side in (+1, -1):
+        d = (m + side * eps) * c / (2.0 * fs)
+        p = np.array([[0.0, d, 0.0]])
+        tau = 2.0 * d / c
+        gbar = np.array([np.exp(1j * 2.0 * np.pi * fc * tau)])
+        out[side] = oracle.vjp(echo, tx, rx, c, fc, fs, 0.0, p, gbar)
+        b = oracle.vjp_segment_bound(echo, tx, rx, c, fc, fs, 0.0, p, gbar, delta=1e-6)
+        far = oracle.vjp_segment_bound(echo, tx, rx, c, fc, fs, 0.0, p + [0.0, 0.3 * c / (2.0 * fs), 0.0],
+                                       gbar, delta=1e-6)
+        assert np.all(far[0] == 0) and far[2] == 0.0
+        tau_m = 2.0 * m / (2.0 * fs)
+        assert b[2] == pytest.approx(fs * tau_m / c, rel=1e-4)
+        assert b[0][0, 1] == pytest.approx(fs / c, rel=1e-4)
+        assert b[1][0, 0, 1] == pytest.approx(fs / c, rel=1e-4)
+    jump_c = abs(out[+1][2] - out[-1][2])
+    jump_t = np.abs(out[+1][0] - out[-1][0])
+    assert jump_c == pytest.approx(fs * (m / fs) / c, rel=1e-5)
+    assert jump_t[0, 1] == pytest.approx(fs / c, rel=1e-5)
+    assert jump_c <= b[2] * (1 + 1e-5)
+
+
 def test_p7_sharpness_identities_and_cotangent():
     one = np.zeros(50, dtype=np.complex128)
     one[17] = 2.5 - 1j
