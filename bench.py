@@ -91,6 +91,74 @@ def cpu_baseline_leg(scn, echo_cpu: np.ndarray, images: dict, sample: int) -> di
             "seconds": dt, "useful_updates": int(useful), "accuracy": acc}
 
 
+def _buffers(api, scn, echo):
+    g = scn.grid
+    return api.SwathBuffers(
+        echo=echo, tx=torch.as_tensor(scn.tx, device="cuda"), rx=torch.as_tensor(scn.rx, device="cuda"),
+        c=torch.tensor([scn.c], dtype=torch.float64, device="cuda"),
+        image=torch.empty((g.n[2], g.n[1], g.n[0]), dtype=torch.complex64, device="cuda"))
+
+
+def _desc(api, scn):
+    g = scn.grid
+    return api.swath_desc(scn.n_ping, scn.n_elem, scn.n_sample, g.n, g.origin, g.spacing, scn.fc, scn.fs,
+                          scn.t0, scn.gate_half_angle)
+
+
+def autofocus_leg(api, steps: int, warmup: int) -> dict:
+    """One autofocus iteration on the differentiable workload (256 pings x 16
+    receivers, 1024 x 1024 pixels, no gate): image, sharpness and its
+    cotangent, then the geometry adjoint."""
+    from synth import make_config, synthesize_echo
+    scn = make_config("c5")
+    echo = synthesize_echo(scn, device="cuda", dtype=torch.complex64)
+    plan = api.sas_bp_plan([_desc(api, scn)])
+    buf = _buffers(api, scn, echo)
+    S = torch.zeros(1, dtype=torch.float64, device="cuda")
+    G = torch.empty_like(buf.image)
+    gtx = torch.empty((scn.n_ping, 3), dtype=torch.float64, device="cuda")
+    grx = torch.empty((scn.n_ping, scn.n_elem, 3), dtype=torch.float64, device="cuda")
+    gc = torch.empty(1, dtype=torch.float64, device="cuda")
+    fwd = time_steps(lambda: api.sas_bp_image(plan, [buf]), steps, warmup)
+    sharp = time_steps(lambda: api.sas_bp_sharpness(plan, buf.image, S, G), steps, warmup)
+    adj = time_steps(lambda: api.sas_bp_adjoint(plan, [buf], [G], [gtx], [grx], [gc]), steps, warmup)
+    updates = scn.nominal_updates()
+    log(f"autofocus: forward {fwd:.3f} ms, sharpness {sharp:.3f} ms, adjoint {adj:.3f} ms")
+    return {"workload": "256 pings x 16 receivers, 4096 samples, 1024x1024 px, no gate",
+            "updates": int(updates), "forward_ms": fwd, "sharpness_ms": sharp, "adjoint_ms": adj,
+            "forward_updates_per_s": updates / (fwd * 1e-3), "adjoint_updates_per_s": updates / (adj * 1e-3),
+            "iteration_ms": fwd + sharp + adj}
+
+
+def batched_leg(api, steps: int, warmup: int) -> dict:
+    """24 swaths of uneven size in one persistent graph launch against 24
+    separate plans launched one after the other on the same stream."""
+    from synth import make_config, synthesize_echo
+    scns = [make_config(f"c4b:{k}") for k in range(24)]
+    echoes = [synthesize_echo(s, device="cuda", dtype=torch.complex64, noise_on_device=True) for s in scns]
+    torch.cuda.synchronize()
+    plan = api.sas_bp_plan([_desc(api, s) for s in scns])
+    bufs = [_buffers(api, s, e) for s, e in zip(scns, echoes)]
+    useful = sum(api.sas_bp_useful_updates(plan, bufs))
+    one = time_steps(lambda: api.sas_bp_image(plan, bufs), steps, warmup)
+    plans = [api.sas_bp_plan([_desc(api, s)]) for s in scns]
+
+    def separate():
+        for p, b in zip(plans, bufs):
+            api.sas_bp_image(p, [b])
+
+    sep = time_steps(separate, steps, warmup)
+    log(f"batched: one launch {one:.2f} ms, 24 launches {sep:.2f} ms, useful {useful:.3e}")
+    nominal = sum(s.nominal_updates() for s in scns)
+    for p in plans:
+        p.destroy()
+    plan.destroy()
+    return {"workload": "24 swaths, sides U{512..4096} px, 128-512 pings, 16-32 receivers, +-10 deg gate",
+            "useful_updates": int(useful), "nominal_updates": int(nominal),
+            "one_launch_ms": one, "separate_launches_ms": sep, "speedup": sep / one,
+            "one_launch_updates_per_s": useful / (one * 1e-3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +167,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-autofocus", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -109,7 +179,7 @@ def main() -> int:
         print(json.dumps({"error": "no HIP device visible"}), flush=True)
         return 3
     if args.profile:
-        args.no_cpu_baseline = True
+        args.no_cpu_baseline = args.no_autofocus = args.no_batched = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -134,10 +204,12 @@ def main() -> int:
         return plan, buf
 
     if args.profile:
-        # calibration for HBM byte counters: a plain copy of exactly 256 MiB
+        # calibration for the HBM byte counters: one elementwise kernel that
+        # reads and writes exactly 256 MiB each (torch.neg, a kernel nothing
+        # else in this program launches)
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
     plan, buf = make(echo)
@@ -145,14 +217,26 @@ def main() -> int:
     nominal = scn.nominal_updates()
     info = plan.info()
     log(f"plan {info}; useful updates {useful} of {nominal}")
-    ms = time_steps(lambda: api.sas_bp_image(plan, [buf]), args.steps, args.warmup)
+    # Timed region: the image kernel is bracketed by HIP events on the launch
+    # stream (the library then enqueues the cull, ordering and image kernels
+    # directly instead of replaying its graph).
+    api.sas_bp_set_kernel_timing(plan, True)
+    for _ in range(args.warmup):
+        api.sas_bp_image(plan, [buf])
+    api.sas_bp_kernel_time(plan)
+    ms = time_steps(lambda: api.sas_bp_image(plan, [buf]), args.steps, 0)
+    k_total, k_launches = api.sas_bp_kernel_time(plan)
+    api.sas_bp_set_kernel_timing(plan, False)
+    kernel_ms = k_total / k_launches
+    graph_ms = time_steps(lambda: api.sas_bp_image(plan, [buf]), args.steps, 1)
     if plan.status() != 0:
         log("device reported bad navigation")
         return 4
     value = useful / (ms * 1e-3)
-    log(f"fp32: {ms:.3f} ms/step, {value:.4e} useful updates/s")
+    log(f"fp32: {ms:.3f} ms/step ({graph_ms:.3f} ms as a graph replay), image kernel {kernel_ms:.3f} ms, "
+        f"{value:.4e} useful updates/s")
     fpu = flops_per_update(scn.n_elem)
-    achieved = value * fpu / 1e12
+    achieved = useful * fpu / (kernel_ms * 1e-3) / 1e12
     images = {"fp32": buf.image.cpu().numpy()}
 
     out = {
@@ -166,9 +250,12 @@ def main() -> int:
                    "tile": [info["tile_x"], info["tile_y"], info["tile_z"]],
                    "pings_per_chunk": info["pings_per_chunk"], "grid": info["grid"]},
         "nominal_updates_per_s": nominal / (ms * 1e-3),
+        "graph_ms_per_step": graph_ms,
+        "image_kernel_ms": kernel_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "flops_per_update": fpu, "kernel": "image_kernel (graph: cull + order + image)"},
+                     "flops_per_update": fpu, "kernel": "image_kernel", "launch_ms": kernel_ms,
+                     "updates_per_launch": int(useful)},
     }
 
     if not args.no_mixed:
@@ -183,6 +270,11 @@ def main() -> int:
             p2.destroy()
             del q, b2
         out["mixed"] = mixed
+
+    if not args.no_autofocus:
+        out["autofocus_step"] = autofocus_leg(api, args.steps, args.warmup)
+    if not args.no_batched:
+        out["batched"] = batched_leg(api, max(3, args.steps // 4), 1)
 
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host cores")

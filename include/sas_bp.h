@@ -164,6 +164,17 @@ int sas_bp_plan_status(sas_bp_plan_t plan);
  * workgroup. */
 int sas_bp_plan_info(sas_bp_plan_t plan, int64_t info[8]);
 
+/* Per-launch timing of the main kernel, for measuring it against its
+ * roofline. With enable != 0, sas_bp_image and sas_bp_adjoint enqueue their
+ * kernels directly (not through the captured graph) and bracket the
+ * persistent image or adjoint kernel with a pair of HIP events on the
+ * caller's stream; enable = 0 restores graph launches and drops pending
+ * pairs. sas_bp_kernel_time waits for the recorded pairs, writes the sum of
+ * their durations in milliseconds to *ms_total and their number to
+ * *launches (host memory), and starts a new count. */
+int sas_bp_set_kernel_timing(sas_bp_plan_t plan, int enable);
+int sas_bp_kernel_time(sas_bp_plan_t plan, double* ms_total, int64_t* launches);
+
 void sas_bp_destroy(sas_bp_plan_t plan);
 
 const char* sas_bp_error_string(int status);

@@ -1,13 +1,14 @@
 """MI355X-native time-domain backprojection for synthetic aperture sonar.
 
 The computation lives in the HIP library ``libsas_bp.so`` (C ABI in
-``include/sas_bp.h``); this package is its binding. Importing it without the
-built library raises ``ImportError``: there is no CPU fallback.
+``include/sas_bp.h``); this package is its binding. Any call into it without
+the built library raises ``ImportError``: there is no CPU fallback.
 """
 from .api import (Plan, SwathBuffers, swath_desc, sas_bp_plan, sas_bp_workspace_size, sas_bp_image,
-                  sas_bp_adjoint, sas_bp_useful_updates, sas_bp_sharpness, sas_bp_abi_version)
+                  sas_bp_adjoint, sas_bp_useful_updates, sas_bp_sharpness, sas_bp_set_kernel_timing,
+                  sas_bp_kernel_time, sas_bp_abi_version)
 from ._native import SasBpError
 
 __all__ = ["Plan", "SwathBuffers", "swath_desc", "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image",
-           "sas_bp_adjoint", "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_abi_version",
-           "SasBpError"]
+           "sas_bp_adjoint", "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_set_kernel_timing",
+           "sas_bp_kernel_time", "sas_bp_abi_version", "SasBpError"]

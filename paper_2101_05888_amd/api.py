@@ -197,5 +197,17 @@ def sas_bp_sharpness(plan: Plan, image: torch.Tensor, out_S: torch.Tensor,
                                  _stream(plan.device, stream)), "sas_bp_sharpness")
 
 
+def sas_bp_set_kernel_timing(plan: Plan, enable: bool) -> None:
+    check(N.lib().sas_bp_set_kernel_timing(plan.handle, 1 if enable else 0), "sas_bp_set_kernel_timing")
+
+
+def sas_bp_kernel_time(plan: Plan) -> tuple:
+    """(total milliseconds, launches) of the main kernel since the last read."""
+    ms = C.c_double()
+    n = C.c_int64()
+    check(N.lib().sas_bp_kernel_time(plan.handle, C.byref(ms), C.byref(n)), "sas_bp_kernel_time")
+    return float(ms.value), int(n.value)
+
+
 def sas_bp_abi_version() -> int:
     return int(N.lib().sas_bp_abi_version())

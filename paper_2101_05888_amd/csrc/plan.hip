@@ -85,14 +85,20 @@ constexpr int kLdsMax = 160 * 1024;
 struct SwathPlan {
   sas_bp_swath_desc d;
   int ntx, nty, ntz, ntiles, tile0;
-  int W, CP;
+  int W, CP, SC;
   double half_diag, c_min;
 };
 
 struct Layout {
-  size_t swaths, prange, order, counters, bucket, tile_swath, scratch, total;
+  size_t swaths, prange, order, counters, bucket, tile_swath, scratch, geo, total;
+  size_t geo_stride;   // bytes of geometry scratch per resident workgroup
+  int geo_slots;       // resident workgroups the geometry scratch serves
   size_t n_partials;   // adjoint records, allocated on the first adjoint call
 };
+
+// Compute units the geometry scratch is sized for (an MI355X has 256); a
+// device with more runs at most this many times the per-CU occupancy.
+constexpr int kMaxCUs = 256;
 
 }  // namespace
 
@@ -123,6 +129,9 @@ struct sas_bp_plan_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // pairs bracketing the main kernel
+  size_t n_timed = 0;              // pairs recorded since the last read
 };
 
 namespace {
@@ -218,12 +227,10 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
     s.half_diag = 0.5 * std::sqrt(ex * ex + ey * ey + ez * ez);
     s.c_min = d[i].c_min > 0.0 ? d[i].c_min : kDefaultCmin;
     // window: delay offsets within the tile are bounded by +-2 r (triangle
-    // inequality on both legs). With the window start rounded down by up to
-    // spl - 1 samples to the staging load width (spl = 2 complex FP32 or 4
-    // complex 16-bit samples), entries up to 4 r f_s / c + spl + 2 are read;
+    // inequality on both legs). With the window start rounded down to an even
+    // sample (the staging load width), entries up to 4 r f_s / c + 4 are read;
     // one more entry of margin for FP32 rounding of the sample position.
-    const int spl = d[i].echo_dtype == SAS_BP_ECHO_C64 ? 2 : 4;
-    s.W = (int)std::ceil(4.0 * s.half_diag * d[i].f_s / s.c_min) + spl + 4;
+    s.W = (int)std::ceil(4.0 * s.half_diag * d[i].f_s / s.c_min) + 6;
     if (s.W > 8192) return fail(SAS_BP_EUNSUPPORTED, "swath %d: tile spans %d samples; use a smaller tile", i, s.W);
     int cp = (o && o->pings_per_chunk > 0) ? o->pings_per_chunk : 0;
     const bool gate = d[i].gate_half_angle > 0.0;
@@ -235,13 +242,20 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
       return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d pings x %d elements x %d samples exceed LDS", i, cp,
                   d[i].n_elem, s.W);
     s.CP = cp;
+    // pings whose FP64 geometry is built at once: enough (ping, element)
+    // records to keep every thread of the workgroup busy, a multiple of the
+    // chunk, and a partial-record list that fits the window area
+    int sc = std::max(1, std::min(32, 1024 / d[i].n_elem));
+    sc = std::max(cp, sc / cp * cp);
+    sc = std::min(sc, 4 * cp * (s.W + 1) / cp * cp);
+    s.SC = sc;
     out->push_back(s);
   }
   *n_tiles = tiles;
   return SAS_BP_OK;
 }
 
-Layout make_layout(int n_swaths, int n_tiles, size_t n_partials) {
+Layout make_layout(int n_swaths, int n_tiles, size_t n_partials, size_t geo_stride, int geo_slots) {
   Layout L{};
   size_t o = 0;
   L.swaths = o;     o = align_up(o + sizeof(SwathDev) * n_swaths);
@@ -251,6 +265,9 @@ Layout make_layout(int n_swaths, int n_tiles, size_t n_partials) {
   L.bucket = o;     o = align_up(o + sizeof(unsigned) * kBuckets);
   L.tile_swath = o; o = align_up(o + sizeof(int) * n_tiles);
   L.scratch = o;    o = align_up(o + sizeof(double) * (2 * kSharpPartials + 64));
+  L.geo = o;        o = align_up(o + geo_stride * (size_t)geo_slots);
+  L.geo_stride = geo_stride;
+  L.geo_slots = geo_slots;
   L.n_partials = n_partials;
   L.total = o;
   return L;
@@ -279,6 +296,7 @@ SwathDev make_dev(const SwathPlan& s) {
   v.tile0 = s.tile0;
   v.W = s.W;
   v.CP = s.CP;
+  v.SC = s.SC;
   for (int a = 0; a < 3; ++a) {
     v.o[a] = s.d.origin[a];
     v.d[a] = (a == 2 && s.d.n[2] == 1 && !(s.d.spacing[2] > 0.0)) ? 1.0 : s.d.spacing[a];
@@ -325,11 +343,33 @@ int upload(sas_bp_plan_s* p, const std::vector<SwathDev>& v, hipStream_t st) {
   return SAS_BP_OK;
 }
 
+// Event pair for the next timed launch (created on first use, then reused).
+int timing_pair(sas_bp_plan_s* p, hipEvent_t* a, hipEvent_t* b) {
+  while (p->events.size() < 2 * (p->n_timed + 1)) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreate(&e));
+    p->events.push_back(e);
+  }
+  *a = p->events[2 * p->n_timed];
+  *b = p->events[2 * p->n_timed + 1];
+  return SAS_BP_OK;
+}
+
 int enqueue_image(sas_bp_plan_s* p, hipStream_t st) {
   HIP_TRY(launch_init(p->ws, st));
   HIP_TRY(launch_cull(p->ws, p->n_tiles, p->tiling.TX, p->tiling.TY, p->tiling.TZ, p->bucket_shift, st));
   HIP_TRY(launch_order(p->ws, p->n_tiles, p->bucket_shift, st));
+  hipEvent_t a = nullptr, b = nullptr;
+  if (p->timing) {
+    int rc = timing_pair(p, &a, &b);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(a, st));
+  }
   HIP_TRY(launch_image(p->image_fn, p->ws, p->n_tiles, p->grid, p->tiling.NT, p->lds_bytes, st));
+  if (p->timing) {
+    HIP_TRY(hipEventRecord(b, st));
+    ++p->n_timed;
+  }
   return SAS_BP_OK;
 }
 
@@ -366,6 +406,7 @@ void release(sas_bp_plan_s* p) {
     (void)hipEventSynchronize(p->upload_done);
     (void)hipEventDestroy(p->upload_done);
   }
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   if (p->host_sw) (void)hipHostFree(p->host_sw);
   if (p->adj_buf) (void)hipFree(p->adj_buf);
   if (p->slab) (void)hipFree(p->slab);
@@ -396,7 +437,21 @@ int plan_sizes(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, Ti
   if (rc) return rc;
   rc = build_swaths(desc, n, o, *t, sw, n_tiles);
   if (rc) return rc;
-  *lay = make_layout(n, *n_tiles, adjoint_partials(*sw));
+  // geometry scratch: one region per resident workgroup, as many as the
+  // smaller of the two kernels' LDS footprints lets a CU hold
+  bool gate_any = false;
+  for (const auto& s : *sw) gate_any |= s.d.gate_half_angle > 0.0;
+  const int rows = t->TY * t->TZ;
+  size_t stride = 0;
+  int lds = 0;
+  for (const auto& s : *sw) {
+    stride = std::max(stride, (size_t)geo_layout(s.SC, s.d.n_elem, rows, gate_any).bytes);
+    lds = std::max(lds, std::min(image_lds_bytes(s.CP, s.d.n_elem, s.W, rows, gate_any),
+                                 adjoint_lds_bytes(s.CP, s.d.n_elem, s.W, rows, gate_any, t->NT)));
+  }
+  const int per_cu = std::max(1, std::min(8, kLdsMax / std::max(1, lds)));
+  const int slots = (int)std::min<long long>(*n_tiles, (long long)kMaxCUs * per_cu);
+  *lay = make_layout(n, *n_tiles, adjoint_partials(*sw), stride, slots);
   return SAS_BP_OK;
 }
 
@@ -511,8 +566,8 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
     release(p);
     return fail(SAS_BP_EUNSUPPORTED, "tiling needs %d bytes of LDS; no workgroup fits", max_lds);
   }
-  p->grid = std::max(1, std::min(n_tiles, occ * prop.multiProcessorCount));
-  p->adj_grid = std::max(1, std::min(n_tiles, adj_occ * prop.multiProcessorCount));
+  p->grid = std::max(1, std::min(std::min(n_tiles, occ * prop.multiProcessorCount), lay.geo_slots));
+  p->adj_grid = std::max(1, std::min(std::min(n_tiles, adj_occ * prop.multiProcessorCount), lay.geo_slots));
 
   e = hipMalloc(&p->slab, lay.total);
   if (e != hipSuccess) {
@@ -529,6 +584,8 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->ws.partials = nullptr;
   p->ws.cpart = nullptr;
   p->ws.scratch64 = reinterpret_cast<double*>(p->slab + lay.scratch);
+  p->ws.geo = p->slab + lay.geo;
+  p->ws.geo_stride = (long long)lay.geo_stride;
 
   std::vector<int> tile_swath(n_tiles);
   for (int i = 0; i < n_swaths; ++i)
@@ -573,7 +630,7 @@ int sas_bp_image(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swaths, void*
   }
   rc = upload(p, v, st);
   if (rc) return rc;
-  if (p->use_graph) {
+  if (p->use_graph && !p->timing) {
     HIP_TRY(hipGraphLaunch(p->graph_exec, st));
     return SAS_BP_OK;
   }
@@ -628,7 +685,17 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
   HIP_TRY(launch_init(p->ws, st));
   HIP_TRY(launch_cull(p->ws, p->n_tiles, p->tiling.TX, p->tiling.TY, p->tiling.TZ, p->bucket_shift, st));
   HIP_TRY(launch_order(p->ws, p->n_tiles, p->bucket_shift, st));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (p->timing) {
+    rc = timing_pair(p, &ea, &eb);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ea, st));
+  }
   HIP_TRY(launch_adjoint(p->adjoint_fn, p->ws, p->n_tiles, p->adj_grid, p->tiling.NT, p->adj_lds_bytes, st));
+  if (p->timing) {
+    HIP_TRY(hipEventRecord(eb, st));
+    ++p->n_timed;
+  }
   HIP_TRY(launch_adjoint_reduce(p->ws, n_swaths, p->max_p, st));
   return SAS_BP_OK;
 }
@@ -704,6 +771,30 @@ int sas_bp_plan_info(sas_bp_plan_t p, int64_t info[8]) {
   info[5] = p->lds_bytes;
   info[6] = p->grid;
   info[7] = p->tiling.NT;
+  return SAS_BP_OK;
+}
+
+int sas_bp_set_kernel_timing(sas_bp_plan_t p, int enable) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  p->timing = enable != 0;
+  p->n_timed = 0;
+  return SAS_BP_OK;
+}
+
+int sas_bp_kernel_time(sas_bp_plan_t p, double* ms_total, int64_t* launches) {
+  if (!p || !ms_total || !launches) return fail(SAS_BP_EINVAL, "NULL argument");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  DeviceGuard guard(p->device);
+  double sum = 0.0;
+  for (size_t i = 0; i < p->n_timed; ++i) {
+    HIP_TRY(hipEventSynchronize(p->events[2 * i + 1]));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->events[2 * i], p->events[2 * i + 1]));
+    sum += (double)ms;
+  }
+  *ms_total = sum;
+  *launches = (int64_t)p->n_timed;
+  p->n_timed = 0;
   return SAS_BP_OK;
 }
 

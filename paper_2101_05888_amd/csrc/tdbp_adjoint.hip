@@ -49,6 +49,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
   const int lx = tid % LX, ly = (tid / LX) % LY, lz = tid / (LX * LY);
   const int row = ly + LY * lz;
   __shared__ int s_item;
+  __shared__ int s_npart;
 
   for (;;) {
     __syncthreads();
@@ -97,11 +98,20 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
       gi[k] = g.y;
     }
     const float szero = (float)W;
+    const int wmask = window_mask(W);
 
-    for (int p0 = pr.lo; p0 <= pr.hi; p0 += CP) {
-      const int cp = min(CP, pr.hi - p0 + 1);
-      __syncthreads();
-      prepare_chunk<NT, TX, LY, LZ, GATE, DT>(lds, ws, sw, c, C, p0, cp, x0, y0, z0, Ld, tid, lane, wave);
+    const Geo geo = geo_for(ws, sw, ROWS, GATE);
+    int* lpart = reinterpret_cast<int*>(lds + Ld.off_win);   // window area, free between chunks
+
+    for (int P0 = pr.lo; P0 <= pr.hi; P0 += sw.SC) {
+     const int sc = min(sw.SC, pr.hi - P0 + 1);
+     __syncthreads();
+     build_geometry<NT, TX, LY, LZ, GATE>(geo, lpart, &s_npart, ws, sw, c, C, P0, sc, x0, y0, z0, tid);
+     for (int off = 0; off < sc; off += CP) {
+      const int cp = min(CP, sc - off);
+      const int p0 = P0 + off;
+      if (off > 0) __syncthreads();
+      load_chunk<NT, ROWS, GATE, DT>(lds, geo, sw, P0, off, cp, Ld, tid, lane, wave);
       for (int slot = 0; slot < cp; ++slot) {
         const TxRec tr = ltx[slot];
         const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
@@ -143,14 +153,12 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
                 const bool in = (unsigned)(da + LX * k) <= (unsigned)span;
                 sidx = in ? sidx : szero;
               }
-              sidx = __builtin_amdgcn_fmed3f(sidx, 0.0f, szero);
-              const int n = (int)sidx;
-              const float w = __builtin_amdgcn_fractf(sidx);
+              const WinIdx wi = window_index(sidx, wmask);
               const float sn = __builtin_amdgcn_sinf(cyc);
               const float cs = __builtin_amdgcn_cosf(cyc);
-              const float4 v = win[n];
+              const float4 v = win[wi.idx];
               const float dar = v.z, dai = v.w;
-              const float Lr = fmaf(w, dar, v.x), Li = fmaf(w, dai, v.y);
+              const float Lr = fmaf(wi.w, dar, v.x), Li = fmaf(wi.w, dai, v.y);
               const float Xr = fmaf(fsf, dar, -tpf * Li);
               const float Xi = fmaf(fsf, dai, tpf * Lr);
               const float Dr = fmaf(Xr, cs, -Xi * sn);
@@ -223,6 +231,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
         }
         out[7] = 0.0;
       }
+     }
     }
   }
 }

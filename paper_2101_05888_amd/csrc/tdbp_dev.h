@@ -46,6 +46,7 @@ struct SwathDev {
   int tile0;              // index of this swath's first tile in the global tile list
   int W;                  // LDS window length per (ping, element), samples (without guard)
   int CP;                 // pings staged per pass
+  int SC;                 // pings whose geometry is built at once (a multiple of CP)
   double o[3], d[3];
   double fc, fs, t0;
   double tan_g, sin_g;    // gate: tan and sin of the half-angle (0 = off)
@@ -71,7 +72,33 @@ struct Workspace {
   double* partials;       // adjoint: kPartial doubles per (tile, ping, element), allocated on first use
   double* cpart;          // adjoint: per-(swath, ping) sound-speed partials
   double* scratch64;      // sharpness partial sums, counters
+  unsigned char* geo;     // per-workgroup geometry of SC pings: geo + blockIdx.x * geo_stride
+  long long geo_stride;   // bytes per workgroup
 };
+
+// Geometry of a run of SC pings of one tile, built once per run by the whole
+// workgroup and then copied chunk by chunk into LDS (bytes from the start of
+// the workgroup's region):
+//   receiver records [SC][E] (48 B)   window starts [SC][E] (int)
+//   transmitter records [SC] (32 B)   gate rows [SC][E][ROWS] (int, gate only)
+constexpr int kRxRecBytes = 48;
+constexpr int kTxRecBytes = 32;
+
+struct GeoLayout {
+  long long rec, n0, tx, rows, bytes;
+};
+
+__host__ __device__ inline GeoLayout geo_layout(int SC, int E, int ROWS, bool gate) {
+  GeoLayout g;
+  long long o = 0;
+  g.rec = o;  o += (long long)SC * E * kRxRecBytes;
+  g.n0 = o;   o += (long long)SC * E * 4;
+  o = (o + 15) & ~15ll;
+  g.tx = o;   o += (long long)SC * kTxRecBytes;
+  g.rows = o; o += gate ? (long long)SC * E * ROWS * 4 : 0;
+  g.bytes = (o + 255) & ~255ll;
+  return g;
+}
 
 constexpr int kBuckets = 64;
 constexpr int kPartial = 8;   // gR.xyz, gc, gT.xyz (element 0 only), pad

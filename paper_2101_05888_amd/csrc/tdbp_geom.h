@@ -23,7 +23,7 @@ namespace sasbp {
 
 // Receiver record per (ping, element), 12 floats = three 16-byte LDS reads:
 //   q0: 2 u_R (x, y, z), flags
-//   q1: s0 = reference delay in samples from the window start,
+//   q1: s0 - 1/2, s0 = reference delay in samples from the window start,
 //       phi0 = frac(f_c tau_ref) in cycles, a5, d0_R
 //   q2: a1..a4
 // with Delta_R ~= num (a1 + num (a2 + num (a3 + num (a4 + num a5)))).
@@ -93,11 +93,9 @@ __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c,
   double nstart = floor(uref - span) - 2.0;
   if (!(nstart > -1.0e9)) nstart = -1.0e9;          // also maps NaN to a harmless value
   if (nstart > 1.0e9) nstart = 1.0e9;
-  // window start on a multiple of the samples per 16-byte load (2 complex
-  // FP32 samples, 4 complex 16-bit samples) so that staging loads are aligned
-  const int spl = sw.dtype == 0 ? 2 : 4;
+  // window start even: staging loads two samples per lane, aligned
   int n0 = (int)nstart;
-  n0 -= ((n0 % spl) + spl) % spl;
+  n0 -= n0 & 1;
   const double cyc = sw.fc * tau;
   unsigned flags = ok ? 0u : kFlagSkip;
   // series bound over the tile: |num| <= 2 d0 r + r^2, remainder of
@@ -116,7 +114,7 @@ __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c,
     a5 = (7.0 / 256.0) * i1 * i2 * i2 * i2 * i2;
   }
   rec->q0 = make_float4((float)(2.0 * uR0), (float)(2.0 * uR1), (float)(2.0 * uR2), __uint_as_float(flags));
-  rec->q1 = make_float4((float)(uref - (double)n0), (float)(cyc - floor(cyc)), (float)a5, (float)d0R);
+  rec->q1 = make_float4((float)(uref - (double)n0 - 0.5), (float)(cyc - floor(cyc)), (float)a5, (float)d0R);
   rec->q2 = make_float4((float)a1, (float)a2, (float)a3, (float)a4);
   *n0_out = n0;
   return ok;
@@ -158,6 +156,24 @@ __device__ __forceinline__ int gate_row(const SwathDev& sw, int p, int e, double
 __device__ __forceinline__ int row_lo(int v) { return (int)(short)(v & 0xffff); }
 __device__ __forceinline__ int row_hi(int v) { return v >> 16; }
 
+// Rounded window index and weight of a sample position with only FP32 adds:
+// adding 2^23 rounds sh = s - 1/2 to an integer n held in the low mantissa
+// bits of t; w = sh - n. The masked bit pattern of t is the index.
+constexpr float kRoundMagic = 8388608.0f;
+
+struct WinIdx {
+  int idx;
+  float w;
+};
+
+__device__ __forceinline__ WinIdx window_index(float sh, int mask) {
+  const float t = sh + kRoundMagic;
+  WinIdx r;
+  r.w = sh - (t - kRoundMagic);
+  r.idx = (int)(__float_as_uint(t) & (unsigned)mask);
+  return r;
+}
+
 // Echo sample loaders: FP32 complex out of each storage type.
 __device__ __forceinline__ float2 load_sample(const void* base, size_t idx, int dtype, float scale) {
   if (dtype == 0) {
@@ -174,9 +190,20 @@ __device__ __forceinline__ float2 load_sample(const void* base, size_t idx, int 
 
 // LDS layout for a chunk of CP pings with E elements and window length W:
 //   TxRec tx[CP]   RxRec rx[CP][E]   int n0[CP][E]   int rows[CP][E][ROWS] (gate only)
-//   float4 win[CP][E][W+1]: {E[n], E[n+1] - E[n]} for n < W, entry W all zero
-// (interpolation is then one 16-byte read and two FMAs; gated-out pixels read
-// the zero entry).
+//   float4 win[CP][E][W+1]: {(E[n] + E[n+1]) / 2, E[n+1] - E[n]} for n < W,
+//   entry W all zero; then a tail pad up to the next power of two.
+// Interpolation at sample position s is then one 16-byte read and two FMAs:
+// with n = round(s - 1/2) and w = (s - 1/2) - n in [-1/2, 1/2],
+//   (1 - frac s) E[floor s] + frac(s) E[floor s + 1] = mid[n] + w diff[n]
+// (a tie, s an integer rounded down to n = s - 1, gives w = 1/2 and the same
+// value). Gated-out pixels read the zero entry. Indices are masked to
+// window_mask(W), so no read can leave the allocation.
+__host__ __device__ inline int window_mask(int W) {
+  int m = 1;
+  while (m < W + 1) m <<= 1;
+  return m - 1;
+}
+
 struct LdsLayout {
   int off_tx, off_rx, off_n0, off_rows, off_win, bytes;
 };
@@ -187,27 +214,62 @@ __host__ __device__ inline LdsLayout lds_layout(int CP, int E, int W, int ROWS, 
   L.off_tx = o;   o += CP * (int)sizeof(TxRec);
   L.off_rx = o;   o += CP * E * (int)sizeof(RxRec);
   L.off_n0 = o;   o += CP * E * 4;
+  o = (o + 15) & ~15;
   L.off_rows = o; o += gate ? CP * E * ROWS * 4 : 0;
   o = (o + 15) & ~15;
-  L.off_win = o;  o += CP * E * (W + 1) * 16;
+  L.off_win = o;  o += (CP * E * (W + 1) + (window_mask(W) - W)) * 16;
   L.bytes = o;
   return L;
 }
 
-// FP64 receiver records and gate classes of one chunk (threads stride over
-// the (ping, element) pairs).
-template <int NT>
-__device__ __forceinline__ void build_records(RxRec* lrx, int* ln0, const Workspace& ws, const SwathDev& sw,
-                                                        double c, const double* C, int p0, int cp, int tid,
-                                                        bool gate_on, double bx0, double bx1, double by0,
-                                                        double by1, double bz0, double bz1) {
+static_assert(sizeof(RxRec) == kRxRecBytes, "receiver record size");
+static_assert(sizeof(TxRec) == kTxRecBytes, "transmitter record size");
+
+// This workgroup's geometry region (see geo_layout).
+struct Geo {
+  RxRec* rec;
+  int* n0;
+  TxRec* tx;
+  int* rows;
+};
+
+__device__ __forceinline__ Geo geo_for(const Workspace& ws, const SwathDev& sw, int ROWS, bool gate) {
+  const GeoLayout gl = geo_layout(sw.SC, sw.E, ROWS, gate);
+  unsigned char* base = ws.geo + (size_t)blockIdx.x * (size_t)ws.geo_stride;
+  Geo g;
+  g.rec = reinterpret_cast<RxRec*>(base + gl.rec);
+  g.n0 = reinterpret_cast<int*>(base + gl.n0);
+  g.tx = reinterpret_cast<TxRec*>(base + gl.tx);
+  g.rows = reinterpret_cast<int*>(base + gl.rows);
+  return g;
+}
+
+// FP64 geometry of pings [P0, P0 + sc) of the tile whose first pixel is
+// (x0, y0, z0): receiver and transmitter records, window starts, gate classes
+// and, for every partially gated (ping, element), the exact gate interval of
+// each pixel row. Built by the whole workgroup into its geometry region, so
+// that the long FP64 dependency chains of many records overlap; the list of
+// partial records is kept in LDS scratch (lpart, *lnpart) that the caller
+// lends (the window area, unused between chunks). Ends with a barrier.
+template <int NT, int TX, int LY, int LZ, bool GATE>
+__device__ __forceinline__ void build_geometry(const Geo& g, int* lpart, int* lnpart, const Workspace& ws,
+                                               const SwathDev& sw, double c, const double* C, int P0, int sc,
+                                               int x0, int y0, int z0, int tid) {
+  constexpr int ROWS = LY * LZ;
   const int E = sw.E;
+  const bool gate_on = GATE && sw.tan_g > 0.0;
   const double tan2 = sw.tan_g * sw.tan_g;
   const double inv_c = 1.0 / c;
+  // pixel-centre box of the tile
+  const double bx0 = sw.o[0] + (double)x0 * sw.d[0], bx1 = bx0 + (double)(TX - 1) * sw.d[0];
+  const double by0 = sw.o[1] + (double)y0 * sw.d[1], by1 = by0 + (double)(LY - 1) * sw.d[1];
+  const double bz0 = sw.o[2] + (double)z0 * sw.d[2], bz1 = bz0 + (double)(LZ - 1) * sw.d[2];
+  if (tid == 0) *lnpart = 0;
+  __syncthreads();
 #pragma unroll 1
-  for (int r = tid; r < cp * E; r += NT) {
+  for (int r = tid; r < sc * E; r += NT) {
     const int slot = r / E, e = r - slot * E;
-    const int p = p0 + slot;
+    const int p = P0 + slot;
     RxRec rec;
     int n0;
     if (!make_rx_record(sw, inv_c, C, p, e, &rec, &n0)) atomicOr(&ws.counters[1], kStatusNav);
@@ -221,34 +283,63 @@ __device__ __forceinline__ void build_records(RxRec* lrx, int* ln0, const Worksp
       const int gr = gt == kGateOut ? kGateOut : gate_class(tan2, R[0], R[1], R[2], bx0, bx1, by0, by1, bz0, bz1);
       if (gt == kGateOut || gr == kGateOut) f |= kFlagSkip;
       else if (gt == kGateIn && gr == kGateIn) f |= kFlagFull;
+      if (!(f & (kFlagSkip | kFlagFull))) lpart[atomicAdd(lnpart, 1)] = r;
     }
     rec.q0.w = __uint_as_float(f);
-    lrx[r] = rec;
-    ln0[r] = n0;
+    g.rec[r] = rec;
+    g.n0[r] = n0;
   }
+#pragma unroll 1
+  for (int s = tid; s < sc; s += NT) make_tx_record(sw, C, P0 + s, &g.tx[s]);
+  __syncthreads();
+  if (gate_on) {
+    const int np = *lnpart;
+#pragma unroll 1
+    for (int q = tid; q < np * ROWS; q += NT) {
+      const int r = lpart[q / ROWS], rr = q % ROWS;
+      const int slot = r / E, e = r - slot * E;
+      const int ry = rr % LY, rz = rr / LY;
+      const double y = sw.o[1] + (double)(y0 + ry) * sw.d[1];
+      const double z = sw.o[2] + (double)(z0 + rz) * sw.d[2];
+      g.rows[r * ROWS + rr] = gate_row(sw, P0 + slot, e, y, z, x0, TX);
+    }
+  }
+  __syncthreads();
 }
 
 
-// Samples of one 16-byte load: 2 complex FP32 samples, or 4 complex 16-bit
-// samples dequantised with the ping's scale.
+// Two consecutive complex samples from one load (16 bytes of FP32, or 8 bytes
+// of 16-bit values dequantised with the ping's scale).
 template <int DT>
-__device__ __forceinline__ void unpack16(const uint4 q, float scale, float2* s) {
-  if (DT == 0) {
-    s[0] = make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
-    s[1] = make_float2(__uint_as_float(q.z), __uint_as_float(q.w));
-  } else if (DT == 1) {
-    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-    const unsigned w[4] = {q.x, q.y, q.z, q.w};
+struct PairLoad {
+  typedef uint4 type;
+};
+template <>
+struct PairLoad<1> {
+  typedef uint2 type;
+};
+template <>
+struct PairLoad<2> {
+  typedef uint2 type;
+};
+
+__device__ __forceinline__ void unpack_pair(const uint4 q, float, float2* s) {
+  s[0] = make_float2(__uint_as_float(q.x), __uint_as_float(q.y));
+  s[1] = make_float2(__uint_as_float(q.z), __uint_as_float(q.w));
+}
+
+template <int DT>
+__device__ __forceinline__ void unpack_pair16(const uint2 q, float scale, float2* s) {
+  const unsigned w[2] = {q.x, q.y};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 2; ++i) {
+    if (DT == 1) {
+      typedef _Float16 h2 __attribute__((ext_vector_type(2)));
       const h2 v = __builtin_bit_cast(h2, w[i]);
       s[i] = make_float2((float)v.x * scale, (float)v.y * scale);
-    }
-  } else {
-    const unsigned w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
+    } else {
       s[i] = make_float2(__uint_as_float(w[i] << 16) * scale, __uint_as_float(w[i] & 0xffff0000u) * scale);
+    }
   }
 }
 
@@ -257,27 +348,28 @@ __device__ __forceinline__ float2 load_guarded(const SwathDev& sw, size_t rowbas
   return load_sample(sw.echo, rowbase + (size_t)n, dt, scale);
 }
 
-// Echo windows of a chunk into LDS. Entry k of window r holds E[n0+k] and
-// E[n0+k+1] - E[n0+k] (k < W); entry W is zero. Work is split into jobs of
+// Echo windows of a chunk into LDS. Entry k of window r holds the midpoint
+// and the difference of E[n0+k] and E[n0+k+1] (k < W); entry W is zero. Work is split into jobs of
 // 64 lanes x one 16-byte load each; every wave issues the loads of B jobs
 // before consuming any, and takes E[n+1] for its last sample from the next
 // lane. Samples outside the record read as zero.
 template <int NT, int DT>
 __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, const int* ln0, const SwathDev& sw,
                                               int p0, int cp, int tid, int lane, int wave) {
+  typedef typename PairLoad<DT>::type LoadT;
   constexpr int NW = NT / 64;
-  constexpr int SPL = DT == 0 ? 2 : 4;      // samples per lane per load
+  constexpr int SPL = 2;                    // samples per lane per load
   constexpr int JS = 64 * SPL;              // samples per job
   constexpr int B = 8;                      // jobs in flight per wave
+  constexpr int SB = DT == 0 ? 8 : 4;       // bytes per sample
   const int E = sw.E, W = sw.W;
   const int J = (W + JS) / JS;              // jobs per window (samples 0..W)
   const int njobs = cp * E * J;
   const bool aligned = (sw.Ns % SPL) == 0;
   const char* echo = reinterpret_cast<const char*>(sw.echo);
-  constexpr int SB = DT == 0 ? 8 : 4;       // bytes per sample
 #pragma unroll 1
   for (int j0 = wave; j0 < njobs; j0 += NW * B) {
-    uint4 q[B];
+    LoadT q[B];
     float2 tail[B];                         // lane 63: the sample after the job
     bool fast[B];
     // issue every load of the batch before using any
@@ -295,7 +387,7 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
       const size_t rowbase = ((size_t)p * E + e) * (size_t)sw.Ns;
       if (aligned && first >= 0 && first + JS < sw.Ns) {
         fast[b] = true;
-        q[b] = *reinterpret_cast<const uint4*>(echo + (rowbase + (size_t)(first + SPL * lane)) * SB);
+        q[b] = *reinterpret_cast<const LoadT*>(echo + (rowbase + (size_t)(first + SPL * lane)) * SB);
         if (lane == 63) tail[b] = load_sample(sw.echo, rowbase + (size_t)(first + JS), DT, 1.0f);
       }
     }
@@ -313,7 +405,8 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
       const int n = ln0[r] + k0;
       float2 s[SPL + 1];
       if (fast[b]) {
-        unpack16<DT>(q[b], scale, s);
+        if constexpr (DT == 0) unpack_pair(q[b], scale, s);
+        else unpack_pair16<DT>(q[b], scale, s);
       } else {
 #pragma unroll
         for (int i = 0; i < SPL; ++i) s[i] = load_guarded(sw, rowbase, n + i, DT, scale);
@@ -328,54 +421,42 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
         const int k = k0 + i;
-        if (k < W) dst[k] = make_float4(s[i].x, s[i].y, s[i + 1].x - s[i].x, s[i + 1].y - s[i].y);
+        if (k < W) {
+          const float dr = s[i + 1].x - s[i].x, di = s[i + 1].y - s[i].y;
+          dst[k] = make_float4(fmaf(0.5f, dr, s[i].x), fmaf(0.5f, di, s[i].y), dr, di);
+        }
       }
     }
   }
   for (int r = tid; r < cp * E; r += NT) lwin[(size_t)r * (W + 1) + W] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// Steps 1-2 of a chunk of pings, shared by the image and adjoint kernels:
-// FP64 records, gate classes and exact rows of partial records, then the echo
-// windows in LDS. Ends with a barrier; the caller must have passed a barrier
-// since the previous chunk's last read of LDS.
-template <int NT, int TX, int LY, int LZ, bool GATE, int DT>
-__device__ __forceinline__ void prepare_chunk(unsigned char* lds, const Workspace& ws, const SwathDev& sw, double c,
-                                              const double C[3], int p0, int cp, int x0, int y0, int z0,
-                                              const LdsLayout& L, int tid, int lane, int wave) {
-  constexpr int ROWS = LY * LZ;
-  const int E = sw.E, W = sw.W;
+// One chunk of cp pings, [P0 + off, P0 + off + cp), of a run whose geometry
+// is in g: records, window starts and gate rows into LDS, then the echo
+// windows. Ends with a barrier.
+template <int NT, int ROWS, bool GATE, int DT>
+__device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, const SwathDev& sw, int P0, int off,
+                                           int cp, const LdsLayout& L, int tid, int lane, int wave) {
+  const int E = sw.E;
   TxRec* ltx = reinterpret_cast<TxRec*>(lds + L.off_tx);
   RxRec* lrx = reinterpret_cast<RxRec*>(lds + L.off_rx);
   int* ln0 = reinterpret_cast<int*>(lds + L.off_n0);
-  int* lrows = reinterpret_cast<int*>(lds + L.off_rows);
   float4* lwin = reinterpret_cast<float4*>(lds + L.off_win);
-  const bool gate_on = GATE && sw.tan_g > 0.0;
-  // pixel-centre box of the tile (uniform)
-  const double bx0 = sw.o[0] + (double)x0 * sw.d[0], bx1 = bx0 + (double)(TX - 1) * sw.d[0];
-  const double by0 = sw.o[1] + (double)y0 * sw.d[1], by1 = by0 + (double)(LY - 1) * sw.d[1];
-  const double bz0 = sw.o[2] + (double)z0 * sw.d[2], bz1 = bz0 + (double)(LZ - 1) * sw.d[2];
-  // 1. FP64 records and gate classes
-  build_records<NT>(lrx, ln0, ws, sw, c, C, p0, cp, tid, gate_on, bx0, bx1, by0, by1, bz0, bz1);
-#pragma unroll 1
-  for (int r = tid; r < cp; r += NT) make_tx_record(sw, C, p0 + r, &ltx[r]);
-  __syncthreads();
-  if (gate_on) {
-    // exact rows of the partial records
-#pragma unroll 1
-    for (int q = tid; q < cp * E * ROWS; q += NT) {
-      const int pe = q / ROWS, rr = q - pe * ROWS;
-      const unsigned f = __float_as_uint(lrx[pe].q0.w);
-      if (f & (kFlagSkip | kFlagFull)) continue;
-      const int slot = pe / E, e = pe - slot * E;
-      const int ry = rr % LY, rz = rr / LY;
-      const double y = sw.o[1] + (double)(y0 + ry) * sw.d[1];
-      const double z = sw.o[2] + (double)(z0 + rz) * sw.d[2];
-      lrows[q] = gate_row(sw, p0 + slot, e, y, z, x0, TX);
-    }
+  const RxRec* grec = g.rec + (size_t)off * E;
+  const int* gn0 = g.n0 + (size_t)off * E;
+  for (int r = tid; r < cp * E; r += NT) {
+    lrx[r] = grec[r];
+    ln0[r] = gn0[r];
   }
-  // 2. echo windows -> LDS
-  stage_windows<NT, DT>(lwin, lrx, ln0, sw, p0, cp, tid, lane, wave);
+  for (int s = tid; s < cp; s += NT) ltx[s] = g.tx[off + s];
+  if (GATE && sw.tan_g > 0.0) {
+    // rows of records that are not partial hold stale values and are never read
+    const int4* src = reinterpret_cast<const int4*>(g.rows + (size_t)off * E * ROWS);
+    int4* dst = reinterpret_cast<int4*>(lds + L.off_rows);
+    for (int q = tid; q < cp * E * (ROWS / 4); q += NT) dst[q] = src[q];
+  }
+  __syncthreads();
+  stage_windows<NT, DT>(lwin, lrx, ln0, sw, P0 + off, cp, tid, lane, wave);
   __syncthreads();
 }
 

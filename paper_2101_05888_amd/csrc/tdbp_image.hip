@@ -7,10 +7,12 @@
 // Pixels are independent (Sec. II-A), so tiles need no atomics and any
 // processing order gives bitwise identical images.
 //
-// Per chunk of pings the workgroup
-//   1. forms the FP64 reference geometry of every (ping, element) and, with a
-//      beam gate, the exact per-row gate intervals (Sec. II-C; transmitter and
-//      receiver tested separately as in the bistatic case, Sec. III-B);
+// For each run of pings of its tile the workgroup forms, all threads at once,
+// the FP64 reference geometry of every (ping, element) and, with a beam gate,
+// the exact per-row gate intervals (Sec. II-C; transmitter and receiver
+// tested separately as in the bistatic case, Sec. III-B), into its own
+// region of the workspace. Then, per chunk of pings of the run, it
+//   1. copies the chunk's records and gate rows into LDS;
 //   2. copies each (ping, element)'s echo window into LDS with coalesced loads,
 //      zero-filling samples outside the record and converting FP16/BF16
 //      storage to FP32;
@@ -129,7 +131,8 @@ __global__ __launch_bounds__(kThreads) void order_kernel(Workspace ws, int n_til
 template <int K, int LX, bool POLY, bool TEST>
 __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __restrict__ win, const float* dx,
                                            const float* dsq, const float* dT, float dyl, float dzl, float fs_c,
-                                           float fc_c, float szero, int da, int span, float* accr, float* acci) {
+                                           float fc_c, float szero, int wmask, int da, int span, float* accr,
+                                           float* acci) {
   const float ryz = fmaf(rec.q0.y, dyl, rec.q0.z * dzl);
   const float d0 = rec.q1.w;
   const float d0sq = d0 * d0;
@@ -149,18 +152,23 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
       const float sq = __builtin_amdgcn_sqrtf(d0sq + num);
       D = fmaf(num, __builtin_amdgcn_rcpf(d0 + sq), dT[k]);
     }
-    float si = fmaf(D, fs_c, rec.q1.x);
-    cyc[k] = fmaf(D, fc_c, rec.q1.y);   // the hardware sin/cos take revolutions
+    float si = fmaf(D, fs_c, rec.q1.x);   // sample position - 1/2 in the window
+    cyc[k] = fmaf(D, fc_c, rec.q1.y);     // the hardware sin/cos take revolutions
     if (TEST) {
       const bool in = (unsigned)(da + LX * k) <= (unsigned)span;
       si = in ? si : szero;
     }
-    sidx[k] = __builtin_amdgcn_fmed3f(si, 0.0f, szero);
+    sidx[k] = si;
   }
   // phase 2: every window read in flight at once
   float4 v[K];
+  float wt[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = win[(int)sidx[k]];
+  for (int k = 0; k < K; ++k) {
+    const WinIdx wi = window_index(sidx[k], wmask);
+    wt[k] = wi.w;
+    v[k] = win[wi.idx];
+  }
   // phase 3: carrier phasors while the reads land
   float sn[K], cs[K];
 #pragma unroll
@@ -171,9 +179,8 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
   // phase 4: interpolate and accumulate
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float w = __builtin_amdgcn_fractf(sidx[k]);
-    const float vr = fmaf(w, v[k].z, v[k].x);
-    const float vi = fmaf(w, v[k].w, v[k].y);
+    const float vr = fmaf(wt[k], v[k].z, v[k].x);
+    const float vi = fmaf(wt[k], v[k].w, v[k].y);
     accr[k] = fmaf(vr, cs[k], accr[k]);
     accr[k] = fmaf(-vi, sn[k], accr[k]);
     acci[k] = fmaf(vr, sn[k], acci[k]);
@@ -196,6 +203,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
   const int lx = tid % LX, ly = (tid / LX) % LY, lz = tid / (LX * LY);
   const int row = ly + LY * lz;
   __shared__ int s_item;
+  __shared__ int s_npart;
 
   for (;;) {
     __syncthreads();
@@ -238,11 +246,19 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
 #pragma unroll
     for (int k = 0; k < K; ++k) { accr[k] = 0.0f; acci[k] = 0.0f; }
     const float szero = (float)W;   // the window's all-zero entry
+    const int wmask = window_mask(W);
 
-    for (int p0 = pr.lo; p0 <= pr.hi; p0 += CP) {
-      const int cp = min(CP, pr.hi - p0 + 1);
+    const Geo geo = geo_for(ws, sw, ROWS, GATE);
+    int* lpart = reinterpret_cast<int*>(lds + Ld.off_win);   // window area, free between chunks
+
+    for (int P0 = pr.lo; P0 <= pr.hi; P0 += sw.SC) {
+      const int sc = min(sw.SC, pr.hi - P0 + 1);
       __syncthreads();
-      prepare_chunk<NT, TX, LY, LZ, GATE, DT>(lds, ws, sw, c, C, p0, cp, x0, y0, z0, Ld, tid, lane, wave);
+      build_geometry<NT, TX, LY, LZ, GATE>(geo, lpart, &s_npart, ws, sw, c, C, P0, sc, x0, y0, z0, tid);
+     for (int off = 0; off < sc; off += CP) {
+      const int cp = min(CP, sc - off);
+      if (off > 0) __syncthreads();
+      load_chunk<NT, ROWS, GATE, DT>(lds, geo, sw, P0, off, cp, Ld, tid, lane, wave);
       for (int slot = 0; slot < cp; ++slot) {
         const TxRec tr = ltx[slot];
         const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
@@ -261,21 +277,22 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
           const float4* win = lwin + (size_t)r * (W + 1);
           if (!GATE || (f & kFlagFull)) {
             if (f & kFlagPoly)
-              accumulate<K, LX, true, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
+              accumulate<K, LX, true, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, wmask, 0, 0, accr, acci);
             else
-              accumulate<K, LX, false, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
+              accumulate<K, LX, false, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, wmask, 0, 0, accr, acci);
           } else {
             const int v = lrows[r * ROWS + row];
             const int a = row_lo(v), b = row_hi(v);
             if (f & kFlagPoly)
-              accumulate<K, LX, true, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a,
+              accumulate<K, LX, true, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, wmask, lx - a, b - a,
                                             accr, acci);
             else
-              accumulate<K, LX, false, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a,
+              accumulate<K, LX, false, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, wmask, lx - a, b - a,
                                              accr, acci);
           }
         }
       }
+     }
     }
     // write the tile once
     const int iy = y0 + ly, iz = z0 + lz;

@@ -107,6 +107,22 @@ def test_graph_replay_equals_direct_launch_and_is_deterministic(api):
         assert np.array_equal(buf.image.cpu().numpy(), a)
 
 
+def test_kernel_timing_brackets_each_launch(api):
+    scn, echo = _case("c1", n_ping=12, n_elem=4, nx=64, ny=48)
+    ref, plan, buf = gpu_image(api, scn, echo)
+    api.sas_bp_set_kernel_timing(plan, True)
+    for _ in range(3):
+        buf.image.fill_(0)
+        api.sas_bp_image(plan, [buf])
+    ms, n = api.sas_bp_kernel_time(plan)
+    assert n == 3 and ms > 0.0
+    assert np.array_equal(buf.image.cpu().numpy(), ref)     # direct launches, same bits
+    assert api.sas_bp_kernel_time(plan) == (0.0, 0)         # the read starts a new count
+    api.sas_bp_set_kernel_timing(plan, False)
+    api.sas_bp_image(plan, [buf])
+    assert api.sas_bp_kernel_time(plan) == (0.0, 0)         # graph replays are not timed
+
+
 def test_graph_sees_new_navigation_and_sound_speed(api):
     scn, echo = _case("c1", n_ping=12, n_elem=4, nx=48, ny=40)
     img, plan, buf = gpu_image(api, scn, echo)
