@@ -21,6 +21,7 @@ on the host cores on a bounded pixel sample).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -34,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3           # MI355X FP32 vector peak (256 CU x 2.4 GHz)
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "image_kernel_operational_swath_counters.txt")
 METRIC = "pixel·ping·element updates/s; mixed vs FP32 at ≤1e-4 rel-L2 vs FP64 oracle"
 
 
@@ -46,6 +48,35 @@ def flops_per_update(n_elem: int) -> float:
     (2): 32, plus the transmitter leg d_T (9) shared by the E elements.
     """
     return 32.0 + 9.0 / n_elem
+
+
+def kernel_sources_digest() -> str:
+    """SHA-256 over the HIP sources, to tell whether counters still describe the kernel."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2101_05888_amd", "csrc")
+    for fn in sorted(os.listdir(d)):
+        if fn.endswith((".hip", ".h")):
+            h.update(fn.encode())
+            with open(os.path.join(d, fn), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per image-kernel launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by the copy calibration), or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            kv = dict(l.split(":", 1) for l in f.read().splitlines() if ":" in l and not l.startswith(" "))
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256", "").strip() != kernel_sources_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg: str) -> None:
@@ -179,7 +210,7 @@ def main() -> int:
         print(json.dumps({"error": "no HIP device visible"}), flush=True)
         return 3
     if args.profile:
-        args.no_cpu_baseline = args.no_autofocus = args.no_batched = True
+        args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -253,7 +284,7 @@ def main() -> int:
         "graph_ms_per_step": graph_ms,
         "image_kernel_ms": kernel_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_update": fpu, "kernel": "image_kernel", "launch_ms": kernel_ms,
                      "updates_per_launch": int(useful)},
     }

@@ -349,81 +349,82 @@ __device__ __forceinline__ float2 load_guarded(const SwathDev& sw, size_t rowbas
 }
 
 // Echo windows of a chunk into LDS. Entry k of window r holds the midpoint
-// and the difference of E[n0+k] and E[n0+k+1] (k < W); entry W is zero. Work is split into jobs of
-// 64 lanes x one 16-byte load each; every wave issues the loads of B jobs
-// before consuming any, and takes E[n+1] for its last sample from the next
-// lane. Samples outside the record read as zero.
+// and the difference of E[n0+k] and E[n0+k+1] (k < W); entry W is zero.
+// Each wave takes B windows (rows r = (ping, element) of the chunk) at a
+// time and, per part of JS = 128 samples, issues the loads of all B rows
+// before consuming any: a lane loads two consecutive samples and takes the
+// sample after them from the next lane (lane 63 loads it itself). Row
+// bookkeeping is wave-uniform and stays in scalar registers. Samples outside
+// the record read as zero.
 template <int NT, int DT>
 __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, const int* ln0, const SwathDev& sw,
-                                              int p0, int cp, int tid, int lane, int wave) {
+                                              int p0, int cp, int tid, int lane, int wave_id) {
   typedef typename PairLoad<DT>::type LoadT;
   constexpr int NW = NT / 64;
   constexpr int SPL = 2;                    // samples per lane per load
-  constexpr int JS = 64 * SPL;              // samples per job
-  constexpr int B = 8;                      // jobs in flight per wave
+  constexpr int JS = 64 * SPL;              // samples per part
+  constexpr int B = 8;                      // rows in flight per wave
   constexpr int SB = DT == 0 ? 8 : 4;       // bytes per sample
-  const int E = sw.E, W = sw.W;
-  const int J = (W + JS) / JS;              // jobs per window (samples 0..W)
-  const int njobs = cp * E * J;
-  const bool aligned = (sw.Ns % SPL) == 0;
+  const int wave = __builtin_amdgcn_readfirstlane(wave_id);
+  const int E = sw.E, W = sw.W, Ns = sw.Ns;
+  const int J = (W + JS) / JS;              // parts per window (samples 0..W)
+  const int nrows = cp * E;
+  const bool aligned = (Ns % SPL) == 0;
   const char* echo = reinterpret_cast<const char*>(sw.echo);
+  const int lane_off = SPL * lane;
 #pragma unroll 1
-  for (int j0 = wave; j0 < njobs; j0 += NW * B) {
-    LoadT q[B];
-    float2 tail[B];                         // lane 63: the sample after the job
-    bool fast[B];
-    // issue every load of the batch before using any
+  for (int r0 = wave * B; r0 < nrows; r0 += NW * B) {
+#pragma unroll 1
+    for (int part = 0; part < J; ++part) {
+      LoadT q[B];
+      float2 tail[B];                       // lane 63: the sample after the part
+      int first[B];                         // sample index of the part's first lane (uniform)
+      unsigned live = 0u, fast = 0u;        // per-row bits (uniform)
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int j = j0 + b * NW;
-      fast[b] = false;
-      tail[b] = make_float2(0.0f, 0.0f);
-      if (j >= njobs) continue;
-      const int r = j / J, part = j - r * J;
-      if (__float_as_uint(lrx[r].q0.w) & kFlagSkip) continue;
-      const int slot = r / E, e = r - slot * E;
-      const int p = p0 + slot;
-      const int first = ln0[r] + part * JS;       // sample index of the job's first lane
-      const size_t rowbase = ((size_t)p * E + e) * (size_t)sw.Ns;
-      if (aligned && first >= 0 && first + JS < sw.Ns) {
-        fast[b] = true;
-        q[b] = *reinterpret_cast<const LoadT*>(echo + (rowbase + (size_t)(first + SPL * lane)) * SB);
-        if (lane == 63) tail[b] = load_sample(sw.echo, rowbase + (size_t)(first + JS), DT, 1.0f);
+      for (int b = 0; b < B; ++b) {
+        const int r = r0 + b;
+        tail[b] = make_float2(0.0f, 0.0f);
+        first[b] = 0;
+        if (r >= nrows) continue;
+        const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(lrx[r].q0.w));
+        if (f & kFlagSkip) continue;
+        live |= 1u << b;
+        first[b] = __builtin_amdgcn_readfirstlane(ln0[r]) + part * JS;
+        if (aligned && first[b] >= 0 && first[b] + JS < Ns) {
+          fast |= 1u << b;
+          const size_t row = ((size_t)p0 * E + r) * (size_t)Ns + (size_t)first[b];
+          q[b] = *reinterpret_cast<const LoadT*>(echo + (row + lane_off) * SB);
+          if (lane == 63) tail[b] = load_sample(sw.echo, row + JS, DT, 1.0f);
+        }
       }
-    }
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int j = j0 + b * NW;
-      if (j >= njobs) continue;
-      const int r = j / J, part = j - r * J;
-      if (__float_as_uint(lrx[r].q0.w) & kFlagSkip) continue;
-      const int slot = r / E, e = r - slot * E;
-      const int p = p0 + slot;
-      const size_t rowbase = ((size_t)p * E + e) * (size_t)sw.Ns;
-      const float scale = DT == 0 ? 1.0f : sw.scale[p];
-      const int k0 = part * JS + SPL * lane;      // window index of this lane's first sample
-      const int n = ln0[r] + k0;
-      float2 s[SPL + 1];
-      if (fast[b]) {
-        if constexpr (DT == 0) unpack_pair(q[b], scale, s);
-        else unpack_pair16<DT>(q[b], scale, s);
-      } else {
+      for (int b = 0; b < B; ++b) {
+        if (!(live & (1u << b))) continue;
+        const int r = r0 + b;
+        const size_t rowbase = ((size_t)p0 * E + r) * (size_t)Ns;
+        const float scale = DT == 0 ? 1.0f : sw.scale[p0 + r / E];
+        const int n = first[b] + lane_off;
+        float2 s[SPL + 1];
+        if (fast & (1u << b)) {
+          if constexpr (DT == 0) unpack_pair(q[b], scale, s);
+          else unpack_pair16<DT>(q[b], scale, s);
+        } else {
 #pragma unroll
-        for (int i = 0; i < SPL; ++i) s[i] = load_guarded(sw, rowbase, n + i, DT, scale);
-      }
-      s[SPL].x = __shfl_down(s[0].x, 1, 64);
-      s[SPL].y = __shfl_down(s[0].y, 1, 64);
-      if (lane == 63) {
-        s[SPL] = fast[b] ? make_float2(tail[b].x * scale, tail[b].y * scale)
-                         : load_guarded(sw, rowbase, n + SPL, DT, scale);
-      }
-      float4* dst = lwin + (size_t)r * (W + 1);
+          for (int i = 0; i < SPL; ++i) s[i] = load_guarded(sw, rowbase, n + i, DT, scale);
+        }
+        s[SPL].x = __shfl_down(s[0].x, 1, 64);
+        s[SPL].y = __shfl_down(s[0].y, 1, 64);
+        if (lane == 63) {
+          s[SPL] = (fast & (1u << b)) ? make_float2(tail[b].x * scale, tail[b].y * scale)
+                                      : load_guarded(sw, rowbase, n + SPL, DT, scale);
+        }
+        float4* dst = lwin + (size_t)r * (W + 1) + part * JS;
 #pragma unroll
-      for (int i = 0; i < SPL; ++i) {
-        const int k = k0 + i;
-        if (k < W) {
-          const float dr = s[i + 1].x - s[i].x, di = s[i + 1].y - s[i].y;
-          dst[k] = make_float4(fmaf(0.5f, dr, s[i].x), fmaf(0.5f, di, s[i].y), dr, di);
+        for (int i = 0; i < SPL; ++i) {
+          if (part * JS + lane_off + i < W) {
+            const float dr = s[i + 1].x - s[i].x, di = s[i + 1].y - s[i].y;
+            dst[lane_off + i] = make_float4(fmaf(0.5f, dr, s[i].x), fmaf(0.5f, di, s[i].y), dr, di);
+          }
         }
       }
     }
