@@ -192,11 +192,16 @@ def batched_leg(api, steps: int, warmup: int) -> dict:
     scns = [make_config(f"c4b:{k}") for k in range(24)]
     echoes = [synthesize_echo(s, device="cuda", dtype=torch.complex64, noise_on_device=True) for s in scns]
     torch.cuda.synchronize()
-    plan = api.sas_bp_plan([_desc(api, s) for s in scns])
     bufs = [_buffers(api, s, e) for s, e in zip(scns, echoes)]
+    t = time.perf_counter()
+    tuned = api.sas_bp_autotune([_desc(api, s) for s in scns], bufs, reps=2)
+    tune_s = time.perf_counter() - t
+    kw = {k: v for k, v in tuned.items() if k != "ms"}
+    log(f"batched: autotuned {kw} in {tune_s:.1f} s")
+    plan = api.sas_bp_plan([_desc(api, s) for s in scns], **kw)
     useful = sum(api.sas_bp_useful_updates(plan, bufs))
     one = time_steps(lambda: api.sas_bp_image(plan, bufs), steps, warmup)
-    plans = [api.sas_bp_plan([_desc(api, s)]) for s in scns]
+    plans = [api.sas_bp_plan([_desc(api, s)], **kw) for s in scns]
 
     def separate():
         for p, b in zip(plans, bufs):
@@ -210,6 +215,8 @@ def batched_leg(api, steps: int, warmup: int) -> dict:
     plan.destroy()
     return {"workload": "24 swaths, sides U{512..4096} px, 128-512 pings, 16-32 receivers, +-10 deg gate",
             "useful_updates": int(useful), "nominal_updates": int(nominal),
+            "tiling": {"tile": list(kw["tile"]), "threads": kw["threads"], "pings_per_chunk": kw["pings_per_chunk"]},
+            "autotune_seconds": tune_s,
             "one_launch_ms": one, "separate_launches_ms": sep, "speedup": sep / one,
             "one_launch_updates_per_s": useful / (one * 1e-3)}
 

@@ -164,6 +164,21 @@ int sas_bp_plan_status(sas_bp_plan_t plan);
  * workgroup. */
 int sas_bp_plan_info(sas_bp_plan_t plan, int64_t info[8]);
 
+/* Autotuner (tile shape and pings per chunk). Times every candidate tiling
+ * of the lane-layout menu (2D layouts for images, 3D ones for volumes) with
+ * 1, 2, 4 and 8 pings per chunk that fits the device, running the image of
+ * these swaths on the caller's buffers (io: as for sas_bp_image; the images
+ * are overwritten) on `stream`: one warm-up and `reps` timed launches each,
+ * measured with HIP events. Writes the fastest candidate's options to *best
+ * (device and workspace_limit copied from `base`, which may be NULL) and its
+ * mean time to *best_ms (host memory). The choice is cached for the process
+ * per shape class (2D/3D, echo dtype, gate on/off, largest element count,
+ * window length and total pixels, each in power-of-two buckets): a later call
+ * for the same class returns it without timing, with *best_ms = 0.
+ * Synchronous; creates and destroys one plan per candidate. */
+int sas_bp_autotune(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_swath_io* io,
+                    const sas_bp_options* base, int reps, void* stream, sas_bp_options* best, double* best_ms);
+
 /* Per-launch timing of the main kernel, for measuring it against its
  * roofline. With enable != 0, sas_bp_image and sas_bp_adjoint enqueue their
  * kernels directly (not through the captured graph) and bracket the

@@ -18,7 +18,7 @@ ECHO_C64, ECHO_F16X2, ECHO_BF16X2 = 0, 1, 2
 EXPORTED = (
     "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image", "sas_bp_adjoint",
     "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_plan_status", "sas_bp_plan_info",
-    "sas_bp_set_kernel_timing", "sas_bp_kernel_time", "sas_bp_destroy", "sas_bp_error_string",
+    "sas_bp_autotune", "sas_bp_set_kernel_timing", "sas_bp_kernel_time", "sas_bp_destroy", "sas_bp_error_string",
     "sas_bp_last_error_detail", "sas_bp_abi_version",
 )
 
@@ -62,6 +62,8 @@ def _load():
     lib.sas_bp_sharpness.argtypes = [P, P, C.c_int64, P, P, P]
     lib.sas_bp_plan_status.argtypes = [P]
     lib.sas_bp_plan_info.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.sas_bp_autotune.argtypes = [C.POINTER(SwathDesc), C.c_int, C.POINTER(SwathIO), C.POINTER(Options), C.c_int,
+                                    P, C.POINTER(Options), C.POINTER(C.c_double)]
     lib.sas_bp_set_kernel_timing.argtypes = [P, C.c_int]
     lib.sas_bp_kernel_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.sas_bp_destroy.argtypes = [P]

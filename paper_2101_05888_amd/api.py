@@ -123,21 +123,25 @@ def _need(t: torch.Tensor, name: str, dtype, shape, device) -> None:
 
 
 def _io(plan: Plan, bufs: Sequence[SwathBuffers]):
-    if len(bufs) != len(plan.descs):
-        raise ValueError(f"plan has {len(plan.descs)} swaths, got {len(bufs)} buffers")
+    return _io_for(plan.descs, plan.device, bufs)
+
+
+def _io_for(descs, device, bufs: Sequence[SwathBuffers]):
+    if len(bufs) != len(descs):
+        raise ValueError(f"plan has {len(descs)} swaths, got {len(bufs)} buffers")
     arr = (N.SwathIO * len(bufs))()
-    for i, (d, b) in enumerate(zip(plan.descs, bufs)):
+    for i, (d, b) in enumerate(zip(descs, bufs)):
         P, E, Ns = d.n_ping, d.n_elem, d.n_sample
         if d.echo_dtype == N.ECHO_C64:
-            _need(b.echo, f"echo[{i}]", torch.complex64, (P, E, Ns), plan.device)
+            _need(b.echo, f"echo[{i}]", torch.complex64, (P, E, Ns), device)
         else:
             dt = torch.float16 if d.echo_dtype == N.ECHO_F16X2 else torch.bfloat16
-            _need(b.echo, f"echo[{i}]", dt, (P, E, Ns, 2), plan.device)
-            _need(b.echo_scale, f"echo_scale[{i}]", torch.float32, (P,), plan.device)
-        _need(b.tx, f"tx[{i}]", torch.float64, (P, 3), plan.device)
-        _need(b.rx, f"rx[{i}]", torch.float64, (P, E, 3), plan.device)
-        _need(b.c, f"c[{i}]", torch.float64, (1,), plan.device)
-        _need(b.image, f"image[{i}]", torch.complex64, (d.n[2], d.n[1], d.n[0]), plan.device)
+            _need(b.echo, f"echo[{i}]", dt, (P, E, Ns, 2), device)
+            _need(b.echo_scale, f"echo_scale[{i}]", torch.float32, (P,), device)
+        _need(b.tx, f"tx[{i}]", torch.float64, (P, 3), device)
+        _need(b.rx, f"rx[{i}]", torch.float64, (P, E, 3), device)
+        _need(b.c, f"c[{i}]", torch.float64, (1,), device)
+        _need(b.image, f"image[{i}]", torch.complex64, (d.n[2], d.n[1], d.n[0]), device)
         arr[i].echo = b.echo.data_ptr()
         arr[i].echo_scale = b.echo_scale.data_ptr() if b.echo_scale is not None else None
         arr[i].tx_pos = b.tx.data_ptr()
@@ -195,6 +199,24 @@ def sas_bp_sharpness(plan: Plan, image: torch.Tensor, out_S: torch.Tensor,
     check(N.lib().sas_bp_sharpness(plan.handle, image.data_ptr(), image.numel(), out_S.data_ptr(),
                                  grad_image.data_ptr() if grad_image is not None else None,
                                  _stream(plan.device, stream)), "sas_bp_sharpness")
+
+
+def sas_bp_autotune(descs: Sequence[N.SwathDesc], bufs: Sequence[SwathBuffers], reps: int = 3, device: int = 0,
+                    stream=None) -> dict:
+    """Fastest tiling for these swaths, timed on their buffers (images are
+    overwritten). Returns ``sas_bp_plan`` keyword arguments (tile, threads,
+    pings_per_chunk) plus ``ms``, the mean image time (0 when the choice came
+    from the process cache)."""
+    descs = list(descs)
+    arr = (N.SwathDesc * len(descs))(*descs)
+    io = _io_for(descs, device, bufs)
+    base = _options(device)
+    best = N.Options()
+    ms = C.c_double()
+    check(N.lib().sas_bp_autotune(arr, len(descs), io, C.byref(base), int(reps), _stream(device, stream),
+                                  C.byref(best), C.byref(ms)), "sas_bp_autotune")
+    return {"tile": (best.tile_x, best.tile_y, best.tile_z), "threads": best.threads,
+            "pings_per_chunk": best.pings_per_chunk, "ms": float(ms.value)}
 
 
 def sas_bp_set_kernel_timing(plan: Plan, enable: bool) -> None:

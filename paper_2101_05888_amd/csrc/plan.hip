@@ -15,7 +15,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -457,6 +460,22 @@ int plan_sizes(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, Ti
 
 }  // namespace
 
+// Autotuner cache (process-wide), keyed by shape class.
+namespace {
+
+typedef std::tuple<int, int, int, int, int, int> TuneKey;   // 3D, dtype, gate, E, W, pixels (log2 buckets)
+
+std::mutex g_tune_mutex;
+std::map<TuneKey, sas_bp_options> g_tune_cache;
+
+int log2_bucket(long long v) {
+  int b = 0;
+  while (v > 1) { v >>= 1; ++b; }
+  return b;
+}
+
+}  // namespace
+
 extern "C" {
 
 int sas_bp_abi_version(void) { return SAS_BP_ABI_VERSION; }
@@ -795,6 +814,111 @@ int sas_bp_kernel_time(sas_bp_plan_t p, double* ms_total, int64_t* launches) {
   *ms_total = sum;
   *launches = (int64_t)p->n_timed;
   p->n_timed = 0;
+  return SAS_BP_OK;
+}
+
+// ------------------------------------------------------------ autotune ---
+
+int sas_bp_autotune(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_swath_io* io,
+                    const sas_bp_options* base, int reps, void* stream, sas_bp_options* best, double* best_ms) {
+  if (!best || !best_ms) return fail(SAS_BP_EINVAL, "best or best_ms is NULL");
+  if (reps < 1 || reps > 1000) return fail(SAS_BP_EINVAL, "reps must be in [1, 1000]");
+  // validate with the default tiling, and get the shape class
+  Tiling t0;
+  std::vector<SwathPlan> sw0;
+  int n_tiles0 = 0;
+  Layout lay0;
+  int rc = plan_sizes(desc, n_swaths, nullptr, &t0, &sw0, &n_tiles0, &lay0);
+  if (rc) return rc;
+  bool any3d = false, gate = false;
+  int E = 0, W = 0;
+  long long pix = 0;
+  for (const auto& s : sw0) {
+    any3d |= s.d.n[2] > 1;
+    gate |= s.d.gate_half_angle > 0.0;
+    E = std::max(E, s.d.n_elem);
+    W = std::max(W, s.W);
+    pix += s.d.n[0] * s.d.n[1] * s.d.n[2];
+  }
+  const TuneKey key(any3d ? 1 : 0, sw0[0].d.echo_dtype, gate ? 1 : 0, log2_bucket(E), log2_bucket(W),
+                    log2_bucket(pix));
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *best = it->second;
+      if (base) {
+        best->device = base->device;
+        best->workspace_limit = base->workspace_limit;
+      }
+      *best_ms = 0.0;
+      return SAS_BP_OK;
+    }
+  }
+  sas_bp_options cand;
+  std::memset(&cand, 0, sizeof cand);
+  if (base) {
+    cand.device = base->device;
+    cand.workspace_limit = base->workspace_limit;
+  }
+  cand.use_graph = 1;
+  DeviceGuard guard(cand.device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIP_TRY(hipEventCreate(&ea));
+  if (hipEventCreate(&eb) != hipSuccess) {
+    (void)hipEventDestroy(ea);
+    return fail(SAS_BP_EDEVICE, "hipEventCreate failed");
+  }
+  double best_time = -1.0;
+  sas_bp_options best_opt = cand;
+  int last_err = SAS_BP_OK;
+  static const int kChunks[] = {1, 2, 4, 8};
+  for (int l = 0; l < kNumLayouts; ++l) {
+    const LaneLayout& L = kLayouts[l];
+    if ((L.LZ > 1) != any3d) continue;
+    for (int cp : kChunks) {
+      sas_bp_options o = cand;
+      o.tile_x = L.LX * L.K;
+      o.tile_y = L.LY;
+      o.tile_z = L.LZ;
+      o.threads = L.LX * L.LY * L.LZ;
+      o.pings_per_chunk = cp;
+      sas_bp_plan_t p = nullptr;
+      if (sas_bp_plan(desc, n_swaths, &o, &p) != SAS_BP_OK) continue;   // does not fit: skip
+      int e = sas_bp_image(p, io, n_swaths, stream);
+      float ms = 0.0f;
+      if (e == SAS_BP_OK && hipEventRecord(ea, st) != hipSuccess) e = SAS_BP_EDEVICE;
+      for (int r = 0; r < reps && e == SAS_BP_OK; ++r) e = sas_bp_image(p, io, n_swaths, stream);
+      if (e == SAS_BP_OK && hipEventRecord(eb, st) != hipSuccess) e = SAS_BP_EDEVICE;
+      if (e == SAS_BP_OK && hipEventSynchronize(eb) != hipSuccess) e = SAS_BP_EDEVICE;
+      if (e == SAS_BP_OK && hipEventElapsedTime(&ms, ea, eb) != hipSuccess) e = SAS_BP_EDEVICE;
+      release(p);
+      if (e != SAS_BP_OK) {
+        last_err = e;
+        if (e == SAS_BP_EINVAL) break;    // the buffers do not match: no candidate can run
+        continue;
+      }
+      const double mean = (double)ms / reps;
+      if (best_time < 0.0 || mean < best_time) {
+        best_time = mean;
+        best_opt = o;
+      }
+    }
+    if (last_err == SAS_BP_EINVAL) break;
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  if (best_time < 0.0) {
+    if (last_err != SAS_BP_OK) return last_err;
+    return fail(SAS_BP_EUNSUPPORTED, "no tiling candidate fits these swaths");
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[key] = best_opt;
+  }
+  *best = best_opt;
+  *best_ms = best_time;
   return SAS_BP_OK;
 }
 

@@ -123,6 +123,24 @@ def test_kernel_timing_brackets_each_launch(api):
     assert api.sas_bp_kernel_time(plan) == (0.0, 0)         # graph replays are not timed
 
 
+def test_autotune_choice_is_a_valid_tiling_and_cached(api):
+    scn, echo = _case("c2", n_ping=48, n_elem=6, nx=200, ny=96, n_sample=4096, n_scat=20, n_speckle=100)
+    d = desc_for(api, scn)
+    buf = buffers_for(api, scn, echo)
+    best = api.sas_bp_autotune([d], [buf], reps=2)
+    assert best["ms"] > 0.0 and best["pings_per_chunk"] in (1, 2, 4, 8)
+    again = api.sas_bp_autotune([d], [buf], reps=2)
+    assert again["ms"] == 0.0 and {k: v for k, v in again.items() if k != "ms"} == \
+        {k: v for k, v in best.items() if k != "ms"}
+    kw = {k: v for k, v in best.items() if k != "ms"}
+    img, plan, _ = gpu_image(api, scn, echo, **kw)
+    info = plan.info()
+    assert (info["tile_x"], info["tile_y"], info["tile_z"]) == tuple(best["tile"])
+    assert info["pings_per_chunk"] == best["pings_per_chunk"] and info["threads"] == best["threads"]
+    r, ph = report("autotuned", img, oracle_image(scn, echo.numpy()).reshape(img.shape))
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+
+
 def test_graph_sees_new_navigation_and_sound_speed(api):
     scn, echo = _case("c1", n_ping=12, n_elem=4, nx=48, ny=40)
     img, plan, buf = gpu_image(api, scn, echo)
