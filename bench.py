@@ -62,6 +62,38 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
+def committed_counters():
+    """Key/value lines of the committed counter summary, or {} when the kernel
+    sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            kv = dict((k.strip(), v.strip()) for k, v in
+                      (l.split(":", 1) for l in f.read().splitlines() if ":" in l and not l.startswith(" ")))
+    except OSError:
+        return {}
+    return kv if kv.get("kernel_sources_sha256") == kernel_sources_digest() else {}
+
+
+def issue_roofline(kernel_ms: float):
+    """Instruction-issue roofline of the image kernel: VALU and transcendental
+    wave-instructions per launch (committed counters) against the issue rate
+    of 256 CUs at 2.4 GHz, 2 FP32 VALU wave-instructions per CU clock (the
+    157.3 TFLOP/s FP32 peak is 256 CU x 2.4 GHz x 2 instr x 64 lanes x 2 flop)
+    and a quarter of that for transcendentals. frac = issue cycles needed /
+    cycles available."""
+    kv = committed_counters()
+    try:
+        valu = float(kv["valu_wave_instructions_per_launch"])
+        trans = float(kv["trans_wave_instructions_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    cu_cycles = kernel_ms * 1e-3 * 2.4e9 * 256
+    need = (valu - trans) / 2.0 + trans * 2.0
+    return {"valu_wave_instructions": valu, "trans_wave_instructions": trans,
+            "achieved_instr_per_s": valu / (kernel_ms * 1e-3), "peak_instr_per_s": 2.0 * 2.4e9 * 256,
+            "issue_cycles_needed": need, "cu_cycles_available": cu_cycles, "frac": need / cu_cycles}
+
+
 def measured_traffic():
     """HBM bytes per image-kernel launch from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE scaled by the copy calibration), or None when the
@@ -318,6 +350,7 @@ def main() -> int:
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_update": fpu, "kernel": "image_kernel", "launch_ms": kernel_ms,
                      "updates_per_launch": int(useful)},
+        "issue_roofline": issue_roofline(kernel_ms),
     }
 
     if not args.no_mixed:
