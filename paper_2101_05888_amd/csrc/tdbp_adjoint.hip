@@ -98,7 +98,6 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
       gi[k] = g.y;
     }
     const float szero = (float)W;
-    const int wmask = window_mask(W);
 
     const Geo geo = geo_for(ws, sw, ROWS, GATE);
     int* lpart = reinterpret_cast<int*>(lds + Ld.off_win);   // window area, free between chunks
@@ -153,12 +152,12 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
                 const bool in = (unsigned)(da + LX * k) <= (unsigned)span;
                 sidx = in ? sidx : szero;
               }
-              const WinIdx wi = window_index(sidx, wmask);
+              float wt;
+              const float4 v = window_read(window_base(win), sidx, &wt);
               const float sn = __builtin_amdgcn_sinf(cyc);
               const float cs = __builtin_amdgcn_cosf(cyc);
-              const float4 v = win[wi.idx];
               const float dar = v.z, dai = v.w;
-              const float Lr = fmaf(wi.w, dar, v.x), Li = fmaf(wi.w, dai, v.y);
+              const float Lr = fmaf(wt, dar, v.x), Li = fmaf(wt, dai, v.y);
               const float Xr = fmaf(fsf, dar, -tpf * Li);
               const float Xi = fmaf(fsf, dai, tpf * Lr);
               const float Dr = fmaf(Xr, cs, -Xi * sn);

@@ -37,7 +37,8 @@ struct TxRec {
 
 constexpr unsigned kFlagSkip = 1u;   // no pixel of the tile is gated in (or bad navigation)
 constexpr unsigned kFlagFull = 2u;   // every pixel of the tile is gated in
-constexpr unsigned kFlagPoly = 4u;   // receiver offset by the degree-5 series
+constexpr unsigned kFlagPoly = 4u;   // receiver offset by the series (degree 5, or 4 with kFlagDeg4)
+constexpr unsigned kFlagDeg4 = 8u;   // the degree-4 series already meets the bound
 constexpr int kEmptyRow = 30000;     // encodes an empty gate interval (never matches a local x)
 constexpr double kPolyTol = 1e-8;    // metres, bound on the series truncation error
 
@@ -99,7 +100,8 @@ __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c,
   const double cyc = sw.fc * tau;
   unsigned flags = ok ? 0u : kFlagSkip;
   // series bound over the tile: |num| <= 2 d0 r + r^2, remainder of
-  // sqrt(1+y) - 1 after y^5 at most (21/1024) |y|^6 / (1 - |y|)
+  // sqrt(1+y) - 1 after y^5 at most (21/1024) |y|^6 / (1 - |y|), after y^4 at
+  // most (7/256) |y|^5 / (1 - |y|) (binomial coefficients of decreasing size)
   const double r = sw.half_diag;
   const double i1 = 1.0 / d0R, i2 = i1 * i1;
   const double y = (2.0 * d0R * r + r * r) * i2;
@@ -107,6 +109,7 @@ __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c,
   const double y3 = y * y * y;
   if (ok && y < 0.5 && d0R * (21.0 / 1024.0) * (y3 * y3) <= kPolyTol * (1.0 - y)) {
     flags |= kFlagPoly;
+    if (d0R * (7.0 / 256.0) * (y3 * y * y) <= kPolyTol * (1.0 - y)) flags |= kFlagDeg4;
     a1 = 0.5 * i1;
     a2 = -0.125 * i1 * i2;
     a3 = 0.0625 * i1 * i2 * i2;
@@ -156,22 +159,31 @@ __device__ __forceinline__ int gate_row(const SwathDev& sw, int p, int e, double
 __device__ __forceinline__ int row_lo(int v) { return (int)(short)(v & 0xffff); }
 __device__ __forceinline__ int row_hi(int v) { return v >> 16; }
 
-// Rounded window index and weight of a sample position with only FP32 adds:
-// adding 2^23 rounds sh = s - 1/2 to an integer n held in the low mantissa
-// bits of t; w = sh - n. The masked bit pattern of t is the index.
+// Window entry and weight of a sample position with FP32 adds and one
+// shift-add: adding 2^23 rounds sh = s - 1/2 to an integer n held in the low
+// mantissa bits of t = sh + 2^23, and w = sh - n. The LDS byte address of entry
+// n of a window at base is base + 16 n = (base - 16 bits(2^23)) + 16 bits(t)
+// in 32-bit arithmetic, so window_base() folds the constant once per window.
+// The window length is sized so that every pixel of the tile reads an entry in
+// 0..W (W is the zero entry that gated-out pixels read).
 constexpr float kRoundMagic = 8388608.0f;
+constexpr unsigned kRoundMagicBits = 0x4B000000u;
 
-struct WinIdx {
-  int idx;
-  float w;
-};
+__device__ __forceinline__ unsigned lds_address(const void* p) {
+  return (unsigned)(uintptr_t)((__attribute__((address_space(3))) const void*)p);
+}
 
-__device__ __forceinline__ WinIdx window_index(float sh, int mask) {
+__device__ __forceinline__ unsigned window_base(const float4* win) {
+  return lds_address(win) - (kRoundMagicBits << 4);
+}
+
+__device__ __forceinline__ float4 window_read(unsigned wbase, float sh, float* w) {
   const float t = sh + kRoundMagic;
-  WinIdx r;
-  r.w = sh - (t - kRoundMagic);
-  r.idx = (int)(__float_as_uint(t) & (unsigned)mask);
-  return r;
+  *w = sh - (t - kRoundMagic);
+  const unsigned addr = wbase + (__float_as_uint(t) << 4);
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const f32x4 q = *reinterpret_cast<__attribute__((address_space(3))) const f32x4*>((uintptr_t)addr);
+  return make_float4(q.x, q.y, q.z, q.w);
 }
 
 // Echo sample loaders: FP32 complex out of each storage type.
@@ -191,19 +203,12 @@ __device__ __forceinline__ float2 load_sample(const void* base, size_t idx, int 
 // LDS layout for a chunk of CP pings with E elements and window length W:
 //   TxRec tx[CP]   RxRec rx[CP][E]   int n0[CP][E]   int rows[CP][E][ROWS] (gate only)
 //   float4 win[CP][E][W+1]: {(E[n] + E[n+1]) / 2, E[n+1] - E[n]} for n < W,
-//   entry W all zero; then a tail pad up to the next power of two.
+//   entry W all zero.
 // Interpolation at sample position s is then one 16-byte read and two FMAs:
 // with n = round(s - 1/2) and w = (s - 1/2) - n in [-1/2, 1/2],
 //   (1 - frac s) E[floor s] + frac(s) E[floor s + 1] = mid[n] + w diff[n]
 // (a tie, s an integer rounded down to n = s - 1, gives w = 1/2 and the same
-// value). Gated-out pixels read the zero entry. Indices are masked to
-// window_mask(W), so no read can leave the allocation.
-__host__ __device__ inline int window_mask(int W) {
-  int m = 1;
-  while (m < W + 1) m <<= 1;
-  return m - 1;
-}
-
+// value). Gated-out pixels read the zero entry.
 struct LdsLayout {
   int off_tx, off_rx, off_n0, off_rows, off_win, bytes;
 };
@@ -217,7 +222,7 @@ __host__ __device__ inline LdsLayout lds_layout(int CP, int E, int W, int ROWS, 
   o = (o + 15) & ~15;
   L.off_rows = o; o += gate ? CP * E * ROWS * 4 : 0;
   o = (o + 15) & ~15;
-  L.off_win = o;  o += (CP * E * (W + 1) + (window_mask(W) - W)) * 16;
+  L.off_win = o;  o += CP * E * (W + 1) * 16;
   L.bytes = o;
   return L;
 }

@@ -125,13 +125,14 @@ __global__ __launch_bounds__(kThreads) void order_kernel(Workspace ws, int n_til
   }
 }
 
-// One (ping, element) record applied to the K pixels of a lane. POLY selects
-// the series form of the receiver-leg offset, TEST the per-pixel gate test of
-// a partially gated record; both are uniform over the workgroup.
-template <int K, int LX, bool POLY, bool TEST>
+// One (ping, element) record applied to the K pixels of a lane. DEG selects
+// the receiver-leg offset (0 the exact form, 4 or 5 the series of that
+// degree), TEST the per-pixel gate test of a partially gated record; both are
+// uniform over the workgroup.
+template <int K, int LX, int DEG, bool TEST>
 __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __restrict__ win, const float* dx,
                                            const float* dsq, const float* dT, float dyl, float dzl, float fs_c,
-                                           float fc_c, float szero, int wmask, int da, int span, float* accr,
+                                           float fc_c, float szero, int da, int span, float* accr,
                                            float* acci) {
   const float ryz = fmaf(rec.q0.y, dyl, rec.q0.z * dzl);
   const float d0 = rec.q1.w;
@@ -142,8 +143,8 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
   for (int k = 0; k < K; ++k) {
     const float num = fmaf(rec.q0.x, dx[k], ryz + dsq[k]);
     float D;   // two-way path offset from the (tile, ping, element) reference, metres
-    if (POLY) {
-      float h = fmaf(rec.q1.z, num, rec.q2.w);
+    if (DEG > 0) {
+      float h = DEG == 5 ? fmaf(rec.q1.z, num, rec.q2.w) : rec.q2.w;
       h = fmaf(h, num, rec.q2.z);
       h = fmaf(h, num, rec.q2.y);
       h = fmaf(h, num, rec.q2.x);
@@ -163,12 +164,9 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
   // phase 2: every window read in flight at once
   float4 v[K];
   float wt[K];
+  const unsigned wbase = window_base(win);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const WinIdx wi = window_index(sidx[k], wmask);
-    wt[k] = wi.w;
-    v[k] = win[wi.idx];
-  }
+  for (int k = 0; k < K; ++k) v[k] = window_read(wbase, sidx[k], &wt[k]);
   // phase 3: carrier phasors while the reads land
   float sn[K], cs[K];
 #pragma unroll
@@ -246,7 +244,6 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
 #pragma unroll
     for (int k = 0; k < K; ++k) { accr[k] = 0.0f; acci[k] = 0.0f; }
     const float szero = (float)W;   // the window's all-zero entry
-    const int wmask = window_mask(W);
 
     const Geo geo = geo_for(ws, sw, ROWS, GATE);
     int* lpart = reinterpret_cast<int*>(lds + Ld.off_win);   // window area, free between chunks
@@ -276,19 +273,24 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
           const RxRec rec = lrx[r];
           const float4* win = lwin + (size_t)r * (W + 1);
           if (!GATE || (f & kFlagFull)) {
-            if (f & kFlagPoly)
-              accumulate<K, LX, true, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, wmask, 0, 0, accr, acci);
+            if (f & kFlagDeg4)
+              accumulate<K, LX, 4, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
+            else if (f & kFlagPoly)
+              accumulate<K, LX, 5, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
             else
-              accumulate<K, LX, false, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, wmask, 0, 0, accr, acci);
+              accumulate<K, LX, 0, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
           } else {
             const int v = lrows[r * ROWS + row];
             const int a = row_lo(v), b = row_hi(v);
-            if (f & kFlagPoly)
-              accumulate<K, LX, true, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, wmask, lx - a, b - a,
-                                            accr, acci);
+            if (f & kFlagDeg4)
+              accumulate<K, LX, 4, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
+                                         acci);
+            else if (f & kFlagPoly)
+              accumulate<K, LX, 5, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
+                                         acci);
             else
-              accumulate<K, LX, false, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, wmask, lx - a, b - a,
-                                             accr, acci);
+              accumulate<K, LX, 0, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
+                                         acci);
           }
         }
       }
