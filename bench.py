@@ -246,7 +246,8 @@ def batched_leg(api, steps: int, warmup: int) -> dict:
     plan.destroy()
     return {"workload": "24 swaths, sides U{512..4096} px, 128-512 pings, 16-32 receivers, +-10 deg gate",
             "useful_updates": int(useful), "nominal_updates": int(nominal),
-            "tiling": {"tile": list(kw["tile"]), "threads": kw["threads"], "pings_per_chunk": kw["pings_per_chunk"]},
+            "tiling": {"tile": list(kw["tile"]), "threads": kw["threads"], "pings_per_chunk": kw["pings_per_chunk"],
+                       "elems_per_chunk": kw["elems_per_chunk"]},
             "autotune_seconds": tune_s,
             "one_launch_ms": one, "separate_launches_ms": sep, "speedup": sep / one,
             "one_launch_updates_per_s": useful / (one * 1e-3)}
@@ -341,7 +342,8 @@ def main() -> int:
                    "pings": scn.n_ping, "elements": scn.n_elem, "samples": scn.n_sample,
                    "pixels": g.n_pix, "useful_updates": int(useful), "nominal_updates": int(nominal),
                    "tile": [info["tile_x"], info["tile_y"], info["tile_z"]],
-                   "pings_per_chunk": info["pings_per_chunk"], "grid": info["grid"]},
+                   "records_per_chunk": info["records_per_chunk"], "grid": info["grid"],
+                   "workgroups_per_cu": info["workgroups_per_cu"]},
         "nominal_updates_per_s": nominal / (ms * 1e-3),
         "graph_ms_per_step": graph_ms,
         "image_kernel_ms": kernel_ms,

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SAS_BP_ABI_VERSION 1
+#define SAS_BP_ABI_VERSION 2
 
 typedef struct sas_bp_plan_s* sas_bp_plan_t;
 
@@ -98,6 +98,9 @@ typedef struct {
     int32_t pings_per_chunk; /* pings staged in LDS per pass; 0 = automatic   */
     int32_t threads;         /* threads per workgroup (256 or 512); 0 = automatic */
     int32_t use_graph;       /* 1 = replay a captured HIP graph (default), 0 = direct launches */
+    int32_t elems_per_chunk; /* image: (ping, element) records staged per pass when
+                                below n_elem (part of a ping; overrides pings_per_chunk
+                                for the image, not the adjoint); 0 = automatic */
     size_t workspace_limit;  /* bytes; 0 = unlimited                           */
 } sas_bp_options;
 
@@ -159,14 +162,16 @@ int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, doubl
  * synchronises with the device and clears it. */
 int sas_bp_plan_status(sas_bp_plan_t plan);
 
-/* Chosen tiling, for reporting: tile_x, tile_y, tile_z, pings_per_chunk,
- * window samples, LDS bytes per workgroup, workgroups launched, threads per
- * workgroup. */
-int sas_bp_plan_info(sas_bp_plan_t plan, int64_t info[8]);
+/* Chosen tiling, for reporting: tile_x, tile_y, tile_z, pings_per_chunk
+ * (adjoint), window samples, image LDS bytes per workgroup, image workgroups
+ * launched, threads per workgroup, image records per chunk, image workgroups
+ * resident per CU. */
+int sas_bp_plan_info(sas_bp_plan_t plan, int64_t info[10]);
 
-/* Autotuner (tile shape and pings per chunk). Times every candidate tiling
- * of the lane-layout menu (2D layouts for images, 3D ones for volumes) with
- * 1, 2, 4 and 8 pings per chunk that fits the device, running the image of
+/* Autotuner (tile shape and chunk size). Times every candidate tiling of the
+ * lane-layout menu (2D layouts for images, 3D ones for volumes) with the
+ * automatic chunk, 1, 2, 4 and 8 pings per chunk and 3/4, 1/2 and 1/4 of a
+ * ping's elements per chunk, each that fits the device, running the image of
  * these swaths on the caller's buffers (io: as for sas_bp_image; the images
  * are overwritten) on `stream`: one warm-up and `reps` timed launches each,
  * measured with HIP events. Writes the fastest candidate's options to *best

@@ -36,7 +36,7 @@ class Options(C.Structure):
     _fields_ = [
         ("device", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
         ("pings_per_chunk", C.c_int32), ("threads", C.c_int32), ("use_graph", C.c_int32),
-        ("workspace_limit", C.c_size_t),
+        ("elems_per_chunk", C.c_int32), ("workspace_limit", C.c_size_t),
     ]
 
 

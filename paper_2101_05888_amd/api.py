@@ -36,11 +36,12 @@ def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin
 
 
 def _options(device=0, tile=(0, 0, 0), pings_per_chunk=0, use_graph=True, workspace_limit=0,
-             threads=0) -> N.Options:
+             threads=0, elems_per_chunk=0) -> N.Options:
     o = N.Options()
     o.device = int(device)
     o.tile_x, o.tile_y, o.tile_z = (int(v) for v in tile)
     o.pings_per_chunk = int(pings_per_chunk)
+    o.elems_per_chunk = int(elems_per_chunk)
     o.threads = int(threads)
     o.use_graph = 1 if use_graph else 0
     o.workspace_limit = int(workspace_limit)
@@ -56,9 +57,10 @@ class Plan:
         self.device = device
 
     def info(self) -> dict:
-        arr = (C.c_int64 * 8)()
+        arr = (C.c_int64 * 10)()
         check(N.lib().sas_bp_plan_info(self.handle, arr), "sas_bp_plan_info")
-        keys = ("tile_x", "tile_y", "tile_z", "pings_per_chunk", "window", "lds_bytes", "grid", "threads")
+        keys = ("tile_x", "tile_y", "tile_z", "pings_per_chunk", "window", "lds_bytes", "grid", "threads",
+                "records_per_chunk", "workgroups_per_cu")
         return dict(zip(keys, (int(v) for v in arr)))
 
     def status(self) -> int:
@@ -77,20 +79,21 @@ class Plan:
 
 
 def sas_bp_plan(descs: Sequence[N.SwathDesc], device: int = 0, tile=(0, 0, 0), pings_per_chunk: int = 0,
-                use_graph: bool = True, workspace_limit: int = 0, threads: int = 0) -> Plan:
+                use_graph: bool = True, workspace_limit: int = 0, threads: int = 0,
+                elems_per_chunk: int = 0) -> Plan:
     descs = list(descs)
     arr = (N.SwathDesc * len(descs))(*descs)
-    opt = _options(device, tile, pings_per_chunk, use_graph, workspace_limit, threads)
+    opt = _options(device, tile, pings_per_chunk, use_graph, workspace_limit, threads, elems_per_chunk)
     out = C.c_void_p()
     check(N.lib().sas_bp_plan(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_plan")
     return Plan(out.value, descs, device)
 
 
 def sas_bp_workspace_size(descs: Sequence[N.SwathDesc], tile=(0, 0, 0), pings_per_chunk: int = 0,
-                          threads: int = 0) -> int:
+                          threads: int = 0, elems_per_chunk: int = 0) -> int:
     descs = list(descs)
     arr = (N.SwathDesc * len(descs))(*descs)
-    opt = _options(0, tile, pings_per_chunk, threads=threads)
+    opt = _options(0, tile, pings_per_chunk, threads=threads, elems_per_chunk=elems_per_chunk)
     out = C.c_size_t()
     check(N.lib().sas_bp_workspace_size(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_workspace_size")
     return int(out.value)
@@ -205,8 +208,8 @@ def sas_bp_autotune(descs: Sequence[N.SwathDesc], bufs: Sequence[SwathBuffers], 
                     stream=None) -> dict:
     """Fastest tiling for these swaths, timed on their buffers (images are
     overwritten). Returns ``sas_bp_plan`` keyword arguments (tile, threads,
-    pings_per_chunk) plus ``ms``, the mean image time (0 when the choice came
-    from the process cache)."""
+    pings_per_chunk, elems_per_chunk) plus ``ms``, the mean image time (0 when
+    the choice came from the process cache)."""
     descs = list(descs)
     arr = (N.SwathDesc * len(descs))(*descs)
     io = _io_for(descs, device, bufs)
@@ -216,7 +219,8 @@ def sas_bp_autotune(descs: Sequence[N.SwathDesc], bufs: Sequence[SwathBuffers], 
     check(N.lib().sas_bp_autotune(arr, len(descs), io, C.byref(base), int(reps), _stream(device, stream),
                                   C.byref(best), C.byref(ms)), "sas_bp_autotune")
     return {"tile": (best.tile_x, best.tile_y, best.tile_z), "threads": best.threads,
-            "pings_per_chunk": best.pings_per_chunk, "ms": float(ms.value)}
+            "pings_per_chunk": best.pings_per_chunk, "elems_per_chunk": best.elems_per_chunk,
+            "ms": float(ms.value)}
 
 
 def sas_bp_set_kernel_timing(plan: Plan, enable: bool) -> None:

@@ -28,7 +28,7 @@
 namespace sasbp {
 typedef void (*ImageKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
 ImageKernelFn image_kernel_for(int layout, bool gate, int dt);
-int image_lds_bytes(int CP, int E, int W, int ROWS, bool gate);
+int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate);
 hipError_t launch_init(const Workspace& ws, hipStream_t st);
 hipError_t launch_cull(const Workspace& ws, int n_tiles, int TX, int TY, int TZ, int bucket_shift, hipStream_t st);
 hipError_t launch_order(const Workspace& ws, int n_tiles, int bucket_shift, hipStream_t st);
@@ -88,7 +88,7 @@ constexpr int kLdsMax = 160 * 1024;
 struct SwathPlan {
   sas_bp_swath_desc d;
   int ntx, nty, ntz, ntiles, tile0;
-  int W, CP, SC;
+  int W, CP, RC, SC;
   double half_diag, c_min;
 };
 
@@ -115,6 +115,7 @@ struct sas_bp_plan_s {
   int bucket_shift = 0;
   int lds_bytes = 0, adj_lds_bytes = 0;
   int grid = 0, adj_grid = 0;
+  int occ = 0;                     // image workgroups resident per CU
   int max_pe = 0;
   int max_p = 0;
   bool use_graph = true;
@@ -166,9 +167,9 @@ int validate(const sas_bp_swath_desc* d, int i) {
 
 // Tile shape from the lane-layout menu. An explicit tile (and optionally the
 // threads per workgroup) must match a menu entry; otherwise 2D images use
-// 64 x 32 pixel tiles on 512 threads (16 x 32 on 256 threads for small images,
-// so that they still give enough tiles to occupy the GPU) and 3D volumes use
-// 32 x 8 x 4 voxel tiles on 256 threads.
+// 64 x 32 pixel tiles (16 x 32 for small images, so that they still give
+// enough tiles to occupy the GPU) and 3D volumes use 32 x 8 x 4 voxel tiles,
+// all on 256 threads.
 int choose_tiling(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, Tiling* t) {
   bool any3d = false;
   long long pix = 0;
@@ -208,6 +209,13 @@ int choose_tiling(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, Ti
 
 constexpr int kLdsBudget = 64 * 1024;
 
+// LDS per workgroup that still lets the image kernel reach the occupancy its
+// register budget allows (kImageWaves waves per SIMD, four SIMDs per CU).
+int image_lds_target(int threads) {
+  const int per_cu = std::max(1, kImageWaves * 4 * 64 / threads);
+  return kLdsMax / per_cu - 512;
+}
+
 int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, const Tiling& t,
                  std::vector<SwathPlan>* out, int* n_tiles) {
   out->clear();
@@ -235,22 +243,51 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
     // one more entry of margin for FP32 rounding of the sample position.
     s.W = (int)std::ceil(4.0 * s.half_diag * d[i].f_s / s.c_min) + 6;
     if (s.W > 8192) return fail(SAS_BP_EUNSUPPORTED, "swath %d: tile spans %d samples; use a smaller tile", i, s.W);
-    int cp = (o && o->pings_per_chunk > 0) ? o->pings_per_chunk : 0;
+    const int E = d[i].n_elem;
+    const int ppc = (o && o->pings_per_chunk > 0) ? o->pings_per_chunk : 0;
+    const int epc = (o && o->elems_per_chunk > 0) ? std::min(o->elems_per_chunk, E) : 0;
     const bool gate = d[i].gate_half_angle > 0.0;
+    // adjoint chunk: whole pings
+    int cp = ppc;
     if (cp == 0) {
       cp = 1;
-      while (cp < 8 && image_lds_bytes(cp * 2, d[i].n_elem, s.W, rows, gate) <= kLdsBudget) cp *= 2;
+      while (cp < 8 && image_lds_bytes(cp * 2 * E, E, s.W, rows, gate) <= kLdsBudget) cp *= 2;
     }
-    if (image_lds_bytes(cp, d[i].n_elem, s.W, rows, gate) > kLdsMax - 1024)
-      return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d pings x %d elements x %d samples exceed LDS", i, cp,
-                  d[i].n_elem, s.W);
+    if (image_lds_bytes(cp * E, E, s.W, rows, gate) > kLdsMax - 1024)
+      return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d pings x %d elements x %d samples exceed LDS", i, cp, E, s.W);
     s.CP = cp;
+    // image chunk in records: explicit elements (part of a ping), explicit
+    // pings, or the largest of 8, 4, 2, 1 pings and then of E - 1, E - 2, ...
+    // records whose LDS lets the kernel reach its register-bound occupancy
+    // (such a chunk may straddle two pings)
+    int rc = 0;
+    if (epc > 0 && epc < E) rc = epc;
+    else if (ppc > 0) rc = ppc * E;
+    else {
+      const int target = image_lds_target(t.NT);
+      rc = 8 * E;
+      while (rc > E && image_lds_bytes(rc, E, s.W, rows, gate) > target) rc /= 2;
+      while (rc > 1 && image_lds_bytes(rc, E, s.W, rows, gate) > target) --rc;
+    }
+    // the geometry build keeps its list of partially gated records (one int
+    // each) in the window area, which must hold at least one ping's list
+    rc = std::max(rc, (E + 4 * (s.W + 1) - 1) / (4 * (s.W + 1)));
+    if (image_lds_bytes(rc, E, s.W, rows, gate) > kLdsMax - 1024)
+      return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d records x %d samples exceed LDS", i, rc, s.W);
+    s.RC = rc;
+    const int cap = (int)std::min<long long>(32, 4ll * rc * (s.W + 1) / E);   // pings whose list fits
+    if (cp > cap) {
+      if (ppc > 0) return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d pings per chunk need a larger image chunk", i, cp);
+      cp = cap;
+      s.CP = cp;
+    }
     // pings whose FP64 geometry is built at once: enough (ping, element)
     // records to keep every thread of the workgroup busy, a multiple of the
-    // chunk, and a partial-record list that fits the window area
-    int sc = std::max(1, std::min(32, 1024 / d[i].n_elem));
+    // adjoint chunk, and a partial-record list that fits the window area of
+    // both kernels
+    int sc = std::max(1, std::min(32, 1024 / E));
+    sc = std::min(sc, cap);
     sc = std::max(cp, sc / cp * cp);
-    sc = std::min(sc, 4 * cp * (s.W + 1) / cp * cp);
     s.SC = sc;
     out->push_back(s);
   }
@@ -299,6 +336,7 @@ SwathDev make_dev(const SwathPlan& s) {
   v.tile0 = s.tile0;
   v.W = s.W;
   v.CP = s.CP;
+  v.RC = s.RC;
   v.SC = s.SC;
   for (int a = 0; a < 3; ++a) {
     v.o[a] = s.d.origin[a];
@@ -449,7 +487,7 @@ int plan_sizes(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, Ti
   int lds = 0;
   for (const auto& s : *sw) {
     stride = std::max(stride, (size_t)geo_layout(s.SC, s.d.n_elem, rows, gate_any).bytes);
-    lds = std::max(lds, std::min(image_lds_bytes(s.CP, s.d.n_elem, s.W, rows, gate_any),
+    lds = std::max(lds, std::min(image_lds_bytes(s.RC, s.d.n_elem, s.W, rows, gate_any),
                                  adjoint_lds_bytes(s.CP, s.d.n_elem, s.W, rows, gate_any, t->NT)));
   }
   const int per_cu = std::max(1, std::min(8, kLdsMax / std::max(1, lds)));
@@ -549,7 +587,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
     p->max_p = std::max(p->max_p, s.d.n_ping);
   }
   for (const auto& s : sw) {
-    max_lds = std::max(max_lds, image_lds_bytes(s.CP, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any));
+    max_lds = std::max(max_lds, image_lds_bytes(s.RC, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any));
     max_adj_lds = std::max(max_adj_lds, adjoint_lds_bytes(s.CP, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any, t.NT));
   }
   p->max_pe = max_pe;
@@ -585,6 +623,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
     release(p);
     return fail(SAS_BP_EUNSUPPORTED, "tiling needs %d bytes of LDS; no workgroup fits", max_lds);
   }
+  p->occ = occ;
   p->grid = std::max(1, std::min(std::min(n_tiles, occ * prop.multiProcessorCount), lay.geo_slots));
   p->adj_grid = std::max(1, std::min(std::min(n_tiles, adj_occ * prop.multiProcessorCount), lay.geo_slots));
 
@@ -780,7 +819,7 @@ int sas_bp_plan_status(sas_bp_plan_t p) {
   return (h & kStatusNav) ? SAS_BP_ENAV : SAS_BP_OK;
 }
 
-int sas_bp_plan_info(sas_bp_plan_t p, int64_t info[8]) {
+int sas_bp_plan_info(sas_bp_plan_t p, int64_t info[10]) {
   if (!p || !info) return fail(SAS_BP_EINVAL, "NULL argument");
   info[0] = p->tiling.TX;
   info[1] = p->tiling.TY;
@@ -790,6 +829,8 @@ int sas_bp_plan_info(sas_bp_plan_t p, int64_t info[8]) {
   info[5] = p->lds_bytes;
   info[6] = p->grid;
   info[7] = p->tiling.NT;
+  info[8] = p->sw[0].RC;
+  info[9] = p->occ;
   return SAS_BP_OK;
 }
 
@@ -873,17 +914,22 @@ int sas_bp_autotune(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_sw
   double best_time = -1.0;
   sas_bp_options best_opt = cand;
   int last_err = SAS_BP_OK;
-  static const int kChunks[] = {1, 2, 4, 8};
+  // chunk candidates {pings, elements}: the automatic choice, whole pings,
+  // and parts of a ping
+  const int kChunks[][2] = {{0, 0}, {1, 0}, {2, 0}, {4, 0}, {8, 0}, {1, 3 * E / 4}, {1, E / 2}, {1, E / 4}};
   for (int l = 0; l < kNumLayouts; ++l) {
     const LaneLayout& L = kLayouts[l];
     if ((L.LZ > 1) != any3d) continue;
-    for (int cp : kChunks) {
+    for (const auto& ch : kChunks) {
+      if (ch[1] != 0 && (ch[1] < 1 || ch[1] >= E)) continue;
+      if (ch[1] == 3 * E / 4 && (ch[1] == E / 2 || ch[1] == E / 4)) continue;   // duplicate for tiny E
       sas_bp_options o = cand;
       o.tile_x = L.LX * L.K;
       o.tile_y = L.LY;
       o.tile_z = L.LZ;
       o.threads = L.LX * L.LY * L.LZ;
-      o.pings_per_chunk = cp;
+      o.pings_per_chunk = ch[0];
+      o.elems_per_chunk = ch[1];
       sas_bp_plan_t p = nullptr;
       if (sas_bp_plan(desc, n_swaths, &o, &p) != SAS_BP_OK) continue;   // does not fit: skip
       int e = sas_bp_image(p, io, n_swaths, stream);

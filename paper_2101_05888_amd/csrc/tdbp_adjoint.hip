@@ -30,7 +30,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 // Extra LDS after the image layout: per (slot, element, wave) 6 floats of
 // receiver/sound-speed sums and per (slot, wave) 4 floats of transmitter sums.
 __host__ __device__ inline int adjoint_red_offset(int CP, int E, int W, int ROWS, bool gate) {
-  return (lds_layout(CP, E, W, ROWS, gate).bytes + 15) & ~15;
+  return (lds_layout(CP * E, CP, W, ROWS, gate).bytes + 15) & ~15;
 }
 __host__ __device__ inline int adjoint_bytes(int CP, int E, int W, int ROWS, bool gate, int NW) {
   return adjoint_red_offset(CP, E, W, ROWS, gate) + CP * E * NW * 6 * 4 + CP * NW * 4 * 4;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
     const float fsf = (float)sw.fs;
     const float tpf = (float)(2.0 * 3.14159265358979323846 * sw.fc);
     const PingRange pr = prange[t];
-    const LdsLayout Ld = lds_layout(CP, E, W, ROWS, GATE);
+    const LdsLayout Ld = lds_layout(CP * E, CP, W, ROWS, GATE);
     const TxRec* ltx = reinterpret_cast<const TxRec*>(lds + Ld.off_tx);
     const RxRec* lrx = reinterpret_cast<const RxRec*>(lds + Ld.off_rx);
     const int* lrows = reinterpret_cast<const int*>(lds + Ld.off_rows);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
       const int cp = min(CP, sc - off);
       const int p0 = P0 + off;
       if (off > 0) __syncthreads();
-      load_chunk<NT, ROWS, GATE, DT>(lds, geo, sw, P0, off, cp, Ld, tid, lane, wave);
+      load_chunk<NT, ROWS, GATE, DT>(lds, geo, sw, P0, off * E, cp * E, off, cp, Ld, tid, lane, wave);
       for (int slot = 0; slot < cp; ++slot) {
         const TxRec tr = ltx[slot];
         const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);

@@ -25,6 +25,10 @@ constexpr LaneLayout kLayouts[] = {
 };
 constexpr int kNumLayouts = sizeof(kLayouts) / sizeof(kLayouts[0]);
 constexpr int kThreads = 256;    // helper kernels (cull, order, count, sharpness)
+// Waves per SIMD the image kernel's register budget is compiled for (512
+// VGPRs per SIMD lane shared by the resident waves); the plan sizes LDS
+// chunks so that this occupancy is not lost to LDS.
+constexpr int kImageWaves = 3;
 constexpr int kMaxElem = 256;
 
 // Per-swath constants and pointers, stored in the plan's workspace so that a
@@ -45,7 +49,8 @@ struct SwathDev {
   int ntx, nty, ntz;      // tiles per axis
   int tile0;              // index of this swath's first tile in the global tile list
   int W;                  // LDS window length per (ping, element), samples (without guard)
-  int CP;                 // pings staged per pass
+  int CP;                 // adjoint: pings staged per pass
+  int RC;                 // image: (ping, element) records staged per pass
   int SC;                 // pings whose geometry is built at once (a multiple of CP)
   double o[3], d[3];
   double fc, fs, t0;
@@ -98,6 +103,14 @@ __host__ __device__ inline GeoLayout geo_layout(int SC, int E, int ROWS, bool ga
   g.rows = o; o += gate ? (long long)SC * E * ROWS * 4 : 0;
   g.bytes = (o + 255) & ~255ll;
   return g;
+}
+
+// Most pings that a chunk of RC consecutive (ping, element) records, starting
+// at a multiple of RC, can touch when each ping has E records.
+__host__ __device__ inline int chunk_pings(int RC, int E) {
+  if (RC % E == 0) return RC / E;
+  if (E % RC == 0) return 1;
+  return (RC - 1) / E + 2;
 }
 
 constexpr int kBuckets = 64;

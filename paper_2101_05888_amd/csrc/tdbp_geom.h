@@ -200,9 +200,10 @@ __device__ __forceinline__ float2 load_sample(const void* base, size_t idx, int 
   }
 }
 
-// LDS layout for a chunk of CP pings with E elements and window length W:
-//   TxRec tx[CP]   RxRec rx[CP][E]   int n0[CP][E]   int rows[CP][E][ROWS] (gate only)
-//   float4 win[CP][E][W+1]: {(E[n] + E[n+1]) / 2, E[n+1] - E[n]} for n < W,
+// LDS layout for a chunk of NR (ping, element) records spanning at most NS
+// pings, with window length W:
+//   TxRec tx[NS]   RxRec rx[NR]   int n0[NR]   int rows[NR][ROWS] (gate only)
+//   float4 win[NR][W+1]: {(E[n] + E[n+1]) / 2, E[n+1] - E[n]} for n < W,
 //   entry W all zero.
 // Interpolation at sample position s is then one 16-byte read and two FMAs:
 // with n = round(s - 1/2) and w = (s - 1/2) - n in [-1/2, 1/2],
@@ -213,16 +214,16 @@ struct LdsLayout {
   int off_tx, off_rx, off_n0, off_rows, off_win, bytes;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int CP, int E, int W, int ROWS, bool gate) {
+__host__ __device__ inline LdsLayout lds_layout(int NR, int NS, int W, int ROWS, bool gate) {
   LdsLayout L;
   int o = 0;
-  L.off_tx = o;   o += CP * (int)sizeof(TxRec);
-  L.off_rx = o;   o += CP * E * (int)sizeof(RxRec);
-  L.off_n0 = o;   o += CP * E * 4;
+  L.off_tx = o;   o += NS * (int)sizeof(TxRec);
+  L.off_rx = o;   o += NR * (int)sizeof(RxRec);
+  L.off_n0 = o;   o += NR * 4;
   o = (o + 15) & ~15;
-  L.off_rows = o; o += gate ? CP * E * ROWS * 4 : 0;
+  L.off_rows = o; o += gate ? NR * ROWS * 4 : 0;
   o = (o + 15) & ~15;
-  L.off_win = o;  o += CP * E * (W + 1) * 16;
+  L.off_win = o;  o += NR * (W + 1) * 16;
   L.bytes = o;
   return L;
 }
@@ -353,8 +354,10 @@ __device__ __forceinline__ float2 load_guarded(const SwathDev& sw, size_t rowbas
   return load_sample(sw.echo, rowbase + (size_t)n, dt, scale);
 }
 
-// Echo windows of a chunk into LDS. Entry k of window r holds the midpoint
-// and the difference of E[n0+k] and E[n0+k+1] (k < W); entry W is zero.
+// Echo windows of a chunk of nrows records into LDS; record r of the chunk is
+// echo row row0 + r of the swath (rows in (ping, element) order). Entry k of
+// window r holds the midpoint and the difference of E[n0+k] and E[n0+k+1]
+// (k < W); entry W is zero.
 // Each wave takes B windows (rows r = (ping, element) of the chunk) at a
 // time and, per part of JS = 128 samples, issues the loads of all B rows
 // before consuming any: a lane loads two consecutive samples and takes the
@@ -363,7 +366,7 @@ __device__ __forceinline__ float2 load_guarded(const SwathDev& sw, size_t rowbas
 // the record read as zero.
 template <int NT, int DT>
 __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, const int* ln0, const SwathDev& sw,
-                                              int p0, int cp, int tid, int lane, int wave_id) {
+                                              long long row0, int nrows, int tid, int lane, int wave_id) {
   typedef typename PairLoad<DT>::type LoadT;
   constexpr int NW = NT / 64;
   constexpr int SPL = 2;                    // samples per lane per load
@@ -373,7 +376,6 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
   const int wave = __builtin_amdgcn_readfirstlane(wave_id);
   const int E = sw.E, W = sw.W, Ns = sw.Ns;
   const int J = (W + JS) / JS;              // parts per window (samples 0..W)
-  const int nrows = cp * E;
   const bool aligned = (Ns % SPL) == 0;
   const char* echo = reinterpret_cast<const char*>(sw.echo);
   const int lane_off = SPL * lane;
@@ -397,7 +399,7 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
         first[b] = __builtin_amdgcn_readfirstlane(ln0[r]) + part * JS;
         if (aligned && first[b] >= 0 && first[b] + JS < Ns) {
           fast |= 1u << b;
-          const size_t row = ((size_t)p0 * E + r) * (size_t)Ns + (size_t)first[b];
+          const size_t row = (size_t)(row0 + r) * (size_t)Ns + (size_t)first[b];
           q[b] = *reinterpret_cast<const LoadT*>(echo + (row + lane_off) * SB);
           if (lane == 63) tail[b] = load_sample(sw.echo, row + JS, DT, 1.0f);
         }
@@ -406,8 +408,8 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
       for (int b = 0; b < B; ++b) {
         if (!(live & (1u << b))) continue;
         const int r = r0 + b;
-        const size_t rowbase = ((size_t)p0 * E + r) * (size_t)Ns;
-        const float scale = DT == 0 ? 1.0f : sw.scale[p0 + r / E];
+        const size_t rowbase = (size_t)(row0 + r) * (size_t)Ns;
+        const float scale = DT == 0 ? 1.0f : sw.scale[(row0 + r) / E];
         const int n = first[b] + lane_off;
         float2 s[SPL + 1];
         if (fast & (1u << b)) {
@@ -434,36 +436,39 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
       }
     }
   }
-  for (int r = tid; r < cp * E; r += NT) lwin[(size_t)r * (W + 1) + W] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int r = tid; r < nrows; r += NT) lwin[(size_t)r * (W + 1) + W] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// One chunk of cp pings, [P0 + off, P0 + off + cp), of a run whose geometry
-// is in g: records, window starts and gate rows into LDS, then the echo
-// windows. Ends with a barrier.
+// One chunk of a run whose geometry is in g: the nr records q0 .. q0 + nr - 1
+// of the run (record q is ping P0 + q / E, element q % E), spanning the ns
+// pings s0 .. s0 + ns - 1 of the run. Records, window starts, transmitter
+// records and gate rows go into LDS, then the echo windows. Ends with a
+// barrier.
 template <int NT, int ROWS, bool GATE, int DT>
-__device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, const SwathDev& sw, int P0, int off,
-                                           int cp, const LdsLayout& L, int tid, int lane, int wave) {
-  const int E = sw.E;
+__device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, const SwathDev& sw, int P0, int q0,
+                                           int nr, int s0, int ns, const LdsLayout& L, int tid, int lane,
+                                           int wave) {
   TxRec* ltx = reinterpret_cast<TxRec*>(lds + L.off_tx);
   RxRec* lrx = reinterpret_cast<RxRec*>(lds + L.off_rx);
   int* ln0 = reinterpret_cast<int*>(lds + L.off_n0);
   float4* lwin = reinterpret_cast<float4*>(lds + L.off_win);
-  const RxRec* grec = g.rec + (size_t)off * E;
-  const int* gn0 = g.n0 + (size_t)off * E;
-  for (int r = tid; r < cp * E; r += NT) {
+  const RxRec* grec = g.rec + q0;
+  const int* gn0 = g.n0 + q0;
+  for (int r = tid; r < nr; r += NT) {
     lrx[r] = grec[r];
     ln0[r] = gn0[r];
   }
-  for (int s = tid; s < cp; s += NT) ltx[s] = g.tx[off + s];
+  for (int s = tid; s < ns; s += NT) ltx[s] = g.tx[s0 + s];
   if (GATE && sw.tan_g > 0.0) {
     // rows of records that are not partial hold stale values and are never read
-    const int4* src = reinterpret_cast<const int4*>(g.rows + (size_t)off * E * ROWS);
+    const int4* src = reinterpret_cast<const int4*>(g.rows + (size_t)q0 * ROWS);
     int4* dst = reinterpret_cast<int4*>(lds + L.off_rows);
-    for (int q = tid; q < cp * E * (ROWS / 4); q += NT) dst[q] = src[q];
+    for (int q = tid; q < nr * (ROWS / 4); q += NT) dst[q] = src[q];
   }
   __syncthreads();
-  stage_windows<NT, DT>(lwin, lrx, ln0, sw, P0 + off, cp, tid, lane, wave);
+  stage_windows<NT, DT>(lwin, lrx, ln0, sw, (long long)P0 * sw.E + q0, nr, tid, lane, wave);
   __syncthreads();
 }
+
 
 }  // namespace sasbp

@@ -189,7 +189,8 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
 // The read-only tables are separate restrict-qualified arguments so that the
 // compiler may read them through the scalar cache.
 template <int L, bool GATE, int DT>
-__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) void image_kernel(
+__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ)
+__attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel(
     Workspace ws, const SwathDev* __restrict__ swaths, const int* __restrict__ order,
     const int* __restrict__ tile_swath, const PingRange* __restrict__ prange, int n_tiles) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
     const int t = __builtin_amdgcn_readfirstlane(order[item]);
     const int s = __builtin_amdgcn_readfirstlane(tile_swath[t]);
     const SwathDev& sw = swaths[s];
-    const int E = sw.E, W = sw.W, CP = sw.CP;
+    const int E = sw.E, W = sw.W, RC = sw.RC;
     const int lt = t - sw.tile0;
     const int tix = lt % sw.ntx, tiy = (lt / sw.ntx) % sw.nty, tiz = lt / (sw.ntx * sw.nty);
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
     const float fs_c = (float)(sw.fs / c);
     const float fc_c = (float)(sw.fc / c);
     const PingRange pr = prange[t];
-    const LdsLayout Ld = lds_layout(CP, E, W, ROWS, GATE);
+    const LdsLayout Ld = lds_layout(RC, chunk_pings(RC, E), W, ROWS, GATE);
     const TxRec* ltx = reinterpret_cast<const TxRec*>(lds + Ld.off_tx);
     const RxRec* lrx = reinterpret_cast<const RxRec*>(lds + Ld.off_rx);
     const int* lrows = reinterpret_cast<const int*>(lds + Ld.off_rows);
@@ -252,49 +253,52 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
       const int sc = min(sw.SC, pr.hi - P0 + 1);
       __syncthreads();
       build_geometry<NT, TX, LY, LZ, GATE>(geo, lpart, &s_npart, ws, sw, c, C, P0, sc, x0, y0, z0, tid);
-     for (int off = 0; off < sc; off += CP) {
-      const int cp = min(CP, sc - off);
-      if (off > 0) __syncthreads();
-      load_chunk<NT, ROWS, GATE, DT>(lds, geo, sw, P0, off, cp, Ld, tid, lane, wave);
-      for (int slot = 0; slot < cp; ++slot) {
-        const TxRec tr = ltx[slot];
-        const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
-        float dT[K];
+      // chunks of RC records (ping-major) of the run; a chunk may hold part
+      // of a ping, a whole ping or several pings
+      for (int q0 = 0; q0 < sc * E; q0 += RC) {
+        const int nr = min(RC, sc * E - q0);
+        const int sa = q0 / E, sb = (q0 + nr - 1) / E;
+        if (q0 > 0) __syncthreads();
+        load_chunk<NT, ROWS, GATE, DT>(lds, geo, sw, P0, q0, nr, sa, sb - sa + 1, Ld, tid, lane, wave);
+        for (int slot = sa; slot <= sb; ++slot) {
+          const TxRec tr = ltx[slot - sa];
+          const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
+          float dT[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float num = fmaf(tr.ux2, dx[k], tyz + dsq[k]);
-          const float sq = __builtin_amdgcn_sqrtf(tr.d0sq + num);
-          dT[k] = num * __builtin_amdgcn_rcpf(tr.d0 + sq);
-        }
-        for (int e = 0; e < E; ++e) {
-          const int r = slot * E + e;
-          const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(lrx[r].q0.w));
-          if (f & kFlagSkip) continue;
-          const RxRec rec = lrx[r];
-          const float4* win = lwin + (size_t)r * (W + 1);
-          if (!GATE || (f & kFlagFull)) {
-            if (f & kFlagDeg4)
-              accumulate<K, LX, 4, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
-            else if (f & kFlagPoly)
-              accumulate<K, LX, 5, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
-            else
-              accumulate<K, LX, 0, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
-          } else {
-            const int v = lrows[r * ROWS + row];
-            const int a = row_lo(v), b = row_hi(v);
-            if (f & kFlagDeg4)
-              accumulate<K, LX, 4, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
-                                         acci);
-            else if (f & kFlagPoly)
-              accumulate<K, LX, 5, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
-                                         acci);
-            else
-              accumulate<K, LX, 0, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
-                                         acci);
+          for (int k = 0; k < K; ++k) {
+            const float num = fmaf(tr.ux2, dx[k], tyz + dsq[k]);
+            const float sq = __builtin_amdgcn_sqrtf(tr.d0sq + num);
+            dT[k] = num * __builtin_amdgcn_rcpf(tr.d0 + sq);
+          }
+          const int r_lo = max(slot * E, q0) - q0, r_hi = min(slot * E + E, q0 + nr) - q0;
+          for (int r = r_lo; r < r_hi; ++r) {
+            const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(lrx[r].q0.w));
+            if (f & kFlagSkip) continue;
+            const RxRec rec = lrx[r];
+            const float4* win = lwin + (size_t)r * (W + 1);
+            if (!GATE || (f & kFlagFull)) {
+              if (f & kFlagDeg4)
+                accumulate<K, LX, 4, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
+              else if (f & kFlagPoly)
+                accumulate<K, LX, 5, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
+              else
+                accumulate<K, LX, 0, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
+            } else {
+              const int v = lrows[r * ROWS + row];
+              const int a = row_lo(v), b = row_hi(v);
+              if (f & kFlagDeg4)
+                accumulate<K, LX, 4, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
+                                           acci);
+              else if (f & kFlagPoly)
+                accumulate<K, LX, 5, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
+                                           acci);
+              else
+                accumulate<K, LX, 0, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, lx - a, b - a, accr,
+                                           acci);
+            }
           }
         }
       }
-     }
     }
     // write the tile once
     const int iy = y0 + ly, iz = z0 + lz;
@@ -344,8 +348,8 @@ ImageKernelFn image_kernel_for(int layout, bool gate, int dt) {
   }
 }
 
-int image_lds_bytes(int CP, int E, int W, int ROWS, bool gate) {
-  return lds_layout(CP, E, W, ROWS, gate).bytes;
+int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate) {
+  return lds_layout(RC, chunk_pings(RC, E), W, ROWS, gate).bytes;
 }
 
 hipError_t launch_init(const Workspace& ws, hipStream_t st) {

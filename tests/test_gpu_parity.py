@@ -94,6 +94,21 @@ def test_ping_chunking_is_bitwise_neutral_within_a_tiling(api, cp):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("epc", [3, 4, 7])
+def test_element_chunks_are_bitwise_neutral_and_match_oracle(api, epc):
+    # chunks of 3 and 7 records straddle pings (8 elements each), 4 split one
+    # ping in two; gated geometry so that partially gated rows cross chunks
+    print(f"elements per chunk {epc}", flush=True)
+    scn, echo = _case("c2", n_ping=24, n_elem=8, nx=150, ny=70, n_sample=4096, n_scat=30, n_speckle=100)
+    a, plan, _ = gpu_image(api, scn, echo, elems_per_chunk=epc)
+    assert plan.info()["records_per_chunk"] == epc
+    b, _, _ = gpu_image(api, scn, echo, pings_per_chunk=1)
+    assert np.array_equal(a, b)
+    ref = oracle_image(scn, echo.numpy()).reshape(a.shape)
+    r, ph = report(f"epc{epc}", a, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+
+
 def test_graph_replay_equals_direct_launch_and_is_deterministic(api):
     scn, echo = _case("c2", n_ping=40, n_elem=4, nx=96, ny=64, n_sample=4096, n_scat=20, n_speckle=50)
     a, plan, buf = gpu_image(api, scn, echo, use_graph=True)
@@ -128,7 +143,7 @@ def test_autotune_choice_is_a_valid_tiling_and_cached(api):
     d = desc_for(api, scn)
     buf = buffers_for(api, scn, echo)
     best = api.sas_bp_autotune([d], [buf], reps=2)
-    assert best["ms"] > 0.0 and best["pings_per_chunk"] in (1, 2, 4, 8)
+    assert best["ms"] > 0.0 and best["pings_per_chunk"] in (0, 1, 2, 4, 8)
     again = api.sas_bp_autotune([d], [buf], reps=2)
     assert again["ms"] == 0.0 and {k: v for k, v in again.items() if k != "ms"} == \
         {k: v for k, v in best.items() if k != "ms"}
@@ -136,7 +151,12 @@ def test_autotune_choice_is_a_valid_tiling_and_cached(api):
     img, plan, _ = gpu_image(api, scn, echo, **kw)
     info = plan.info()
     assert (info["tile_x"], info["tile_y"], info["tile_z"]) == tuple(best["tile"])
-    assert info["pings_per_chunk"] == best["pings_per_chunk"] and info["threads"] == best["threads"]
+    assert info["threads"] == best["threads"] and info["workgroups_per_cu"] >= 1
+    ppc, epc = best["pings_per_chunk"], best["elems_per_chunk"]
+    if 0 < epc < d.n_elem:
+        assert info["records_per_chunk"] == epc
+    elif ppc > 0:
+        assert info["pings_per_chunk"] == ppc and info["records_per_chunk"] == ppc * d.n_elem
     r, ph = report("autotuned", img, oracle_image(scn, echo.numpy()).reshape(img.shape))
     assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
 
