@@ -30,9 +30,10 @@ namespace sasbp {
 struct RxRec {
   float4 q0, q1, q2;
 };
-// Transmitter record per ping: 2 u_T (x, y, z), d0_T, d0_T^2.
+// Transmitter record per ping: 2 u_T (x, y, z), d0_T, d0_T^2, and the
+// ping's dequantisation scale for 16-bit echo storage (1 for FP32).
 struct TxRec {
-  float ux2, uy2, uz2, d0, d0sq, pad0, pad1, pad2;
+  float ux2, uy2, uz2, d0, d0sq, scale, pad1, pad2;
 };
 
 constexpr unsigned kFlagSkip = 1u;   // no pixel of the tile is gated in (or bad navigation)
@@ -132,7 +133,8 @@ __device__ __forceinline__ void make_tx_record(const SwathDev& sw, const double 
   rec->uz2 = (float)(2.0 * u2);
   rec->d0 = (float)d0;
   rec->d0sq = (float)(d0 * d0);
-  rec->pad0 = rec->pad1 = rec->pad2 = 0.0f;
+  rec->scale = sw.dtype == 0 ? 1.0f : sw.scale[p];
+  rec->pad1 = rec->pad2 = 0.0f;
 }
 
 // Exact gate interval of tile row (y, z) for (ping p, element e): local x indices
@@ -355,9 +357,10 @@ __device__ __forceinline__ float2 load_guarded(const SwathDev& sw, size_t rowbas
 }
 
 // Echo windows of a chunk of nrows records into LDS; record r of the chunk is
-// echo row row0 + r of the swath (rows in (ping, element) order). Entry k of
-// window r holds the midpoint and the difference of E[n0+k] and E[n0+k+1]
-// (k < W); entry W is zero.
+// echo row row0 + r of the swath (rows in (ping, element) order), element e0
+// + r of the chunk's first ping when r < E - e0, and its ping's transmitter
+// record is ltx[(e0 + r) / E]. Entry k of window r holds the midpoint and the
+// difference of E[n0+k] and E[n0+k+1] (k < W); entry W is zero.
 // Each wave takes B windows (rows r = (ping, element) of the chunk) at a
 // time and, per part of JS = 128 samples, issues the loads of all B rows
 // before consuming any: a lane loads two consecutive samples and takes the
@@ -365,8 +368,9 @@ __device__ __forceinline__ float2 load_guarded(const SwathDev& sw, size_t rowbas
 // bookkeeping is wave-uniform and stays in scalar registers. Samples outside
 // the record read as zero.
 template <int NT, int DT>
-__device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, const int* ln0, const SwathDev& sw,
-                                              long long row0, int nrows, int tid, int lane, int wave_id) {
+__device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, const int* ln0, const TxRec* ltx,
+                                              const SwathDev& sw, long long row0, int e0, int nrows, int tid,
+                                              int lane, int wave_id) {
   typedef typename PairLoad<DT>::type LoadT;
   constexpr int NW = NT / 64;
   constexpr int SPL = 2;                    // samples per lane per load
@@ -409,7 +413,7 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
         if (!(live & (1u << b))) continue;
         const int r = r0 + b;
         const size_t rowbase = (size_t)(row0 + r) * (size_t)Ns;
-        const float scale = DT == 0 ? 1.0f : sw.scale[(row0 + r) / E];
+        const float scale = DT == 0 ? 1.0f : ltx[(e0 + r) / E].scale;
         const int n = first[b] + lane_off;
         float2 s[SPL + 1];
         if (fast & (1u << b)) {
@@ -466,7 +470,7 @@ __device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, con
     for (int q = tid; q < nr * (ROWS / 4); q += NT) dst[q] = src[q];
   }
   __syncthreads();
-  stage_windows<NT, DT>(lwin, lrx, ln0, sw, (long long)P0 * sw.E + q0, nr, tid, lane, wave);
+  stage_windows<NT, DT>(lwin, lrx, ln0, ltx, sw, (long long)P0 * sw.E + q0, q0 - s0 * sw.E, nr, tid, lane, wave);
   __syncthreads();
 }
 

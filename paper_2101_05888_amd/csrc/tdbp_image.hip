@@ -254,21 +254,26 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
       __syncthreads();
       build_geometry<NT, TX, LY, LZ, GATE>(geo, lpart, &s_npart, ws, sw, c, C, P0, sc, x0, y0, z0, tid);
       // chunks of RC records (ping-major) of the run; a chunk may hold part
-      // of a ping, a whole ping or several pings
+      // of a ping, a whole ping or several pings. The transmitter leg dT of
+      // a ping split over two chunks is formed once.
+      float dT[K];
+      int dT_slot = -1;
       for (int q0 = 0; q0 < sc * E; q0 += RC) {
         const int nr = min(RC, sc * E - q0);
         const int sa = q0 / E, sb = (q0 + nr - 1) / E;
         if (q0 > 0) __syncthreads();
         load_chunk<NT, ROWS, GATE, DT>(lds, geo, sw, P0, q0, nr, sa, sb - sa + 1, Ld, tid, lane, wave);
         for (int slot = sa; slot <= sb; ++slot) {
-          const TxRec tr = ltx[slot - sa];
-          const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
-          float dT[K];
+          if (slot != dT_slot) {
+            const TxRec tr = ltx[slot - sa];
+            const float tyz = fmaf(tr.uy2, dyl, tr.uz2 * dzl);
 #pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const float num = fmaf(tr.ux2, dx[k], tyz + dsq[k]);
-            const float sq = __builtin_amdgcn_sqrtf(tr.d0sq + num);
-            dT[k] = num * __builtin_amdgcn_rcpf(tr.d0 + sq);
+            for (int k = 0; k < K; ++k) {
+              const float num = fmaf(tr.ux2, dx[k], tyz + dsq[k]);
+              const float sq = __builtin_amdgcn_sqrtf(tr.d0sq + num);
+              dT[k] = num * __builtin_amdgcn_rcpf(tr.d0 + sq);
+            }
+            dT_slot = slot;
           }
           const int r_lo = max(slot * E, q0) - q0, r_hi = min(slot * E + E, q0 + nr) - q0;
           for (int r = r_lo; r < r_hi; ++r) {
