@@ -76,10 +76,15 @@ def committed_counters():
 
 def issue_roofline(kernel_ms: float):
     """Instruction-issue roofline of the image kernel: VALU wave-instructions
-    per launch (committed counters) per CU clock, against the highest rate
-    measured on this GPU for independent FP32 FMA chains, 1.14 wave-instructions
-    per CU clock at 8 waves per SIMD (0.75 at the 2 waves per SIMD the image
-    kernel runs with), 256 CUs at 2.4 GHz."""
+    per launch (committed counters) per CU clock (256 CUs at 2.4 GHz).
+
+    The peak is the architectural FP32 VALU issue rate implied by the
+    157.3 TFLOP/s vector peak: 157.3e12 / (2 flops x 64 lanes x 256 CUs x
+    2.4 GHz) = 2 wave64 instructions per CU per clock, without packed math.
+    Also reported against what independent FP32 FMA chains reach on this GPU
+    (the issue_probe microbenchmark) at 8 waves per SIMD: 1.44 with one VGPR
+    operand, 1.18 with three (1.00 with three at the 3 waves per SIMD the
+    image kernel runs with)."""
     kv = committed_counters()
     try:
         valu = float(kv["valu_wave_instructions_per_launch"])
@@ -87,10 +92,13 @@ def issue_roofline(kernel_ms: float):
     except (KeyError, ValueError):
         return None
     rate = valu / (kernel_ms * 1e-3 * 2.4e9 * 256)
-    peak = 1.14
+    peak = 2.0
+    ceilings = {"fma_one_vgpr_operand_8_waves": 1.44, "fma_three_vgpr_operands_8_waves": 1.18,
+                "fma_three_vgpr_operands_3_waves": 1.00}
     return {"valu_wave_instructions": valu, "trans_wave_instructions": trans,
             "achieved_wave_instr_per_cu_clock": rate, "peak_wave_instr_per_cu_clock": peak,
-            "frac": rate / peak}
+            "frac": rate / peak, "measured_fma_ceilings": ceilings,
+            "frac_of_measured_ceilings": {k: rate / v for k, v in ceilings.items()}}
 
 
 def measured_traffic():
