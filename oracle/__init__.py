@@ -8,13 +8,15 @@ loudly when its HIP library is missing.
 The oracle is a plain, slow, obviously correct NumPy transcription of the
 backprojection sum that inverts Eq. 1 (Sec. II-A), with the beam gate of
 Sec. II-C evaluated per term, and of its gradient with respect to the
-navigation and the sound speed. It shares no code with the HIP path.
+navigation and the sound speed, and of its linear adjoint with respect to the
+echo (reprojection). It shares no code with the HIP path.
 """
 from .tdbp import (pixel_points, backproject, backproject_image, gated_term_count,
-                   gated_term_count_rows, vjp, vjp_segment_bound, sharpness,
+                   gated_term_count_rows, vjp, vjp_segment_bound, reproject, sharpness,
                    sharpness_cotangent)
 from .metrics import rel_l2, phase_error_mrad
 
 __all__ = ["pixel_points", "backproject", "backproject_image", "gated_term_count",
-           "gated_term_count_rows", "vjp", "vjp_segment_bound", "sharpness", "sharpness_cotangent",
+           "gated_term_count_rows", "vjp", "vjp_segment_bound", "reproject", "sharpness",
+           "sharpness_cotangent",
            "rel_l2", "phase_error_mrad"]

@@ -285,6 +285,47 @@ def vjp_segment_bound(echo, tx, rx, c, fc, fs, t0, points, gbar, gate_half_angle
     return b_tx, b_rx, b_c
 
 
+def reproject(ybar, tx, rx, c, fc, fs, t0, points, n_sample, gate_half_angle=0.0):
+    """Linear adjoint of the image with respect to the echo (reprojection).
+
+    The image is complex-linear in the echo cube: I = A E, with one row of A
+    per point and, per term (point p, ping i, element e) with g = 1, the entry
+    (1 - w) exp(+j 2 pi f_c tau) on sample n = floor(u) of row (i, e) and
+    w exp(+j 2 pi f_c tau) on sample n + 1 (samples outside the record have no
+    entry: the zero extension). This returns A^H Y for Y at the points, an
+    echo-shaped complex128 [P, E, n_sample]. For Y = Gbar (dJ/dRe I +
+    j dJ/dIm I) it is the gradient of J with respect to the echo in the same
+    convention.
+    """
+    tx = np.asarray(tx, dtype=np.float64)
+    rx = np.asarray(rx, dtype=np.float64)
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    ybar = np.asarray(ybar, dtype=np.complex128).reshape(-1)
+    P, E = rx.shape[0], rx.shape[1]
+    out = np.zeros((P, E, int(n_sample)), dtype=np.complex128)
+    sin_g = math.sin(gate_half_angle) if gate_half_angle > 0 else None
+    for i in range(P):
+        dT = np.sqrt(((pts - tx[i]) ** 2).sum(axis=1))
+        gT = _gate(pts[:, 0] - tx[i, 0], dT, sin_g) if sin_g is not None else None
+        for e in range(E):
+            R = rx[i, e]
+            dR = np.sqrt(((pts - R) ** 2).sum(axis=1))
+            tau = (dT + dR) / c
+            u = (tau - t0) * fs
+            nf = np.floor(u)
+            w = u - nf
+            n = nf.astype(np.int64)
+            v = np.exp(-1j * 2.0 * np.pi * fc * tau) * ybar
+            if sin_g is not None:
+                v = np.where(gT & _gate(pts[:, 0] - R[0], dR, sin_g), v, 0.0)
+            row = out[i, e]
+            lo = (n >= 0) & (n < n_sample)
+            hi = (n + 1 >= 0) & (n + 1 < n_sample)
+            np.add.at(row, n[lo], (1.0 - w[lo]) * v[lo])
+            np.add.at(row, n[hi] + 1, w[hi] * v[hi])
+    return out
+
+
 def sharpness(img) -> float:
     """S = sum |I|^4 / (sum |I|^2)^2."""
     m2 = np.abs(np.asarray(img, dtype=np.complex128)) ** 2

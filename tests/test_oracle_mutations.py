@@ -1,8 +1,9 @@
 """The oracle's pins must reject plausible mistakes.
 
 Each case plants one slip in a private copy of the oracle's source (on the
-CPU, never in the HIP path) and checks that the brute-force pin (P1) or the
-lone-scatterer closed form (P2) rejects the mutated oracle.
+CPU, never in the HIP path) and checks that the brute-force pin (P1) rejects
+the mutated backprojection, or that the adjoint identity against the
+unmutated backprojection (P10) rejects the mutated reprojection.
 """
 import inspect
 import math
@@ -56,3 +57,28 @@ def test_unmutated_copy_passes():
     pts = g["grid"].points()
     got = mod.backproject(g["echo"], g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, g["gate"])
     assert np.linalg.norm(got - _brute_mp(g, pts)) <= 1e-12 * np.linalg.norm(got)
+
+
+REPROJECT_MUTATIONS = {
+    "phase_not_conjugated": ("v = np.exp(-1j * 2.0 * np.pi * fc * tau) * ybar",
+                             "v = np.exp(1j * 2.0 * np.pi * fc * tau) * ybar"),
+    "weights_swapped": ("np.add.at(row, n[lo], (1.0 - w[lo]) * v[lo])", "np.add.at(row, n[lo], w[lo] * v[lo])"),
+    "upper_tap_off_by_one": ("np.add.at(row, n[hi] + 1, w[hi] * v[hi])", "np.add.at(row, n[hi], w[hi] * v[hi])"),
+    "gate_ignored": ("v = np.where(gT & _gate(pts[:, 0] - R[0], dR, sin_g), v, 0.0)", "v = v"),
+    "cotangent_conjugated": ("* ybar\n", "* np.conj(ybar)\n"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(REPROJECT_MUTATIONS))
+def test_adjoint_identity_rejects_reprojection_mutation(name):
+    old, new = REPROJECT_MUTATIONS[name]
+    mod = _mutant(old, new)
+    g = _tiny_geometry(gate_deg=12.0, ns=48, t0=4.95e-3, P=4, E=3)
+    pts = g["grid"].points()
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=g["echo"].shape) + 1j * rng.normal(size=g["echo"].shape)
+    y = rng.normal(size=pts.shape[0]) + 1j * rng.normal(size=pts.shape[0])
+    ax = tdbp.backproject(x, g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, g["gate"])
+    ahy = mod.reproject(y, g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, x.shape[2], g["gate"])
+    lhs, rhs = np.vdot(ax, y), np.vdot(x.ravel(), ahy.ravel())
+    assert abs(lhs - rhs) > 1e-9 * abs(lhs), f"mutation {name} survived the adjoint identity"

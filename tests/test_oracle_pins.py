@@ -12,7 +12,10 @@ inversion statement of Sec. II-A; gate of Sec. II-C):
 * P6  the interpolator on echoes where it is exact (linear, single impulse);
 * P7  the analytic gradient against central finite differences, and the
       sharpness objective's identities;
-* P8  the gated-term count from per-row cone intervals.
+* P8  the gated-term count from per-row cone intervals;
+* P10 reprojection is the conjugate transpose of backprojection: the
+      adjoint identity <A x, y> = <x, A^H y> and, element by element, the
+      matrix A assembled column by column from the (pinned) backprojection.
 
 A plausible slip anywhere in the oracle (a dropped path leg, a wrong phase
 sign, transposed tx/rx, an off-by-one tap, a gate on the wrong axis) fails at
@@ -380,6 +383,43 @@ def test_p8_gated_count_3d_rows():
     brute = oracle.gated_term_count(scn.tx, scn.rx, gr.points(), gate)
     rows = oracle.gated_term_count_rows(scn.tx, scn.rx, gr.origin, gr.spacing, gr.n, gate)
     assert brute == rows and brute > 0
+
+
+# ------------------------------------------------------------------ P10 ----
+
+def _inner(a, b):
+    return np.vdot(np.asarray(a).ravel(), np.asarray(b).ravel())
+
+
+@pytest.mark.parametrize("gate_deg,t0", [(0.0, 1.5e-3), (12.0, 1.5e-3), (12.0, 4.95e-3)])
+def test_p10_reprojection_satisfies_the_adjoint_identity(gate_deg, t0):
+    # t0 = 4.95 ms puts part of the delays past the record end (taps dropped)
+    g = _tiny_geometry(gate_deg=gate_deg, t0=t0, ns=48, P=4, E=3)
+    pts = g["grid"].points()
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=g["echo"].shape) + 1j * rng.normal(size=g["echo"].shape)
+    y = rng.normal(size=pts.shape[0]) + 1j * rng.normal(size=pts.shape[0])
+    ax = oracle.backproject(x, g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, g["gate"])
+    ahy = oracle.reproject(y, g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, x.shape[2], g["gate"])
+    lhs, rhs = _inner(ax, y), _inner(x, ahy)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs) and abs(lhs) > 0
+
+
+def test_p10_reprojection_equals_the_assembled_conjugate_transpose():
+    g = _tiny_geometry(gate_deg=12.0, t0=4.95e-3, ns=20, P=2, E=2)
+    pts = g["grid"].points()[::3]
+    P, E, ns = 2, 2, 20
+    # column (i, e, n) of A is the image of a unit echo at that sample
+    A = np.zeros((pts.shape[0], P * E * ns), dtype=np.complex128)
+    for col in range(P * E * ns):
+        unit = np.zeros((P, E, ns), dtype=np.complex128)
+        unit.reshape(-1)[col] = 1.0
+        A[:, col] = oracle.backproject(unit, g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, g["gate"])
+    assert np.count_nonzero(A) > 0
+    y = np.random.default_rng(5).normal(size=(pts.shape[0], 2)) @ np.array([1.0, 1j])
+    got = oracle.reproject(y, g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, ns, g["gate"])
+    want = (A.conj().T @ y).reshape(P, E, ns)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
 
 
 def test_multiprocess_oracle_matches_single():
