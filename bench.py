@@ -175,6 +175,32 @@ def _desc(api, scn):
                           scn.t0, scn.gate_half_angle)
 
 
+def reprojection_leg(api, plan, buf, useful: int, steps: int, warmup: int, forward_kernel_ms: float) -> dict:
+    """Reprojection (the linear adjoint of the image in the echo) on the same
+    swath and plan: the FP32 image as the image-side input, the whole echo cube
+    as output. Also the adjoint identity <A x, y> = <x, A^H y> between the
+    timed forward and adjoint at full size, in FP64 on the host."""
+    y = buf.image.clone()
+    out = torch.empty_like(buf.echo)
+    api.sas_bp_set_kernel_timing(plan, True)
+    for _ in range(warmup):
+        api.sas_bp_reproject(plan, [buf], [y], [out])
+    api.sas_bp_kernel_time(plan)
+    ms = time_steps(lambda: api.sas_bp_reproject(plan, [buf], [y], [out]), steps, 0)
+    k_total, k_n = api.sas_bp_kernel_time(plan)
+    api.sas_bp_set_kernel_timing(plan, False)
+    kms = k_total / k_n
+    lhs = torch.vdot(buf.image.reshape(-1).to(torch.complex128), y.reshape(-1).to(torch.complex128)).item()
+    rhs = torch.vdot(buf.echo.reshape(-1).to(torch.complex128), out.reshape(-1).to(torch.complex128)).item()
+    ident = abs(lhs - rhs) / abs(lhs)
+    log(f"reprojection: {ms:.3f} ms/call, kernel {kms:.3f} ms ({kms / forward_kernel_ms:.2f}x the image kernel), "
+        f"adjoint identity {ident:.2e}")
+    del out, y
+    return {"ms_per_call": ms, "kernel_ms": kms, "useful_updates_per_s": useful / (kms * 1e-3),
+            "vs_image_kernel": kms / forward_kernel_ms, "adjoint_identity_rel": ident,
+            "note": "float atomics: not bitwise reproducible"}
+
+
 def autofocus_leg(api, steps: int, warmup: int) -> dict:
     """One autofocus iteration on the differentiable workload (256 pings x 16
     receivers, 1024 x 1024 pixels, no gate): image, sharpness and its
@@ -271,6 +297,7 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autofocus", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-reprojection", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -282,6 +309,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
+        args.no_reprojection = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -375,6 +403,8 @@ def main() -> int:
             del q, b2
         out["mixed"] = mixed
 
+    if not args.no_reprojection:
+        out["reprojection"] = reprojection_leg(api, plan, buf, useful, max(3, args.steps // 4), 1, kernel_ms)
     if not args.no_autofocus:
         out["autofocus_step"] = autofocus_leg(api, args.steps, args.warmup)
     if not args.no_batched:

@@ -144,6 +144,28 @@ int sas_bp_adjoint(sas_bp_plan_t plan, const sas_bp_swath_io* io,
                    double* const* grad_rx, double* const* grad_c,
                    int n_swaths, void* stream);
 
+/* Reprojection: the linear adjoint of the image with respect to the echo
+ * (the transpose of the backprojection sum; the echo-to-image map of Eq. 1
+ * inverted, Sec. II-A, is complex-linear, I = A E). For an image-shaped
+ * complex64 Y per swath (image_in[s], layout of sas_bp_swath_io.image) it
+ * writes echo_out[s] = A^H Y, complex64 [P][E][N_s] in the echo layout,
+ * overwritten: every term with g = 1 adds
+ *   (1 - w) exp(-j 2 pi f_c tau) Y(p)   to sample n = floor(u)
+ *   w       exp(-j 2 pi f_c tau) Y(p)   to sample n + 1
+ * of row (ping, element), for samples inside the record. With Y = Gbar
+ * (dJ/dRe I + j dJ/dIm I) this is dJ/dRe E + j dJ/dIm E. Navigation, c and
+ * the plan's tiling are those of sas_bp_image (io as for sas_bp_image; its
+ * echo and image are not read or written). The output is the same for
+ * 16-bit echo plans (the gradient with respect to the dequantised echo).
+ * Within a tile of pixels, contributions are summed in fixed point (int32,
+ * resolution about 1e-6 of the tile's largest |Re Y|, |Im Y|); across tiles
+ * with float atomics, so results agree with the definition to FP32 rounding
+ * but are not bitwise reproducible. A tile whose Y holds a non-finite value
+ * contributes nothing. Buffers must be 8-byte aligned device memory.
+ * Asynchronous on `stream`. */
+int sas_bp_reproject(sas_bp_plan_t plan, const sas_bp_swath_io* io, const void* const* image_in,
+                     void* const* echo_out, int n_swaths, void* stream);
+
 /* Exact number of (pixel, ping, element) terms with g = 1 for each swath,
  * from the same per-row cone intervals the image kernels use. Writes
  * counts[s] (host memory) and synchronises the stream. */

@@ -184,6 +184,21 @@ def sas_bp_adjoint(plan: Plan, bufs: Sequence[SwathBuffers], grad_images: Sequen
           "sas_bp_adjoint")
 
 
+def sas_bp_reproject(plan: Plan, bufs: Sequence[SwathBuffers], images_in: Sequence[torch.Tensor],
+                     echoes_out: Sequence[torch.Tensor], stream=None) -> None:
+    """Linear adjoint of the image with respect to the echo: echoes_out[s]
+    (complex64 [P, E, N_s], overwritten) = A^H images_in[s]."""
+    arr = _io(plan, bufs)
+    n = len(bufs)
+    for i, d in enumerate(plan.descs):
+        _need(images_in[i], f"images_in[{i}]", torch.complex64, (d.n[2], d.n[1], d.n[0]), plan.device)
+        _need(echoes_out[i], f"echoes_out[{i}]", torch.complex64, (d.n_ping, d.n_elem, d.n_sample), plan.device)
+    P = C.c_void_p
+    yi = (P * n)(*[t.data_ptr() for t in images_in])
+    eo = (P * n)(*[t.data_ptr() for t in echoes_out])
+    check(N.lib().sas_bp_reproject(plan.handle, arr, yi, eo, n, _stream(plan.device, stream)), "sas_bp_reproject")
+
+
 def sas_bp_useful_updates(plan: Plan, bufs: Sequence[SwathBuffers], stream=None) -> list:
     arr = _io(plan, bufs)
     out = (C.c_int64 * len(bufs))()

@@ -44,6 +44,14 @@ hipError_t launch_adjoint(AdjointKernelFn fn, const Workspace& ws, int n_tiles, 
                           hipStream_t st);
 hipError_t adjoint_occupancy(AdjointKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu);
 hipError_t set_adjoint_lds_limit(AdjointKernelFn fn, int lds_bytes);
+
+typedef void (*ReprojectKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
+ReprojectKernelFn reproject_kernel_for(int layout, bool gate);
+hipError_t launch_reproject(ReprojectKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads,
+                            int lds_bytes, hipStream_t st);
+hipError_t launch_zero_rows(void* p, long long n, hipStream_t st);
+hipError_t reproject_occupancy(ReprojectKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu);
+hipError_t set_reproject_lds_limit(ReprojectKernelFn fn, int lds_bytes);
 hipError_t launch_adjoint_reduce(const Workspace& ws, int n_swaths, int max_p, hipStream_t st);
 hipError_t launch_count(const Workspace& ws, int s, int P, int E, int rows, unsigned long long* out, hipStream_t st);
 hipError_t launch_sharpness(const void* image, long long n, double* partials, double* out_S, void* grad,
@@ -126,6 +134,8 @@ struct sas_bp_plan_s {
   Workspace ws{};
   ImageKernelFn image_fn = nullptr;
   AdjointKernelFn adjoint_fn = nullptr;
+  ReprojectKernelFn reproject_fn = nullptr;
+  int rep_grid = 0;
   SwathDev* host_sw = nullptr;     // pinned mirror of ws.swaths
   std::vector<SwathDev> last_sw;   // what the device copy currently holds
   hipEvent_t upload_done = nullptr;
@@ -598,7 +608,8 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->adj_lds_bytes = max_adj_lds;
   p->image_fn = image_kernel_for(t.layout, p->gate_any, p->dtype);
   p->adjoint_fn = adjoint_kernel_for(t.layout, p->gate_any, p->dtype);
-  if (!p->image_fn || !p->adjoint_fn) {
+  p->reproject_fn = reproject_kernel_for(t.layout, p->gate_any);
+  if (!p->image_fn || !p->adjoint_fn || !p->reproject_fn) {
     release(p);
     return fail(SAS_BP_EUNSUPPORTED, "no kernel for tiling %d", t.layout);
   }
@@ -611,21 +622,24 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   }
   if (e == hipSuccess) e = set_image_lds_limit(p->image_fn, max_lds);
   if (e == hipSuccess) e = set_adjoint_lds_limit(p->adjoint_fn, max_adj_lds);
-  int occ = 0, adj_occ = 0;
+  if (e == hipSuccess) e = set_reproject_lds_limit(p->reproject_fn, max_lds);   // same layout as the image
+  int occ = 0, adj_occ = 0, rep_occ = 0;
   if (e == hipSuccess) e = image_occupancy(p->image_fn, t.NT, max_lds, &occ);
   if (e == hipSuccess) e = adjoint_occupancy(p->adjoint_fn, t.NT, max_adj_lds, &adj_occ);
+  if (e == hipSuccess) e = reproject_occupancy(p->reproject_fn, t.NT, max_lds, &rep_occ);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     release(p);
     return fail(SAS_BP_EDEVICE, "kernel setup failed: %s", hipGetErrorString(e));
   }
-  if (occ < 1 || adj_occ < 1) {
+  if (occ < 1 || adj_occ < 1 || rep_occ < 1) {
     release(p);
     return fail(SAS_BP_EUNSUPPORTED, "tiling needs %d bytes of LDS; no workgroup fits", max_lds);
   }
   p->occ = occ;
   p->grid = std::max(1, std::min(std::min(n_tiles, occ * prop.multiProcessorCount), lay.geo_slots));
   p->adj_grid = std::max(1, std::min(std::min(n_tiles, adj_occ * prop.multiProcessorCount), lay.geo_slots));
+  p->rep_grid = std::max(1, std::min(std::min(n_tiles, rep_occ * prop.multiProcessorCount), lay.geo_slots));
 
   e = hipMalloc(&p->slab, lay.total);
   if (e != hipSuccess) {
@@ -755,6 +769,55 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
     ++p->n_timed;
   }
   HIP_TRY(launch_adjoint_reduce(p->ws, n_swaths, p->max_p, st));
+  return SAS_BP_OK;
+}
+
+int sas_bp_reproject(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const* image_in,
+                     void* const* echo_out, int n_swaths, void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  int rc = check_io(p, io, n_swaths);
+  if (rc) return rc;
+  if (!image_in || !echo_out) return fail(SAS_BP_EINVAL, "image_in or echo_out is NULL");
+  for (int i = 0; i < n_swaths; ++i) {
+    if (!image_in[i] || !echo_out[i]) return fail(SAS_BP_EINVAL, "swath %d: NULL image_in or echo_out", i);
+    if (((uintptr_t)image_in[i] & 7u) || ((uintptr_t)echo_out[i] & 7u))
+      return fail(SAS_BP_EINVAL, "swath %d: image_in or echo_out not 8-byte aligned", i);
+  }
+  DeviceGuard guard(p->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::vector<SwathDev> v(n_swaths);
+  for (int i = 0; i < n_swaths; ++i) {
+    v[i] = make_dev(p->sw[i]);
+    v[i].echo = io[i].echo;
+    v[i].scale = io[i].echo_scale;
+    v[i].tx = io[i].tx_pos;
+    v[i].rx = io[i].rx_pos;
+    v[i].c = io[i].c;
+    v[i].image = reinterpret_cast<float2*>(io[i].image);
+    v[i].gimage = reinterpret_cast<const float2*>(image_in[i]);
+    v[i].gecho = reinterpret_cast<float2*>(echo_out[i]);
+  }
+  rc = upload(p, v, st);
+  if (rc) return rc;
+  for (int i = 0; i < n_swaths; ++i) {
+    const auto& d = p->sw[i].d;
+    HIP_TRY(launch_zero_rows(echo_out[i], (long long)d.n_ping * d.n_elem * d.n_sample, st));
+  }
+  HIP_TRY(launch_init(p->ws, st));
+  HIP_TRY(launch_cull(p->ws, p->n_tiles, p->tiling.TX, p->tiling.TY, p->tiling.TZ, p->bucket_shift, st));
+  HIP_TRY(launch_order(p->ws, p->n_tiles, p->bucket_shift, st));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (p->timing) {
+    rc = timing_pair(p, &ea, &eb);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ea, st));
+  }
+  HIP_TRY(launch_reproject(p->reproject_fn, p->ws, p->n_tiles, p->rep_grid, p->tiling.NT, p->lds_bytes, st));
+  if (p->timing) {
+    HIP_TRY(hipEventRecord(eb, st));
+    ++p->n_timed;
+  }
   return SAS_BP_OK;
 }
 

@@ -37,7 +37,8 @@ __host__ __device__ inline int adjoint_bytes(int CP, int E, int W, int ROWS, boo
 }
 
 template <int L, bool GATE, int DT>
-__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) void adjoint_kernel(
+__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ)
+__attribute__((amdgpu_waves_per_eu(kAdjointWaves, kAdjointWaves))) void adjoint_kernel(
     Workspace ws, const SwathDev* __restrict__ swaths, const int* __restrict__ order,
     const int* __restrict__ tile_swath, const PingRange* __restrict__ prange, int n_tiles) {
   extern __shared__ __align__(16) unsigned char lds[];

@@ -29,6 +29,7 @@ constexpr int kThreads = 256;    // helper kernels (cull, order, count, sharpnes
 // VGPRs per SIMD lane shared by the resident waves); the plan sizes LDS
 // chunks so that this occupancy is not lost to LDS.
 constexpr int kImageWaves = 3;
+constexpr int kAdjointWaves = 3;   // the adjoint's register budget (its chunks stay whole pings)
 constexpr int kMaxElem = 256;
 
 // Per-swath constants and pointers, stored in the plan's workspace so that a
@@ -44,6 +45,7 @@ struct SwathDev {
   double* grad_tx;        // adjoint outputs
   double* grad_rx;
   double* grad_c;
+  float2* gecho;          // reprojection output (complex64, echo layout)
   int P, E, Ns, dtype;
   int nx, ny, nz;
   int ntx, nty, ntz;      // tiles per axis

@@ -443,19 +443,16 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
   for (int r = tid; r < nrows; r += NT) lwin[(size_t)r * (W + 1) + W] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// One chunk of a run whose geometry is in g: the nr records q0 .. q0 + nr - 1
-// of the run (record q is ping P0 + q / E, element q % E), spanning the ns
-// pings s0 .. s0 + ns - 1 of the run. Records, window starts, transmitter
-// records and gate rows go into LDS, then the echo windows. Ends with a
-// barrier.
-template <int NT, int ROWS, bool GATE, int DT>
-__device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, const SwathDev& sw, int P0, int q0,
-                                           int nr, int s0, int ns, const LdsLayout& L, int tid, int lane,
-                                           int wave) {
+// The records of one chunk of a run whose geometry is in g: the nr records
+// q0 .. q0 + nr - 1 of the run (record q is ping P0 + q / E, element q % E),
+// spanning the ns pings s0 .. s0 + ns - 1 of the run. Receiver records,
+// window starts, transmitter records and gate rows go into LDS. No barrier.
+template <int NT, int ROWS, bool GATE>
+__device__ __forceinline__ void load_records(unsigned char* lds, const Geo& g, const SwathDev& sw, int q0, int nr,
+                                             int s0, int ns, const LdsLayout& L, int tid) {
   TxRec* ltx = reinterpret_cast<TxRec*>(lds + L.off_tx);
   RxRec* lrx = reinterpret_cast<RxRec*>(lds + L.off_rx);
   int* ln0 = reinterpret_cast<int*>(lds + L.off_n0);
-  float4* lwin = reinterpret_cast<float4*>(lds + L.off_win);
   const RxRec* grec = g.rec + q0;
   const int* gn0 = g.n0 + q0;
   for (int r = tid; r < nr; r += NT) {
@@ -469,8 +466,19 @@ __device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, con
     int4* dst = reinterpret_cast<int4*>(lds + L.off_rows);
     for (int q = tid; q < nr * (ROWS / 4); q += NT) dst[q] = src[q];
   }
+}
+
+// One chunk (as for load_records): the records into LDS, then the echo
+// windows. Ends with a barrier.
+template <int NT, int ROWS, bool GATE, int DT>
+__device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, const SwathDev& sw, int P0, int q0,
+                                           int nr, int s0, int ns, const LdsLayout& L, int tid, int lane,
+                                           int wave) {
+  load_records<NT, ROWS, GATE>(lds, g, sw, q0, nr, s0, ns, L, tid);
   __syncthreads();
-  stage_windows<NT, DT>(lwin, lrx, ln0, ltx, sw, (long long)P0 * sw.E + q0, q0 - s0 * sw.E, nr, tid, lane, wave);
+  stage_windows<NT, DT>(reinterpret_cast<float4*>(lds + L.off_win), reinterpret_cast<const RxRec*>(lds + L.off_rx),
+                        reinterpret_cast<const int*>(lds + L.off_n0), reinterpret_cast<const TxRec*>(lds + L.off_tx),
+                        sw, (long long)P0 * sw.E + q0, q0 - s0 * sw.E, nr, tid, lane, wave);
   __syncthreads();
 }
 
