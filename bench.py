@@ -201,6 +201,36 @@ def reprojection_leg(api, plan, buf, useful: int, steps: int, warmup: int, forwa
             "note": "float atomics: not bitwise reproducible"}
 
 
+def volume_leg(api, steps: int, warmup: int) -> dict:
+    """The 3D workload at full size: 256 pings x 64 receivers (32 across x 2
+    along), 8192 samples, 512 x 512 x 128 voxels at 2 cm, no gate. The seabed
+    carries 5000 weak scatterers instead of 1e5 to keep synthesis short (the
+    echo content does not change the work)."""
+    from synth import make_config, synthesize_echo
+    scn = make_config("c3", n_seabed=5000)
+    echo = synthesize_echo(scn, device="cuda", dtype=torch.complex64, noise_on_device=True)
+    plan = api.sas_bp_plan([_desc(api, scn)])
+    buf = _buffers(api, scn, echo)
+    updates = scn.nominal_updates()
+    api.sas_bp_set_kernel_timing(plan, True)
+    for _ in range(warmup):
+        api.sas_bp_image(plan, [buf])
+    api.sas_bp_kernel_time(plan)
+    ms = time_steps(lambda: api.sas_bp_image(plan, [buf]), steps, 0)
+    k_total, k_n = api.sas_bp_kernel_time(plan)
+    kms = k_total / k_n
+    info = plan.info()
+    log(f"volume: {ms:.2f} ms/step, image kernel {kms:.2f} ms, {updates / (kms * 1e-3):.4e} updates/s, plan {info}")
+    plan.destroy()
+    del echo, buf
+    torch.cuda.empty_cache()
+    return {"workload": "3D volume 512x512x128 voxels at 2 cm, 256 pings x 64 receivers, 8192 samples, no gate",
+            "updates": int(updates), "ms_per_step": ms, "image_kernel_ms": kms,
+            "updates_per_s": updates / (ms * 1e-3), "kernel_updates_per_s": updates / (kms * 1e-3),
+            "tile": [info["tile_x"], info["tile_y"], info["tile_z"]], "records_per_chunk": info["records_per_chunk"],
+            "workgroups_per_cu": info["workgroups_per_cu"]}
+
+
 def autofocus_leg(api, steps: int, warmup: int) -> dict:
     """One autofocus iteration on the differentiable workload (256 pings x 16
     receivers, 1024 x 1024 pixels, no gate): image, sharpness and its
@@ -298,6 +328,7 @@ def main() -> int:
     ap.add_argument("--no-autofocus", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-reprojection", action="store_true")
+    ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -309,7 +340,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
-        args.no_reprojection = True
+        args.no_reprojection = args.no_volume = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -405,6 +436,8 @@ def main() -> int:
 
     if not args.no_reprojection:
         out["reprojection"] = reprojection_leg(api, plan, buf, useful, max(3, args.steps // 4), 1, kernel_ms)
+    if not args.no_volume:
+        out["volume"] = volume_leg(api, max(3, args.steps // 4), 1)
     if not args.no_autofocus:
         out["autofocus_step"] = autofocus_leg(api, args.steps, args.warmup)
     if not args.no_batched:
