@@ -138,7 +138,9 @@ int sas_bp_image(sas_bp_plan_t plan, const sas_bp_swath_io* io, int n_swaths, vo
  * using dI/dtau = [f_s (E[n+1] - E[n]) + j 2 pi f_c L] exp(j 2 pi f_c tau),
  * dtau/dT = (T - p)/(c d_T), dtau/dR = (R - p)/(c d_R), dtau/dc = -tau/c
  * (gate held fixed). Outputs are overwritten. Reduction order is fixed, so
- * results are bitwise reproducible for a given plan. */
+ * results are bitwise reproducible for a given plan. The adjoint stages whole
+ * pings; with a tiling whose window of one ping's elements exceeds the LDS,
+ * it returns SAS_BP_EUNSUPPORTED (the plan's image still works). */
 int sas_bp_adjoint(sas_bp_plan_t plan, const sas_bp_swath_io* io,
                    const void* const* grad_image, double* const* grad_tx,
                    double* const* grad_rx, double* const* grad_c,

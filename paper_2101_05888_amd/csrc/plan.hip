@@ -124,6 +124,7 @@ struct sas_bp_plan_s {
   int lds_bytes = 0, adj_lds_bytes = 0;
   int grid = 0, adj_grid = 0;
   int occ = 0;                     // image workgroups resident per CU
+  bool adj_ok = false;             // the adjoint's whole-ping chunks fit the device
   int max_pe = 0;
   int max_p = 0;
   bool use_graph = true;
@@ -263,9 +264,9 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
       cp = 1;
       while (cp < 8 && image_lds_bytes(cp * 2 * E, E, s.W, rows, gate) <= kLdsBudget) cp *= 2;
     }
-    if (image_lds_bytes(cp * E, E, s.W, rows, gate) > kLdsMax - 1024)
+    if (ppc > 0 && image_lds_bytes(cp * E, E, s.W, rows, gate) > kLdsMax - 1024)
       return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d pings x %d elements x %d samples exceed LDS", i, cp, E, s.W);
-    s.CP = cp;
+    s.CP = cp;   // if even one whole ping does not fit, the plan has no adjoint
     // image chunk in records: explicit elements (part of a ping), explicit
     // pings, or the largest of 8, 4, 2, 1 pings and then of E - 1, E - 2, ...
     // records whose LDS lets the kernel reach its register-bound occupancy
@@ -278,6 +279,9 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
       rc = 8 * E;
       while (rc > E && image_lds_bytes(rc, E, s.W, rows, gate) > target) rc /= 2;
       while (rc > 1 && image_lds_bytes(rc, E, s.W, rows, gate) > target) --rc;
+      // part of a ping: a whole number of quarter pings where possible (measured
+      // faster than the largest fitting count on both the 2D and 3D workloads)
+      if (rc < E && E >= 4 && rc >= E / 4) rc = rc / (E / 4) * (E / 4);
     }
     // the geometry build keeps its list of partially gated records (one int
     // each) in the window area, which must hold at least one ping's list
@@ -615,17 +619,18 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   }
   hipDeviceProp_t prop;
   hipError_t e = hipGetDeviceProperties(&prop, device);
-  if (e == hipSuccess && (size_t)std::max(max_lds, max_adj_lds) + 1024 > prop.sharedMemPerBlock) {
+  if (e == hipSuccess && (size_t)max_lds + 1024 > prop.sharedMemPerBlock) {
     release(p);
-    return fail(SAS_BP_EUNSUPPORTED, "tiling needs %d bytes of LDS, the device allows %zu per workgroup",
-                std::max(max_lds, max_adj_lds), (size_t)prop.sharedMemPerBlock);
+    return fail(SAS_BP_EUNSUPPORTED, "tiling needs %d bytes of LDS, the device allows %zu per workgroup", max_lds,
+                (size_t)prop.sharedMemPerBlock);
   }
+  p->adj_ok = e == hipSuccess && (size_t)max_adj_lds + 1024 <= prop.sharedMemPerBlock;
   if (e == hipSuccess) e = set_image_lds_limit(p->image_fn, max_lds);
-  if (e == hipSuccess) e = set_adjoint_lds_limit(p->adjoint_fn, max_adj_lds);
+  if (e == hipSuccess && p->adj_ok) e = set_adjoint_lds_limit(p->adjoint_fn, max_adj_lds);
   if (e == hipSuccess) e = set_reproject_lds_limit(p->reproject_fn, max_lds);   // same layout as the image
-  int occ = 0, adj_occ = 0, rep_occ = 0;
+  int occ = 0, adj_occ = 1, rep_occ = 0;
   if (e == hipSuccess) e = image_occupancy(p->image_fn, t.NT, max_lds, &occ);
-  if (e == hipSuccess) e = adjoint_occupancy(p->adjoint_fn, t.NT, max_adj_lds, &adj_occ);
+  if (e == hipSuccess && p->adj_ok) e = adjoint_occupancy(p->adjoint_fn, t.NT, max_adj_lds, &adj_occ);
   if (e == hipSuccess) e = reproject_occupancy(p->reproject_fn, t.NT, max_lds, &rep_occ);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -717,6 +722,9 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   if (!grad_image || !grad_tx || !grad_rx || !grad_c) return fail(SAS_BP_EINVAL, "gradient array is NULL");
+  if (!p->adj_ok)
+    return fail(SAS_BP_EUNSUPPORTED, "the adjoint stages whole pings and needs %d bytes of LDS with this tiling; "
+                "plan with a smaller tile", p->adj_lds_bytes);
   for (int i = 0; i < n_swaths; ++i) {
     if (!grad_image[i] || !grad_tx[i] || !grad_rx[i] || !grad_c[i])
       return fail(SAS_BP_EINVAL, "swath %d: NULL gradient pointer", i);

@@ -303,3 +303,25 @@ def test_full_size_volume_sampled(api):
     ref = oracle_image(scn, echo_np, idx)
     r, ph = report("c3-full-subset", img, ref)
     assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+
+
+def test_wide_tile_without_adjoint_still_images(api):
+    # 64 receivers and a 64 x 8 x 4 voxel tile: one ping's windows need more
+    # LDS than a workgroup has, so the plan images in element chunks and the
+    # adjoint (which stages whole pings) is refused with EUNSUPPORTED
+    from paper_2101_05888_amd._native import SasBpError, SAS_BP_EUNSUPPORTED
+    scn, echo = _case("c3", n_ping=6, n_across=32, nx=70, ny=16, nz=9, n_seabed=100, n_surface=6, n_buried=2,
+                      n_sample=2048)
+    img, plan, buf = gpu_image(api, scn, echo, tile=(64, 8, 4), threads=256)
+    info = plan.info()
+    assert info["records_per_chunk"] < scn.n_elem
+    ref = oracle_image(scn, echo.numpy()).reshape(img.shape)
+    r, ph = report("wide-tile", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+    g = torch.zeros_like(buf.image)
+    gtx = torch.zeros((scn.n_ping, 3), dtype=torch.float64, device="cuda")
+    grx = torch.zeros((scn.n_ping, scn.n_elem, 3), dtype=torch.float64, device="cuda")
+    gc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(SasBpError) as ei:
+        api.sas_bp_adjoint(plan, [buf], [g], [gtx], [grx], [gc])
+    assert ei.value.status == SAS_BP_EUNSUPPORTED
