@@ -13,10 +13,10 @@ echo (reprojection). It shares no code with the HIP path.
 """
 from .tdbp import (pixel_points, backproject, backproject_image, gated_term_count,
                    gated_term_count_rows, vjp, vjp_segment_bound, reproject, sharpness,
-                   sharpness_cotangent)
+                   sharpness_cotangent, sinc_kernel, SINC_HALF)
 from .metrics import rel_l2, phase_error_mrad
 
 __all__ = ["pixel_points", "backproject", "backproject_image", "gated_term_count",
            "gated_term_count_rows", "vjp", "vjp_segment_bound", "reproject", "sharpness",
-           "sharpness_cotangent",
+           "sharpness_cotangent", "sinc_kernel", "SINC_HALF",
            "rel_l2", "phase_error_mrad"]

@@ -15,7 +15,8 @@ and receiver element e at R_ie:
     I(p) = sum_i sum_e  g * L * exp(+j 2 pi f_c tau)
 
 Readings where the paper is silent: linear interpolation in sample index with
-zero extension; t_k = t0 + k / f_s; echoes at complex baseband so the carrier
+zero extension (a Hann-windowed sinc over 8 samples is available as a
+variant of the image); t_k = t0 + k / f_s; echoes at complex baseband so the carrier
 phase is re-applied; no amplitude weighting; positions fixed per ping.
 
 Gradient (vector-Jacobian product) for a cotangent Gbar = dJ/dRe I + j dJ/dIm I:
@@ -67,7 +68,30 @@ def _gate(dx: np.ndarray, d: np.ndarray, sin_g: float) -> np.ndarray:
     return np.abs(dx) <= sin_g * d
 
 
-def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate):
+SINC_HALF = 4   # the windowed-sinc interpolator uses 2 * SINC_HALF taps
+
+
+def sinc_kernel(t, half: int = SINC_HALF) -> np.ndarray:
+    """Hann-windowed sinc: sinc(t) (1 + cos(pi t / half)) / 2 for |t| < half, 0 beyond."""
+    t = np.asarray(t, dtype=np.float64)
+    return np.where(np.abs(t) < half, np.sinc(t) * 0.5 * (1.0 + np.cos(np.pi * t / half)), 0.0)
+
+
+def _sinc_interp(row: np.ndarray, u: np.ndarray, half: int = SINC_HALF) -> np.ndarray:
+    """sum over m = floor(u) - half + 1 .. floor(u) + half of E~[m] h(u - m)."""
+    n = np.floor(u).astype(np.int64)
+    ns = row.shape[0]
+    out = np.zeros(u.shape, dtype=np.complex128)
+    for j in range(2 * half):
+        m = n - half + 1 + j
+        inside = (m >= 0) & (m < ns)
+        v = np.zeros(u.shape, dtype=np.complex128)
+        v[inside] = row[m[inside]]
+        out += v * sinc_kernel(u - m, half)
+    return out
+
+
+def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear"):
     P, E = rx.shape[0], rx.shape[1]
     acc = np.zeros(pts.shape[0], dtype=np.complex128)
     count = 0
@@ -80,10 +104,13 @@ def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate):
             dR = np.sqrt(((pts - R) ** 2).sum(axis=1))
             tau = (dT + dR) / c
             u = (tau - t0) * fs
-            nf = np.floor(u)
-            w = u - nf
-            a, b = _taps(echo[i, e], nf.astype(np.int64))
-            L = (1.0 - w) * a + w * b
+            if interp == "sinc":
+                L = _sinc_interp(echo[i, e], u)
+            else:
+                nf = np.floor(u)
+                w = u - nf
+                a, b = _taps(echo[i, e], nf.astype(np.int64))
+                L = (1.0 - w) * a + w * b
             term = L * np.exp(1j * 2.0 * np.pi * fc * tau)
             if sin_g is not None:
                 g = gT & _gate(pts[:, 0] - R[0], dR, sin_g)
@@ -102,15 +129,18 @@ def _worker(args):
     lo, hi = args
     s = _SHARED
     return _bp_chunk(s["echo"], s["tx"], s["rx"], s["c"], s["fc"], s["fs"], s["t0"],
-                     s["pts"][lo:hi], s["gate"])
+                     s["pts"][lo:hi], s["gate"], s["interp"])
 
 
 def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
-                workers=1, chunk=4096, return_count=False):
+                workers=1, chunk=4096, return_count=False, interp="linear"):
     """Backprojected complex values at arbitrary points [N,3] (float64 in, complex128 out).
 
     echo: complex [P,E,N_s]; tx: [P,3]; rx: [P,E,3]; gate_half_angle in radians
     (0 = no gate). ``workers`` > 1 splits the points over forked processes.
+    ``interp`` = "linear" (the definition above) or "sinc": the interpolation
+    variant L = sum over the 2 SINC_HALF samples m around u of E~[m] h(u - m),
+    h the Hann-windowed sinc of ``sinc_kernel``.
     """
     echo = np.ascontiguousarray(np.asarray(echo).astype(np.complex128, copy=False))
     tx = np.asarray(tx, dtype=np.float64)
@@ -122,12 +152,12 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
     total = 0
     if workers <= 1 or len(spans) <= 1:
         for lo, hi in spans:
-            v, cnt = _bp_chunk(echo, tx, rx, float(c), fc, fs, t0, pts[lo:hi], gate_half_angle)
+            v, cnt = _bp_chunk(echo, tx, rx, float(c), fc, fs, t0, pts[lo:hi], gate_half_angle, interp)
             out[lo:hi] = v
             total += cnt
     else:
         _SHARED.update(echo=echo, tx=tx, rx=rx, c=float(c), fc=fc, fs=fs, t0=t0, pts=pts,
-                       gate=gate_half_angle)
+                       gate=gate_half_angle, interp=interp)
         ctx = mp.get_context("fork")
         with ctx.Pool(workers) as pool:
             res = pool.map(_worker, spans, chunksize=1)
@@ -139,11 +169,11 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
 
 
 def backproject_image(echo, tx, rx, c, fc, fs, t0, origin, spacing, n, gate_half_angle=0.0,
-                      workers=1, return_count=False):
+                      workers=1, return_count=False, interp="linear"):
     """Full image [nz, ny, nx] complex128 on the grid origin + index * spacing."""
     pts = pixel_points(origin, spacing, n)
     r = backproject(echo, tx, rx, c, fc, fs, t0, pts, gate_half_angle, workers=workers,
-                    return_count=return_count)
+                    return_count=return_count, interp=interp)
     nx, ny, nz = (int(v) for v in n)
     if return_count:
         return r[0].reshape(nz, ny, nx), r[1]

@@ -82,3 +82,23 @@ def test_adjoint_identity_rejects_reprojection_mutation(name):
     ahy = mod.reproject(y, g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, x.shape[2], g["gate"])
     lhs, rhs = np.vdot(ax, y), np.vdot(x.ravel(), ahy.ravel())
     assert abs(lhs - rhs) > 1e-9 * abs(lhs), f"mutation {name} survived the adjoint identity"
+
+
+SINC_MUTATIONS = {
+    "taps_shifted_by_one": ("m = n - half + 1 + j", "m = n - half + j"),
+    "window_too_wide": ("np.cos(np.pi * t / half)", "np.cos(np.pi * t / (2 * half))"),
+    "sinc_without_pi": ("np.sinc(t) * 0.5", "np.sinc(t / np.pi) * 0.5"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SINC_MUTATIONS))
+def test_brute_force_rejects_sinc_variant_mutation(name):
+    from tests.test_oracle_pins import _brute_mp_sinc
+    old, new = SINC_MUTATIONS[name]
+    mod = _mutant(old, new)
+    g = _tiny_geometry(gate_deg=12.0, ns=48, P=3, E=2)
+    pts = g["grid"].points()[::2]
+    got = mod.backproject(g["echo"], g["tx"], g["rx"], g["c"], g["fc"], g["fs"], g["t0"], pts, g["gate"],
+                          interp="sinc")
+    ref = _brute_mp_sinc(g, pts)
+    assert np.linalg.norm(got - ref) > 1e-9 * np.linalg.norm(ref), f"mutation {name} survived"
