@@ -201,6 +201,39 @@ def reprojection_leg(api, plan, buf, useful: int, steps: int, warmup: int, forwa
             "note": "float atomics: not bitwise reproducible"}
 
 
+def sinc_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_kernel_ms: float, sample: int) -> dict:
+    """The windowed-sinc interpolation variant (8 taps) on the same swath:
+    image kernel time, and its error against the oracle's sinc variant on a
+    seeded pixel sample."""
+    import oracle
+    from synth import subset_indices
+    d = _desc(api, scn)
+    d.interp = 1
+    plan = api.sas_bp_plan([d])
+    buf = _buffers(api, scn, echo)
+    api.sas_bp_set_kernel_timing(plan, True)
+    for _ in range(warmup):
+        api.sas_bp_image(plan, [buf])
+    api.sas_bp_kernel_time(plan)
+    ms = time_steps(lambda: api.sas_bp_image(plan, [buf]), steps, 0)
+    k_total, k_n = api.sas_bp_kernel_time(plan)
+    kms = k_total / k_n
+    idx = subset_indices(scn, sample)
+    got = buf.image.reshape(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    g = scn.grid
+    pts = oracle.pixel_points(g.origin, g.spacing, g.n, idx)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    ref = oracle.backproject(echo.cpu().numpy(), scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
+                             scn.gate_half_angle, workers=workers, interp="sinc")
+    r, ph = oracle.rel_l2(got, ref), oracle.phase_error_mrad(got, ref)
+    log(f"sinc8: {ms:.3f} ms/step, image kernel {kms:.3f} ms ({kms / forward_kernel_ms:.2f}x linear), "
+        f"rel_l2 {r:.2e}, max phase {ph:.3f} mrad on {sample} pixels")
+    plan.destroy()
+    return {"interpolator": "Hann-windowed sinc, 8 taps", "ms_per_step": ms, "image_kernel_ms": kms,
+            "useful_updates_per_s": useful / (kms * 1e-3), "vs_linear_kernel": kms / forward_kernel_ms,
+            "rel_l2": r, "max_phase_mrad": ph, "sample_pixels": sample}
+
+
 def volume_leg(api, steps: int, warmup: int) -> dict:
     """The 3D workload at full size: 256 pings x 64 receivers (32 across x 2
     along), 8192 samples, 512 x 512 x 128 voxels at 2 cm, no gate. The seabed
@@ -329,6 +362,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-reprojection", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
+    ap.add_argument("--no-sinc", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -340,7 +374,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
-        args.no_reprojection = args.no_volume = True
+        args.no_reprojection = args.no_volume = args.no_sinc = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -434,6 +468,8 @@ def main() -> int:
             del q, b2
         out["mixed"] = mixed
 
+    if not args.no_sinc:
+        out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_reprojection:
         out["reprojection"] = reprojection_leg(api, plan, buf, useful, max(3, args.steps // 4), 1, kernel_ms)
     if not args.no_volume:

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SAS_BP_ABI_VERSION 2
+#define SAS_BP_ABI_VERSION 3
 
 typedef struct sas_bp_plan_s* sas_bp_plan_t;
 
@@ -75,6 +75,17 @@ enum sas_bp_echo_dtype {
     SAS_BP_ECHO_BF16X2 = 2
 };
 
+/* Interpolation of the echo at the sample position u (Sec. II-A's sum reads
+ * the echo between samples; the paper does not name the interpolator):
+ *   LINEAR : (1 - w) E[n] + w E[n+1], n = floor(u), w = u - n (the default)
+ *   SINC8  : sum over m = n - 3 .. n + 4 of E[m] h(u - m), the Hann-windowed
+ *            sinc h(t) = sinc(t) (1 + cos(pi t / 4)) / 2; about 4x the work,
+ *            image only (sas_bp_adjoint and sas_bp_reproject refuse it). */
+enum sas_bp_interp {
+    SAS_BP_INTERP_LINEAR = 0,
+    SAS_BP_INTERP_SINC8 = 1
+};
+
 /* One swath: acquisition constants and image grid. */
 typedef struct {
     int32_t n_ping;         /* P >= 1                                          */
@@ -89,6 +100,7 @@ typedef struct {
     double t0;              /* time of sample 0 after transmit, s             */
     double gate_half_angle; /* radians in [0, pi/2); 0 disables the beam gate */
     double c_min;           /* smallest sound speed the plan must accept, m/s; 0 selects 1400 */
+    int32_t interp;         /* enum sas_bp_interp; all swaths of a plan share it */
 } sas_bp_swath_desc;
 
 /* Plan options; a NULL options pointer selects every default. */

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libsas_bp.so")
 
 SAS_BP_OK, SAS_BP_EINVAL, SAS_BP_EUNSUPPORTED, SAS_BP_ENOMEM, SAS_BP_EDEVICE, SAS_BP_ENAV = range(6)
 ECHO_C64, ECHO_F16X2, ECHO_BF16X2 = 0, 1, 2
+INTERP_LINEAR, INTERP_SINC8 = 0, 1
 
 EXPORTED = (
     "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image", "sas_bp_adjoint", "sas_bp_reproject",
@@ -28,7 +29,7 @@ class SwathDesc(C.Structure):
         ("n_ping", C.c_int32), ("n_elem", C.c_int32), ("n_sample", C.c_int32), ("echo_dtype", C.c_int32),
         ("n", C.c_int64 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
         ("f_c", C.c_double), ("f_s", C.c_double), ("t0", C.c_double),
-        ("gate_half_angle", C.c_double), ("c_min", C.c_double),
+        ("gate_half_angle", C.c_double), ("c_min", C.c_double), ("interp", C.c_int32),
     ]
 
 

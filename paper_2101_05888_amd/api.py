@@ -18,11 +18,17 @@ from . import _native as N
 from ._native import check
 
 ECHO_DTYPES = {"c64": N.ECHO_C64, "f16": N.ECHO_F16X2, "bf16": N.ECHO_BF16X2}
+INTERPS = {"linear": N.INTERP_LINEAR, "sinc8": N.INTERP_SINC8}
 
 
 def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin: Sequence[float],
                spacing: Sequence[float], f_c: float, f_s: float, t0: float = 0.0,
-               gate_half_angle: float = 0.0, echo_dtype: str = "c64", c_min: float = 0.0) -> N.SwathDesc:
+               gate_half_angle: float = 0.0, echo_dtype: str = "c64", c_min: float = 0.0,
+               interp: str = "linear") -> N.SwathDesc:
+    """Descriptor of one swath; ``interp`` is "linear" or "sinc8" (the
+    Hann-windowed sinc over 8 samples)."""
+    if interp not in INTERPS:
+        raise ValueError(f"interp must be one of {sorted(INTERPS)}")
     d = N.SwathDesc()
     d.n_ping, d.n_elem, d.n_sample = int(n_ping), int(n_elem), int(n_sample)
     d.echo_dtype = ECHO_DTYPES[echo_dtype]
@@ -32,6 +38,7 @@ def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin
         d.spacing[a] = float(spacing[a])
     d.f_c, d.f_s, d.t0 = float(f_c), float(f_s), float(t0)
     d.gate_half_angle, d.c_min = float(gate_half_angle), float(c_min)
+    d.interp = INTERPS[interp]
     return d
 
 

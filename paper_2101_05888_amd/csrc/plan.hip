@@ -27,7 +27,7 @@
 
 namespace sasbp {
 typedef void (*ImageKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
-ImageKernelFn image_kernel_for(int layout, bool gate, int dt);
+ImageKernelFn image_kernel_for(int layout, bool gate, int dt, int interp);
 int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate);
 hipError_t launch_init(const Workspace& ws, hipStream_t st);
 hipError_t launch_cull(const Workspace& ws, int n_tiles, int TX, int TY, int TZ, int bucket_shift, hipStream_t st);
@@ -120,6 +120,7 @@ struct sas_bp_plan_s {
   Tiling tiling{};
   bool gate_any = false;
   int dtype = 0;
+  int interp = 0;                  // SAS_BP_INTERP_*, shared by all swaths of the plan
   int bucket_shift = 0;
   int lds_bytes = 0, adj_lds_bytes = 0;
   int grid = 0, adj_grid = 0;
@@ -173,6 +174,8 @@ int validate(const sas_bp_swath_desc* d, int i) {
   if (!(d->gate_half_angle >= 0.0) || !(d->gate_half_angle < 1.5707963267948966))
     return fail(SAS_BP_EINVAL, "swath %d: gate_half_angle must be in [0, pi/2)", i);
   if (!(d->c_min >= 0.0) || !finite(d->c_min)) return fail(SAS_BP_EINVAL, "swath %d: c_min must be >= 0", i);
+  if (d->interp != SAS_BP_INTERP_LINEAR && d->interp != SAS_BP_INTERP_SINC8)
+    return fail(SAS_BP_EINVAL, "swath %d: unknown interpolator %d", i, d->interp);
   return SAS_BP_OK;
 }
 
@@ -341,6 +344,7 @@ SwathDev make_dev(const SwathPlan& s) {
   v.E = s.d.n_elem;
   v.Ns = s.d.n_sample;
   v.dtype = s.d.echo_dtype;
+  v.interp = s.d.interp;
   v.nx = (int)s.d.n[0];
   v.ny = (int)s.d.n[1];
   v.nz = (int)s.d.n[2];
@@ -589,6 +593,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   if (options && options->use_graph == 0) p->use_graph = false;
   if (!options) p->use_graph = true;
   p->dtype = sw[0].d.echo_dtype;
+  p->interp = sw[0].d.interp;
   int max_pe = 1, max_lds = 0, max_adj_lds = 0;
   for (const auto& s : sw) {
     const bool gate = s.d.gate_half_angle > 0.0;
@@ -596,6 +601,10 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
     if (s.d.echo_dtype != p->dtype) {
       release(p);
       return fail(SAS_BP_EUNSUPPORTED, "all swaths of a plan must share one echo dtype");
+    }
+    if (s.d.interp != p->interp) {
+      release(p);
+      return fail(SAS_BP_EUNSUPPORTED, "all swaths of a plan must share one interpolator");
     }
     max_pe = std::max(max_pe, s.d.n_ping * s.d.n_elem);
     p->max_p = std::max(p->max_p, s.d.n_ping);
@@ -610,7 +619,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->bucket_shift = shift;
   p->lds_bytes = max_lds;
   p->adj_lds_bytes = max_adj_lds;
-  p->image_fn = image_kernel_for(t.layout, p->gate_any, p->dtype);
+  p->image_fn = image_kernel_for(t.layout, p->gate_any, p->dtype, p->interp);
   p->adjoint_fn = adjoint_kernel_for(t.layout, p->gate_any, p->dtype);
   p->reproject_fn = reproject_kernel_for(t.layout, p->gate_any);
   if (!p->image_fn || !p->adjoint_fn || !p->reproject_fn) {
@@ -722,6 +731,8 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   if (!grad_image || !grad_tx || !grad_rx || !grad_c) return fail(SAS_BP_EINVAL, "gradient array is NULL");
+  if (p->interp != SAS_BP_INTERP_LINEAR)
+    return fail(SAS_BP_EUNSUPPORTED, "the adjoint is built for linear interpolation only");
   if (!p->adj_ok)
     return fail(SAS_BP_EUNSUPPORTED, "the adjoint stages whole pings and needs %d bytes of LDS with this tiling; "
                 "plan with a smaller tile", p->adj_lds_bytes);
@@ -787,6 +798,8 @@ int sas_bp_reproject(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* con
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   if (!image_in || !echo_out) return fail(SAS_BP_EINVAL, "image_in or echo_out is NULL");
+  if (p->interp != SAS_BP_INTERP_LINEAR)
+    return fail(SAS_BP_EUNSUPPORTED, "reprojection is built for linear interpolation only");
   for (int i = 0; i < n_swaths; ++i) {
     if (!image_in[i] || !echo_out[i]) return fail(SAS_BP_EINVAL, "swath %d: NULL image_in or echo_out", i);
     if (((uintptr_t)image_in[i] & 7u) || ((uintptr_t)echo_out[i] & 7u))

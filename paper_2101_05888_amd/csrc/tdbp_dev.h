@@ -31,6 +31,7 @@ constexpr int kThreads = 256;    // helper kernels (cull, order, count, sharpnes
 constexpr int kImageWaves = 3;
 constexpr int kAdjointWaves = 3;   // the adjoint's register budget (its chunks stay whole pings)
 constexpr int kMaxElem = 256;
+constexpr int kSincHalf = 4;     // windowed-sinc interpolation: taps on each side
 
 // Per-swath constants and pointers, stored in the plan's workspace so that a
 // captured graph stays valid when the caller passes new buffers.
@@ -47,6 +48,7 @@ struct SwathDev {
   double* grad_c;
   float2* gecho;          // reprojection output (complex64, echo layout)
   int P, E, Ns, dtype;
+  int interp;             // 0 linear, 1 windowed sinc over 2 * kSincHalf samples
   int nx, ny, nz;
   int ntx, nty, ntz;      // tiles per axis
   int tile0;              // index of this swath's first tile in the global tile list

@@ -443,6 +443,75 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
   for (int r = tid; r < nrows; r += NT) lwin[(size_t)r * (W + 1) + W] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
+// Raw echo windows for the windowed-sinc variant: entry k of window r is the
+// complex sample n0 - kSincHalf + k (zero outside the record), k = 0 ..
+// W + 2 kSincHalf - 1, as float2 in the area that holds W + 1 float4 entries
+// of the midpoint windows (W >= 7, so it has room). Row bookkeeping as in
+// stage_windows; a lane loads and stores two consecutive samples.
+template <int NT, int DT>
+__device__ __forceinline__ void stage_windows_raw(float2* lwin, const RxRec* lrx, const int* ln0, const TxRec* ltx,
+                                                  const SwathDev& sw, long long row0, int e0, int nrows, int lane,
+                                                  int wave_id) {
+  typedef typename PairLoad<DT>::type LoadT;
+  constexpr int NW = NT / 64;
+  constexpr int SPL = 2;
+  constexpr int JS = 64 * SPL;
+  constexpr int B = 8;
+  constexpr int SB = DT == 0 ? 8 : 4;
+  const int wave = __builtin_amdgcn_readfirstlane(wave_id);
+  const int E = sw.E, Ns = sw.Ns;
+  const int WR = sw.W + 2 * kSincHalf;     // entries per raw window
+  const int stride = 2 * (sw.W + 1);       // float2 entries per record slot
+  const int J = (WR + JS - 1) / JS;
+  const bool aligned = (Ns % SPL) == 0;
+  const char* echo = reinterpret_cast<const char*>(sw.echo);
+  const int lane_off = SPL * lane;
+#pragma unroll 1
+  for (int r0 = wave * B; r0 < nrows; r0 += NW * B) {
+#pragma unroll 1
+    for (int part = 0; part < J; ++part) {
+      LoadT q[B];
+      int first[B];
+      unsigned live = 0u, fast = 0u;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int r = r0 + b;
+        first[b] = 0;
+        if (r >= nrows) continue;
+        const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(lrx[r].q0.w));
+        if (f & kFlagSkip) continue;
+        live |= 1u << b;
+        first[b] = __builtin_amdgcn_readfirstlane(ln0[r]) - kSincHalf + part * JS;
+        if (aligned && first[b] >= 0 && first[b] + JS <= Ns) {
+          fast |= 1u << b;
+          const size_t row = (size_t)(row0 + r) * (size_t)Ns + (size_t)first[b];
+          q[b] = *reinterpret_cast<const LoadT*>(echo + (row + lane_off) * SB);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (!(live & (1u << b))) continue;
+        const int r = r0 + b;
+        const size_t rowbase = (size_t)(row0 + r) * (size_t)Ns;
+        const float scale = DT == 0 ? 1.0f : ltx[(e0 + r) / E].scale;
+        const int n = first[b] + lane_off;
+        float2 sm[SPL];
+        if (fast & (1u << b)) {
+          if constexpr (DT == 0) unpack_pair(q[b], scale, sm);
+          else unpack_pair16<DT>(q[b], scale, sm);
+        } else {
+#pragma unroll
+          for (int i = 0; i < SPL; ++i) sm[i] = load_guarded(sw, rowbase, n + i, DT, scale);
+        }
+        float2* dst = lwin + (size_t)r * stride + part * JS;
+#pragma unroll
+        for (int i = 0; i < SPL; ++i)
+          if (part * JS + lane_off + i < WR) dst[lane_off + i] = sm[i];
+      }
+    }
+  }
+}
+
 // The records of one chunk of a run whose geometry is in g: the nr records
 // q0 .. q0 + nr - 1 of the run (record q is ping P0 + q / E, element q % E),
 // spanning the ns pings s0 .. s0 + ns - 1 of the run. Receiver records,
@@ -469,16 +538,22 @@ __device__ __forceinline__ void load_records(unsigned char* lds, const Geo& g, c
 }
 
 // One chunk (as for load_records): the records into LDS, then the echo
-// windows. Ends with a barrier.
-template <int NT, int ROWS, bool GATE, int DT>
+// windows (midpoint form, or raw samples for the windowed-sinc variant).
+// Ends with a barrier.
+template <int NT, int ROWS, bool GATE, int DT, bool RAW = false>
 __device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, const SwathDev& sw, int P0, int q0,
                                            int nr, int s0, int ns, const LdsLayout& L, int tid, int lane,
                                            int wave) {
   load_records<NT, ROWS, GATE>(lds, g, sw, q0, nr, s0, ns, L, tid);
   __syncthreads();
-  stage_windows<NT, DT>(reinterpret_cast<float4*>(lds + L.off_win), reinterpret_cast<const RxRec*>(lds + L.off_rx),
-                        reinterpret_cast<const int*>(lds + L.off_n0), reinterpret_cast<const TxRec*>(lds + L.off_tx),
-                        sw, (long long)P0 * sw.E + q0, q0 - s0 * sw.E, nr, tid, lane, wave);
+  if (RAW)
+    stage_windows_raw<NT, DT>(reinterpret_cast<float2*>(lds + L.off_win), reinterpret_cast<const RxRec*>(lds + L.off_rx),
+                              reinterpret_cast<const int*>(lds + L.off_n0), reinterpret_cast<const TxRec*>(lds + L.off_tx),
+                              sw, (long long)P0 * sw.E + q0, q0 - s0 * sw.E, nr, lane, wave);
+  else
+    stage_windows<NT, DT>(reinterpret_cast<float4*>(lds + L.off_win), reinterpret_cast<const RxRec*>(lds + L.off_rx),
+                          reinterpret_cast<const int*>(lds + L.off_n0), reinterpret_cast<const TxRec*>(lds + L.off_tx),
+                          sw, (long long)P0 * sw.E + q0, q0 - s0 * sw.E, nr, tid, lane, wave);
   __syncthreads();
 }
 

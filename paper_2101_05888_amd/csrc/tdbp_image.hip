@@ -72,7 +72,8 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
         const double dR = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
         const double ulo = ((dT + dR - 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
         const double uhi = ((dT + dR + 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
-        const bool rec_e = (uhi >= -2.0) && (ulo <= (double)sw.Ns + 1.0);
+        const double reach = sw.interp ? (double)kSincHalf : 0.0;   // taps beyond the delay
+        const bool rec_e = (uhi >= -2.0 - reach) && (ulo <= (double)sw.Ns + 1.0 + reach);
         const bool gate_e = sw.tan_g > 0.0 ? cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, R) : true;
         in_record |= rec_e && gate_e;
         rx_hit |= gate_e;
@@ -186,9 +187,97 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
   }
 }
 
+// sin(pi x) / pi for x in [0, 1], accurate relative to its value (the
+// hardware sine is accurate only in absolute terms, which is too coarse near
+// x = 0 and x = 1, where the central sinc tap divides by a small distance):
+// by symmetry x -> min(x, 1 - x) in [0, 1/2], then the Taylor series of
+// sin(pi x) / pi through x^11 (truncation below 6e-8 relative at x = 1/2).
+__device__ __forceinline__ float sin_pi_over_pi(float x) {
+  const float y = fminf(x, 1.0f - x);
+  const float y2 = y * y;
+  const float p2 = 9.8696044010893586f;   // pi^2
+  float h = -p2 / 39916800.0f * p2 * p2 * p2 * p2;   // -pi^10 / 11!
+  h = fmaf(h, y2, p2 * p2 * p2 * p2 / 362880.0f);    // +pi^8 / 9!
+  h = fmaf(h, y2, -p2 * p2 * p2 / 5040.0f);          // -pi^6 / 7!
+  h = fmaf(h, y2, p2 * p2 / 120.0f);                 // +pi^4 / 5!
+  h = fmaf(h, y2, -p2 / 6.0f);                       // -pi^2 / 3!
+  h = fmaf(h, y2, 1.0f);
+  return y * h;
+}
+
+// The windowed-sinc variant of accumulate(): L = sum over the 8 samples m
+// around u of E~[m] h(u - m), h(t) = sinc(t) (1 + cos(pi t / 4)) / 2. With
+// n = floor(s) and w = s - n (s the sample position in the window), tap j
+// (j = 0..7, sample n - 3 + j) is at t_j = w + 3 - j, and
+//   sinc(t_j) = (-1)^(3-j) sin(pi w) / (pi t_j),
+//   cos(pi t_j / 4) = cos(th) cos(j pi / 4) + sin(th) sin(j pi / 4), th = pi (w + 3) / 4,
+// so one sine, one sine/cosine pair and eight reciprocals serve the 8 taps.
+// w is kept in [1e-6, 1 - 1e-6] so that no t_j is zero (an offset of at most
+// 1e-6 samples). Gated-out pixels read samples 0..8 and are weighted by zero.
+template <int K, int LX, int DEG, bool TEST>
+__device__ __forceinline__ void accumulate_sinc(const RxRec& rec, const float2* __restrict__ win, const float* dx,
+                                                const float* dsq, const float* dT, float dyl, float dzl, float fs_c,
+                                                float fc_c, int da, int span, float* accr, float* acci) {
+  const float ryz = fmaf(rec.q0.y, dyl, rec.q0.z * dzl);
+  const float d0 = rec.q1.w;
+  const float d0sq = d0 * d0;
+  const unsigned wbase = lds_address(win) + 8u - (kRoundMagicBits << 3);   // entry of sample n - 3 is n + 1
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float num = fmaf(rec.q0.x, dx[k], ryz + dsq[k]);
+    float D;
+    if (DEG > 0) {
+      float h = DEG == 5 ? fmaf(rec.q1.z, num, rec.q2.w) : rec.q2.w;
+      h = fmaf(h, num, rec.q2.z);
+      h = fmaf(h, num, rec.q2.y);
+      h = fmaf(h, num, rec.q2.x);
+      D = fmaf(h, num, dT[k]);
+    } else {
+      const float sq = __builtin_amdgcn_sqrtf(d0sq + num);
+      D = fmaf(num, __builtin_amdgcn_rcpf(d0 + sq), dT[k]);
+    }
+    float sh = fmaf(D, fs_c, rec.q1.x);   // s - 1/2
+    const float cyc = fmaf(D, fc_c, rec.q1.y);
+    float keep = 1.0f;
+    if (TEST) {
+      const bool in = (unsigned)(da + LX * k) <= (unsigned)span;
+      sh = in ? sh : 0.0f;
+      keep = in ? 1.0f : 0.0f;
+    }
+    const float t = sh + kRoundMagic;                 // n = round(s - 1/2) = floor(s)
+    const float w = fminf(fmaxf(sh - (t - kRoundMagic) + 0.5f, 1e-6f), 1.0f - 1e-6f);
+    const unsigned addr = wbase + (__float_as_uint(t) << 3);
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const __attribute__((address_space(3))) f32x2* e =
+        reinterpret_cast<const __attribute__((address_space(3))) f32x2*>((uintptr_t)addr);
+    const float a = keep * sin_pi_over_pi(w) * 0.5f;  // sin(pi w) / pi, times the window's 1/2
+    const float th = (w + 3.0f) * 0.125f;             // revolutions: pi (w + 3) / 4
+    const float cth = __builtin_amdgcn_cosf(th), sth = __builtin_amdgcn_sinf(th);
+    float lr = 0.0f, li = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      constexpr float kC[8] = {1.0f, 0.70710678f, 0.0f, -0.70710678f, -1.0f, -0.70710678f, 0.0f, 0.70710678f};
+      constexpr float kS[8] = {0.0f, 0.70710678f, 1.0f, 0.70710678f, 0.0f, -0.70710678f, -1.0f, -0.70710678f};
+      const float tj = w + (float)(3 - j);
+      const float hann2 = fmaf(cth, kC[j], fmaf(sth, kS[j], 1.0f));   // 1 + cos(pi t_j / 4)
+      const float sg = ((3 - j) & 1) ? -a : a;                        // (-1)^(3-j) sin(pi w) / (2 pi)
+      const float hw = sg * __builtin_amdgcn_rcpf(tj) * hann2;
+      const f32x2 v = e[j];
+      lr = fmaf(hw, v.x, lr);
+      li = fmaf(hw, v.y, li);
+    }
+    const float sn = __builtin_amdgcn_sinf(cyc);
+    const float cs = __builtin_amdgcn_cosf(cyc);
+    accr[k] = fmaf(lr, cs, accr[k]);
+    accr[k] = fmaf(-li, sn, accr[k]);
+    acci[k] = fmaf(lr, sn, acci[k]);
+    acci[k] = fmaf(li, cs, acci[k]);
+  }
+}
+
 // The read-only tables are separate restrict-qualified arguments so that the
 // compiler may read them through the scalar cache.
-template <int L, bool GATE, int DT>
+template <int L, bool GATE, int DT, int INTERP>
 __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ)
 __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel(
     Workspace ws, const SwathDev* __restrict__ swaths, const int* __restrict__ order,
@@ -262,7 +351,7 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
         const int nr = min(RC, sc * E - q0);
         const int sa = q0 / E, sb = (q0 + nr - 1) / E;
         if (q0 > 0) __syncthreads();
-        load_chunk<NT, ROWS, GATE, DT>(lds, geo, sw, P0, q0, nr, sa, sb - sa + 1, Ld, tid, lane, wave);
+        load_chunk<NT, ROWS, GATE, DT, INTERP == 1>(lds, geo, sw, P0, q0, nr, sa, sb - sa + 1, Ld, tid, lane, wave);
         for (int slot = sa; slot <= sb; ++slot) {
           if (slot != dT_slot) {
             const TxRec tr = ltx[slot - sa];
@@ -281,6 +370,24 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
             if (f & kFlagSkip) continue;
             const RxRec rec = lrx[r];
             const float4* win = lwin + (size_t)r * (W + 1);
+            if (INTERP == 1) {
+              const float2* rwin = reinterpret_cast<const float2*>(win);
+              int da = 0, span = 0;
+              if (GATE && !(f & kFlagFull)) {
+                const int v = lrows[r * ROWS + row];
+                da = lx - row_lo(v);
+                span = row_hi(v) - row_lo(v);
+              }
+              const bool test = GATE && !(f & kFlagFull);
+              if (f & kFlagPoly) {
+                if (test) accumulate_sinc<K, LX, 5, true>(rec, rwin, dx, dsq, dT, dyl, dzl, fs_c, fc_c, da, span, accr, acci);
+                else accumulate_sinc<K, LX, 5, false>(rec, rwin, dx, dsq, dT, dyl, dzl, fs_c, fc_c, 0, 0, accr, acci);
+              } else {
+                if (test) accumulate_sinc<K, LX, 0, true>(rec, rwin, dx, dsq, dT, dyl, dzl, fs_c, fc_c, da, span, accr, acci);
+                else accumulate_sinc<K, LX, 0, false>(rec, rwin, dx, dsq, dT, dyl, dzl, fs_c, fc_c, 0, 0, accr, acci);
+              }
+              continue;
+            }
             if (!GATE || (f & kFlagFull)) {
               if (f & kFlagDeg4)
                 accumulate<K, LX, 4, false>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci);
@@ -322,35 +429,40 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
 
 typedef void (*ImageKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
 
-template <int L>
+template <int L, int INTERP>
 static ImageKernelFn image_for_layout(bool gate, int dt) {
   if (gate) {
     switch (dt) {
-      case 0: return image_kernel<L, true, 0>;
-      case 1: return image_kernel<L, true, 1>;
-      default: return image_kernel<L, true, 2>;
+      case 0: return image_kernel<L, true, 0, INTERP>;
+      case 1: return image_kernel<L, true, 1, INTERP>;
+      default: return image_kernel<L, true, 2, INTERP>;
     }
   }
   switch (dt) {
-    case 0: return image_kernel<L, false, 0>;
-    case 1: return image_kernel<L, false, 1>;
-    default: return image_kernel<L, false, 2>;
+    case 0: return image_kernel<L, false, 0, INTERP>;
+    case 1: return image_kernel<L, false, 1, INTERP>;
+    default: return image_kernel<L, false, 2, INTERP>;
   }
 }
 
-ImageKernelFn image_kernel_for(int layout, bool gate, int dt) {
+template <int INTERP>
+static ImageKernelFn image_for_interp(int layout, bool gate, int dt) {
   switch (layout) {
-    case 0: return image_for_layout<0>(gate, dt);
-    case 1: return image_for_layout<1>(gate, dt);
-    case 2: return image_for_layout<2>(gate, dt);
-    case 3: return image_for_layout<3>(gate, dt);
-    case 4: return image_for_layout<4>(gate, dt);
-    case 5: return image_for_layout<5>(gate, dt);
-    case 6: return image_for_layout<6>(gate, dt);
-    case 7: return image_for_layout<7>(gate, dt);
-    case 8: return image_for_layout<8>(gate, dt);
+    case 0: return image_for_layout<0, INTERP>(gate, dt);
+    case 1: return image_for_layout<1, INTERP>(gate, dt);
+    case 2: return image_for_layout<2, INTERP>(gate, dt);
+    case 3: return image_for_layout<3, INTERP>(gate, dt);
+    case 4: return image_for_layout<4, INTERP>(gate, dt);
+    case 5: return image_for_layout<5, INTERP>(gate, dt);
+    case 6: return image_for_layout<6, INTERP>(gate, dt);
+    case 7: return image_for_layout<7, INTERP>(gate, dt);
+    case 8: return image_for_layout<8, INTERP>(gate, dt);
     default: return nullptr;
   }
+}
+
+ImageKernelFn image_kernel_for(int layout, bool gate, int dt, int interp) {
+  return interp == 1 ? image_for_interp<1>(layout, gate, dt) : image_for_interp<0>(layout, gate, dt);
 }
 
 int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate) {

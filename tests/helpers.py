@@ -29,10 +29,10 @@ def workers() -> int:
     return max(1, min(16, n))
 
 
-def desc_for(api, scn: Scenario, echo_dtype: str = "c64", c_min: float = 0.0):
+def desc_for(api, scn: Scenario, echo_dtype: str = "c64", c_min: float = 0.0, interp: str = "linear"):
     g = scn.grid
     return api.swath_desc(scn.n_ping, scn.n_elem, scn.n_sample, g.n, g.origin, g.spacing,
-                          scn.fc, scn.fs, scn.t0, scn.gate_half_angle, echo_dtype, c_min)
+                          scn.fc, scn.fs, scn.t0, scn.gate_half_angle, echo_dtype, c_min, interp)
 
 
 def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scale=None,
@@ -51,8 +51,9 @@ def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scal
     )
 
 
-def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_scale=None, **plan_kw):
-    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype)], **plan_kw)
+def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_scale=None, interp="linear",
+              **plan_kw):
+    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype, interp=interp)], **plan_kw)
     buf = buffers_for(api, scn, echo, echo_scale=echo_scale)
     api.sas_bp_image(plan, [buf])
     torch.cuda.synchronize()
@@ -60,11 +61,12 @@ def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_sca
     return buf.image.cpu().numpy(), plan, buf
 
 
-def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None):
+def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None, interp="linear"):
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, index)
     return oracle.backproject(echo_np, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
-                              scn.gate_half_angle, workers=workers())
+                              scn.gate_half_angle, workers=workers(),
+                              interp="sinc" if interp == "sinc8" else interp)
 
 
 def report(name, img, ref):

@@ -325,3 +325,73 @@ def test_wide_tile_without_adjoint_still_images(api):
     with pytest.raises(SasBpError) as ei:
         api.sas_bp_adjoint(plan, [buf], [g], [gtx], [grx], [gc])
     assert ei.value.status == SAS_BP_EUNSUPPORTED
+
+
+# ------------------------------------------------- windowed-sinc variant ---
+
+@pytest.mark.parametrize("case", ["c1_ragged", "c2_small", "c3_small", "c5_small"])
+def test_sinc_image_matches_oracle(api, case):
+    name, kw = CASES[case]
+    print(f"sinc case {case}", flush=True)
+    scn, echo = _case(name, **kw)
+    img, plan, _ = gpu_image(api, scn, echo, interp="sinc8")
+    ref = oracle_image(scn, echo.numpy(), interp="sinc8").reshape(img.shape)
+    r, ph = report(f"sinc-{case}", img, ref)
+    assert np.abs(ref).max() > 0
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+    lin = oracle_image(scn, echo.numpy()).reshape(img.shape)
+    assert oracle.rel_l2(img, lin) > 10 * FP32_REL_L2      # a different interpolator
+
+
+@pytest.mark.parametrize("kw", [dict(elems_per_chunk=3), dict(tile=(64, 0, 0)), dict(pings_per_chunk=2)])
+def test_sinc_tilings_match_oracle(api, kw):
+    scn, echo = _case("c2", n_ping=24, n_elem=8, nx=150, ny=70, n_sample=4096, n_scat=30, n_speckle=100)
+    img, _, _ = gpu_image(api, scn, echo, interp="sinc8", **kw)
+    ref = oracle_image(scn, echo.numpy(), interp="sinc8").reshape(img.shape)
+    r, ph = report(f"sinc-{kw}", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+
+
+def test_sinc_sixteen_bit_storage(api):
+    scn, echo = _case("c1", n_ping=16, n_elem=4, nx=100, ny=77)
+    q, scale = quantize_echo(echo, "f16")
+    deq = dequantize_echo(q, scale)
+    img, _, _ = gpu_image(api, scn, q, echo_dtype="f16", echo_scale=scale, interp="sinc8")
+    ref = oracle_image(scn, deq.numpy(), interp="sinc8").reshape(img.shape)
+    r, ph = report("sinc-f16-compute", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+
+
+def test_sinc_plan_refuses_adjoint_and_reprojection(api):
+    from paper_2101_05888_amd._native import SasBpError, SAS_BP_EUNSUPPORTED
+    scn, echo = _case("c1", n_ping=8, n_elem=4, nx=48, ny=40)
+    img, plan, buf = gpu_image(api, scn, echo, interp="sinc8")
+    g = torch.zeros_like(buf.image)
+    with pytest.raises(SasBpError) as ei:
+        api.sas_bp_adjoint(plan, [buf], [g], [torch.zeros((8, 3), dtype=torch.float64, device="cuda")],
+                           [torch.zeros((8, 4, 3), dtype=torch.float64, device="cuda")],
+                           [torch.zeros(1, dtype=torch.float64, device="cuda")])
+    assert ei.value.status == SAS_BP_EUNSUPPORTED
+    with pytest.raises(SasBpError) as ei:
+        api.sas_bp_reproject(plan, [buf], [g], [torch.zeros_like(buf.echo)])
+    assert ei.value.status == SAS_BP_EUNSUPPORTED
+
+
+def test_full_size_sinc_sampled(api):
+    # the windowed-sinc variant on the operational swath at full size, default
+    # launch configuration, compared with the oracle's variant on 256 pixels
+    print("case c2 full size sinc", flush=True)
+    scn = make_config("c2")
+    echo = synthesize_echo(scn, device="cuda", dtype=torch.complex64)
+    plan = api.sas_bp_plan([desc_for(api, scn, interp="sinc8")])
+    buf = buffers_for(api, scn, echo)
+    api.sas_bp_image(plan, [buf])
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    idx = subset_indices(scn, 256)
+    img = buf.image.reshape(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    echo_np = echo.cpu().numpy()
+    del echo, buf
+    ref = oracle_image(scn, echo_np, idx, interp="sinc8")
+    r, ph = report("c2-full-sinc-subset", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
