@@ -4,6 +4,7 @@
 // workgroup reserves), for three instruction mixes:
 //   fma1  a = fma(a, 0.999, 1e-4)            one VGPR operand
 //   fma3  a = fma(a, c, d)                   three VGPR operands
+//   fmas  a = fma(a, s, d)                   two VGPR operands and one SGPR
 //   sin   8 fma3 + 2 v_sin_f32 per 8 chains  cost of a transcendental
 // Clock and CU count are the MI355X's (2.4 GHz, 256 CUs). Standalone
 // program; built next to the library by the package's build script.
@@ -26,7 +27,7 @@ constexpr int kBlocks = 256 * 16;
 constexpr int kIters = 1024;
 
 template <int MIX>
-__global__ __launch_bounds__(kThreads) void chains(float* out, int iters) {
+__global__ __launch_bounds__(kThreads) void chains(float* out, int iters, float su) {
   extern __shared__ float reserve[];   // occupancy control only
   float a[kChains], c[kChains];
   for (int i = 0; i < kChains; ++i) {
@@ -39,6 +40,8 @@ __global__ __launch_bounds__(kThreads) void chains(float* out, int iters) {
     for (int i = 0; i < kChains; ++i) {
       if (MIX == 0) {
         a[i] = __builtin_fmaf(a[i], 0.999f, 1e-4f);
+      } else if (MIX == 3) {
+        a[i] = __builtin_fmaf(a[i], su, c[i]);
       } else {
         a[i] = __builtin_fmaf(a[i], c[i], d);
         if (MIX == 2 && (i & 3) == 0) a[i] = __builtin_amdgcn_sinf(a[i]);
@@ -60,10 +63,10 @@ int run(const char* name, float* out, int lds) {
   hipEvent_t e0, e1;
   CHECK(hipEventCreate(&e0));
   CHECK(hipEventCreate(&e1));
-  hipLaunchKernelGGL(chains<MIX>, dim3(kBlocks), dim3(kThreads), lds, 0, out, kIters);   // warm-up
+  hipLaunchKernelGGL(chains<MIX>, dim3(kBlocks), dim3(kThreads), lds, 0, out, kIters, 0.999f);   // warm-up
   CHECK(hipGetLastError());
   CHECK(hipEventRecord(e0));
-  hipLaunchKernelGGL(chains<MIX>, dim3(kBlocks), dim3(kThreads), lds, 0, out, kIters);
+  hipLaunchKernelGGL(chains<MIX>, dim3(kBlocks), dim3(kThreads), lds, 0, out, kIters, 0.999f);
   CHECK(hipGetLastError());
   CHECK(hipEventRecord(e1));
   CHECK(hipEventSynchronize(e1));
@@ -87,6 +90,8 @@ int main() {
     if (run<0>("fma1", out, l)) return 1;
   for (int l : lds)
     if (run<1>("fma3", out, l)) return 1;
+  for (int l : lds)
+    if (run<3>("fmas", out, l)) return 1;
   for (int l : lds)
     if (run<2>("sin", out, l)) return 1;
   CHECK(hipFree(out));
