@@ -51,11 +51,12 @@ def flops_per_update(n_elem: int) -> float:
 
 
 def kernel_sources_digest() -> str:
-    """SHA-256 over the HIP sources, to tell whether counters still describe the kernel."""
+    """SHA-256 over the library's HIP sources (not the standalone issue probe),
+    to tell whether counters still describe the kernel."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2101_05888_amd", "csrc")
     for fn in sorted(os.listdir(d)):
-        if fn.endswith((".hip", ".h")):
+        if fn.endswith((".hip", ".h")) and fn != "issue_probe.hip":
             h.update(fn.encode())
             with open(os.path.join(d, fn), "rb") as f:
                 h.update(f.read())
