@@ -235,6 +235,26 @@ def sinc_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_kerne
             "rel_l2": r, "max_phase_mrad": ph, "sample_pixels": sample}
 
 
+def drc_leg(api, plan, image: torch.Tensor, steps: int, warmup: int) -> dict:
+    """Dynamic range compression of the operational image (16.7 M pixels) for
+    display at brightness 0.3: time, HBM bytes the algorithm moves (the image
+    read five times: maximum, three radix-select passes and the map; the FP32
+    output written once), and the largest difference from the FP64 oracle
+    over the whole image."""
+    import oracle
+    n = image.numel()
+    out = torch.empty(image.shape, dtype=torch.float32, device="cuda")
+    prm = torch.zeros(3, dtype=torch.float64, device="cuda")
+    ms = time_steps(lambda: api.sas_bp_drc(plan, image, 0.3, out, prm), steps, warmup)
+    moved = 5 * n * 8 + n * 4
+    ref, rp = oracle.drc(image.cpu().numpy().astype(np.complex128), 0.3)
+    err = float(np.abs(out.cpu().numpy() - ref).max())
+    log(f"drc: {ms:.3f} ms for {n} pixels, {moved / (ms * 1e-3) / 1e9:.0f} GB/s, max |out - oracle| {err:.1e}")
+    return {"pixels": int(n), "ms": ms, "algorithmic_bytes": moved, "gb_per_s": moved / (ms * 1e-3) / 1e9,
+            "hbm_peak_frac": moved / (ms * 1e-3) / 8e12, "max_abs_error_vs_oracle": err,
+            "q": float(prm[2]), "median": float(prm[1])}
+
+
 def volume_leg(api, steps: int, warmup: int) -> dict:
     """The 3D workload at full size: 256 pings x 64 receivers (32 across x 2
     along), 8192 samples, 512 x 512 x 128 voxels at 2 cm, no gate. The seabed
@@ -364,6 +384,7 @@ def main() -> int:
     ap.add_argument("--no-reprojection", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-sinc", action="store_true")
+    ap.add_argument("--no-drc", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -375,7 +396,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
-        args.no_reprojection = args.no_volume = args.no_sinc = True
+        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -469,6 +490,8 @@ def main() -> int:
             del q, b2
         out["mixed"] = mixed
 
+    if not args.no_drc:
+        out["drc"] = drc_leg(api, plan, buf.image, max(3, args.steps // 4), 1)
     if not args.no_sinc:
         out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_reprojection:

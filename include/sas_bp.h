@@ -194,6 +194,19 @@ int sas_bp_useful_updates(sas_bp_plan_t plan, const sas_bp_swath_io* io, int n_s
 int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, double* out_S,
                      void* grad_image, void* stream);
 
+/* Dynamic range compression of an image for display (Eqs. 11-12, Sec.
+ * II-E). x = |I| / max |I| over the n_pix complex64 pixels of image; each
+ * pixel maps to out[i] = q x / ((q - 1) x + 1) (FP32, n_pix floats), with
+ * q = (b - b x~) / (x~ - b x~) so that the median x~ (the element of rank
+ * floor((n_pix - 1) / 2)) maps to the brightness b in (0, 1). Degenerate
+ * images: all zero -> zeros (q = 1); x~ = 0 -> every non-zero pixel to 1
+ * (q = +inf); x~ = 1 -> every pixel below the maximum to 0 (q = 0). The
+ * median is an exact radix selection on the FP32 squared magnitudes. If
+ * params is not NULL it receives (device memory, 3 doubles) max |I|, x~ and
+ * q. n_pix in [1, 2^31]. The plan lends a small workspace; asynchronous. */
+int sas_bp_drc(sas_bp_plan_t plan, const void* image, int64_t n_pix, double brightness, float* out,
+               double* params, void* stream);
+
 /* Sticky device-detected status of the plan (SAS_BP_OK or SAS_BP_ENAV);
  * synchronises with the device and clears it. */
 int sas_bp_plan_status(sas_bp_plan_t plan);

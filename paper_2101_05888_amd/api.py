@@ -206,6 +206,21 @@ def sas_bp_reproject(plan: Plan, bufs: Sequence[SwathBuffers], images_in: Sequen
     check(N.lib().sas_bp_reproject(plan.handle, arr, yi, eo, n, _stream(plan.device, stream)), "sas_bp_reproject")
 
 
+def sas_bp_drc(plan: Plan, image: torch.Tensor, brightness: float, out: torch.Tensor,
+               params: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Dynamic range compression for display: out (float32, image's shape) from
+    a complex64 image; params (float64 [3], optional) gets max |I|, the
+    normalised median and q."""
+    if image.dtype != torch.complex64 or not image.is_contiguous() or image.device.type != "cuda":
+        raise ValueError("image must be a contiguous complex64 device tensor")
+    _need(out, "out", torch.float32, tuple(image.shape), plan.device)
+    if params is not None:
+        _need(params, "params", torch.float64, (3,), plan.device)
+    check(N.lib().sas_bp_drc(plan.handle, image.data_ptr(), image.numel(), float(brightness), out.data_ptr(),
+                             params.data_ptr() if params is not None else None, _stream(plan.device, stream)),
+          "sas_bp_drc")
+
+
 def sas_bp_useful_updates(plan: Plan, bufs: Sequence[SwathBuffers], stream=None) -> list:
     arr = _io(plan, bufs)
     out = (C.c_int64 * len(bufs))()

@@ -52,6 +52,9 @@ hipError_t launch_reproject(ReprojectKernelFn fn, const Workspace& ws, int n_til
 hipError_t launch_zero_rows(void* p, long long n, hipStream_t st);
 hipError_t reproject_occupancy(ReprojectKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu);
 hipError_t set_reproject_lds_limit(ReprojectKernelFn fn, int lds_bytes);
+hipError_t launch_drc(const void* image, long long n, double brightness, float* out, double* params, void* work,
+                      hipStream_t st);
+size_t drc_work_bytes();
 hipError_t launch_adjoint_reduce(const Workspace& ws, int n_swaths, int max_p, hipStream_t st);
 hipError_t launch_count(const Workspace& ws, int s, int P, int E, int rows, unsigned long long* out, hipStream_t st);
 hipError_t launch_sharpness(const void* image, long long n, double* partials, double* out_S, void* grad,
@@ -101,7 +104,7 @@ struct SwathPlan {
 };
 
 struct Layout {
-  size_t swaths, prange, order, counters, bucket, tile_swath, scratch, geo, total;
+  size_t swaths, prange, order, counters, bucket, tile_swath, scratch, drc, geo, total;
   size_t geo_stride;   // bytes of geometry scratch per resident workgroup
   int geo_slots;       // resident workgroups the geometry scratch serves
   size_t n_partials;   // adjoint records, allocated on the first adjoint call
@@ -322,6 +325,7 @@ Layout make_layout(int n_swaths, int n_tiles, size_t n_partials, size_t geo_stri
   L.bucket = o;     o = align_up(o + sizeof(unsigned) * kBuckets);
   L.tile_swath = o; o = align_up(o + sizeof(int) * n_tiles);
   L.scratch = o;    o = align_up(o + sizeof(double) * (2 * kSharpPartials + 64));
+  L.drc = o;        o = align_up(o + drc_work_bytes());
   L.geo = o;        o = align_up(o + geo_stride * (size_t)geo_slots);
   L.geo_stride = geo_stride;
   L.geo_slots = geo_slots;
@@ -839,6 +843,21 @@ int sas_bp_reproject(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* con
     HIP_TRY(hipEventRecord(eb, st));
     ++p->n_timed;
   }
+  return SAS_BP_OK;
+}
+
+int sas_bp_drc(sas_bp_plan_t p, const void* image, int64_t n_pix, double brightness, float* out, double* params,
+               void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  if (!image || !out) return fail(SAS_BP_EINVAL, "image or out is NULL");
+  if (n_pix < 1 || n_pix > (int64_t)1 << 31) return fail(SAS_BP_EINVAL, "n_pix must be in [1, 2^31]");
+  if (!(brightness > 0.0 && brightness < 1.0)) return fail(SAS_BP_EINVAL, "brightness must lie in (0, 1)");
+  if (((uintptr_t)image & 7u) || ((uintptr_t)out & 3u) || ((uintptr_t)params & 7u))
+    return fail(SAS_BP_EINVAL, "image, out or params misaligned");
+  DeviceGuard guard(p->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(launch_drc(image, (long long)n_pix, brightness, out, params, p->slab + p->lay.drc, st));
   return SAS_BP_OK;
 }
 
