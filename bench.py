@@ -50,13 +50,16 @@ def flops_per_update(n_elem: int) -> float:
     return 32.0 + 9.0 / n_elem
 
 
+IMAGE_KERNEL_SOURCES = ("plan.hip", "tdbp_dev.h", "tdbp_geom.h", "tdbp_image.hip")
+
+
 def kernel_sources_digest() -> str:
-    """SHA-256 over the library's HIP sources (not the standalone issue probe),
-    to tell whether counters still describe the kernel."""
+    """SHA-256 over the sources the image kernel and its launch configuration
+    are built from, to tell whether counters still describe the kernel."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2101_05888_amd", "csrc")
     for fn in sorted(os.listdir(d)):
-        if fn.endswith((".hip", ".h")) and fn != "issue_probe.hip":
+        if fn in IMAGE_KERNEL_SOURCES:
             h.update(fn.encode())
             with open(os.path.join(d, fn), "rb") as f:
                 h.update(f.read())
