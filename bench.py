@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -53,16 +54,24 @@ def flops_per_update(n_elem: int) -> float:
 IMAGE_KERNEL_SOURCES = ("plan.hip", "tdbp_dev.h", "tdbp_geom.h", "tdbp_image.hip")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace collapsed."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_sources_digest() -> str:
-    """SHA-256 over the sources the image kernel and its launch configuration
-    are built from, to tell whether counters still describe the kernel."""
+    """SHA-256 over the code (comments and layout ignored) of the sources the
+    image kernel and its launch configuration are built from, to tell whether
+    counters still describe the kernel."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2101_05888_amd", "csrc")
     for fn in sorted(os.listdir(d)):
         if fn in IMAGE_KERNEL_SOURCES:
             h.update(fn.encode())
-            with open(os.path.join(d, fn), "rb") as f:
-                h.update(f.read())
+            with open(os.path.join(d, fn), encoding="utf-8") as f:
+                h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 

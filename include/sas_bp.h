@@ -107,7 +107,8 @@ typedef struct {
 typedef struct {
     int32_t device;          /* HIP device ordinal                             */
     int32_t tile_x, tile_y, tile_z; /* pixel tile shape; 0 = automatic         */
-    int32_t pings_per_chunk; /* pings staged in LDS per pass; 0 = automatic   */
+    int32_t pings_per_chunk; /* pings staged in LDS per pass (the adjoint's, and the
+                                image's unless elems_per_chunk is set); 0 = automatic */
     int32_t threads;         /* threads per workgroup (256 or 512); 0 = automatic */
     int32_t use_graph;       /* 1 = replay a captured HIP graph (default), 0 = direct launches */
     int32_t elems_per_chunk; /* image: (ping, element) records staged per pass when

@@ -1,7 +1,7 @@
 // Plan, workspace slab, graph capture/replay and the exported C ABI.
 //
 // A plan is made once per set of swath shapes. It validates the descriptors on
-// the host, picks the tile shape and the pings staged per pass, sizes one
+// the host, picks the tile shape and the records staged per pass, sizes one
 // device slab for every buffer the kernels need (one allocation, the slab
 // scheme of Sec. II-C), and captures the launch sequence
 //     init -> cull -> cost order -> persistent image kernel

@@ -11,14 +11,16 @@
 // the FP64 reference geometry of every (ping, element) and, with a beam gate,
 // the exact per-row gate intervals (Sec. II-C; transmitter and receiver
 // tested separately as in the bistatic case, Sec. III-B), into its own
-// region of the workspace. Then, per chunk of pings of the run, it
+// region of the workspace. Then, per chunk of consecutive (ping, element)
+// records of the run (part of a ping, one ping or several, sized so that
+// three workgroups share a CU), it
 //   1. copies the chunk's records and gate rows into LDS;
 //   2. copies each (ping, element)'s echo window into LDS with coalesced loads,
 //      zero-filling samples outside the record and converting FP16/BF16
 //      storage to FP32;
 //   3. updates K pixels per lane per (ping, element): FP32 delay offset,
-//      linear interpolation from LDS, carrier phase via the hardware sin/cos
-//      (which take revolutions), complex multiply-accumulate.
+//      linear (or windowed-sinc) interpolation from LDS, carrier phase via the
+//      hardware sin/cos (which take revolutions), complex multiply-accumulate.
 #include "tdbp_geom.h"
 
 namespace sasbp {
