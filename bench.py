@@ -267,6 +267,30 @@ def drc_leg(api, plan, image: torch.Tensor, steps: int, warmup: int) -> dict:
             "q": float(prm[2]), "median": float(prm[1])}
 
 
+def tvg_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
+    """Time-varying gain (Eq. 10) of the operational echo cube (512 x 32 x
+    16384 complex samples, on a copy): time and the HBM bytes the algorithm
+    moves (the cube read by three radix-select passes, then read and written
+    by the gain)."""
+    x = echo.clone()
+    n = x.numel()
+    api.sas_bp_tvg(plan, 0, x, 0.1)   # warm-up (also allocates the workspace)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        api.sas_bp_tvg(plan, 0, x, 0.1)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    moved = 5 * n * 8
+    log(f"tvg: {ms:.3f} ms for {n} samples, {moved / (ms * 1e-3) / 1e9:.0f} GB/s")
+    del x
+    return {"samples": int(n), "ms": ms, "algorithmic_bytes": moved, "gb_per_s": moved / (ms * 1e-3) / 1e9,
+            "hbm_peak_frac": moved / (ms * 1e-3) / 8e12}
+
+
 def volume_leg(api, steps: int, warmup: int) -> dict:
     """The 3D workload at full size: 256 pings x 64 receivers (32 across x 2
     along), 8192 samples, 512 x 512 x 128 voxels at 2 cm, no gate. The seabed
@@ -397,6 +421,7 @@ def main() -> int:
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-sinc", action="store_true")
     ap.add_argument("--no-drc", action="store_true")
+    ap.add_argument("--no-tvg", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -408,7 +433,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
-        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = True
+        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -504,6 +529,8 @@ def main() -> int:
 
     if not args.no_drc:
         out["drc"] = drc_leg(api, plan, buf.image, max(3, args.steps // 4), 1)
+    if not args.no_tvg:
+        out["tvg"] = tvg_leg(api, plan, echo, 3)
     if not args.no_sinc:
         out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_reprojection:

@@ -195,6 +195,19 @@ int sas_bp_useful_updates(sas_bp_plan_t plan, const sas_bp_swath_io* io, int n_s
 int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, double* out_S,
                      void* grad_image, void* stream);
 
+/* Time-varying gain of swath `swath`'s echo cube, in place (Eq. 10, Sec.
+ * II-E): per sample time t, P~(t) = the population median of |E|^2 over all
+ * (ping, element) (the element of rank floor((P E - 1) / 2)), and the power
+ * gain G(t) = (alpha mean_t P~ + P~(t))^-1, applied as sqrt(G(t)) to the
+ * complex samples; a time whose G is not finite (alpha = 0 and a zero
+ * median) is left unchanged. echo is complex64 [P][E][N_s] with the swath's
+ * sizes, whatever the plan's echo dtype (the gain conditions the echo before
+ * any 16-bit storage). If gain_out is not NULL it receives G as f32[N_s]
+ * (device memory). alpha >= 0. The medians are exact radix selections on the
+ * FP32 squared magnitudes. The plan allocates 8 N_s bytes of workspace on
+ * the first call. Asynchronous on `stream`. */
+int sas_bp_tvg(sas_bp_plan_t plan, int swath, void* echo, double alpha, float* gain_out, void* stream);
+
 /* Dynamic range compression of an image for display (Eqs. 11-12, Sec.
  * II-E). x = |I| / max |I| over the n_pix complex64 pixels of image; each
  * pixel maps to out[i] = q x / ((q - 1) x + 1) (FP32, n_pix floats), with

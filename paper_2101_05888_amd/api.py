@@ -206,6 +206,19 @@ def sas_bp_reproject(plan: Plan, bufs: Sequence[SwathBuffers], images_in: Sequen
     check(N.lib().sas_bp_reproject(plan.handle, arr, yi, eo, n, _stream(plan.device, stream)), "sas_bp_reproject")
 
 
+def sas_bp_tvg(plan: Plan, swath: int, echo: torch.Tensor, alpha: float,
+               gain_out: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Time-varying gain of a complex64 echo cube [P, E, N_s], in place;
+    gain_out (float32 [N_s], optional) receives the power gain G(t)."""
+    d = plan.descs[swath]
+    _need(echo, "echo", torch.complex64, (d.n_ping, d.n_elem, d.n_sample), plan.device)
+    if gain_out is not None:
+        _need(gain_out, "gain_out", torch.float32, (d.n_sample,), plan.device)
+    check(N.lib().sas_bp_tvg(plan.handle, int(swath), echo.data_ptr(), float(alpha),
+                             gain_out.data_ptr() if gain_out is not None else None, _stream(plan.device, stream)),
+          "sas_bp_tvg")
+
+
 def sas_bp_drc(plan: Plan, image: torch.Tensor, brightness: float, out: torch.Tensor,
                params: Optional[torch.Tensor] = None, stream=None) -> None:
     """Dynamic range compression for display: out (float32, image's shape) from

@@ -55,6 +55,8 @@ hipError_t set_reproject_lds_limit(ReprojectKernelFn fn, int lds_bytes);
 hipError_t launch_drc(const void* image, long long n, double brightness, float* out, double* params, void* work,
                       hipStream_t st);
 size_t drc_work_bytes();
+hipError_t launch_tvg(void* echo, long long rows, int Ns, double alpha, float* work, float* gain_out,
+                      hipStream_t st);
 hipError_t launch_adjoint_reduce(const Workspace& ws, int n_swaths, int max_p, hipStream_t st);
 hipError_t launch_count(const Workspace& ws, int s, int P, int E, int rows, unsigned long long* out, hipStream_t st);
 hipError_t launch_sharpness(const void* image, long long n, double* partials, double* out_S, void* grad,
@@ -133,6 +135,7 @@ struct sas_bp_plan_s {
   int max_p = 0;
   bool use_graph = true;
   void* adj_buf = nullptr;   // adjoint partials + sound-speed partials
+  void* tvg_buf = nullptr;   // time-varying gain: medians and factors per sample time
   std::vector<SwathPlan> sw;
   Layout lay{};
   unsigned char* slab = nullptr;
@@ -472,6 +475,7 @@ void release(sas_bp_plan_s* p) {
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   if (p->host_sw) (void)hipHostFree(p->host_sw);
   if (p->adj_buf) (void)hipFree(p->adj_buf);
+  if (p->tvg_buf) (void)hipFree(p->tvg_buf);
   if (p->slab) (void)hipFree(p->slab);
   (void)hipSetDevice(cur);
   delete p;
@@ -858,6 +862,30 @@ int sas_bp_drc(sas_bp_plan_t p, const void* image, int64_t n_pix, double brightn
   DeviceGuard guard(p->device);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(launch_drc(image, (long long)n_pix, brightness, out, params, p->slab + p->lay.drc, st));
+  return SAS_BP_OK;
+}
+
+int sas_bp_tvg(sas_bp_plan_t p, int swath, void* echo, double alpha, float* gain_out, void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  if (swath < 0 || swath >= p->n_swaths) return fail(SAS_BP_EINVAL, "swath %d out of range", swath);
+  if (!echo) return fail(SAS_BP_EINVAL, "echo is NULL");
+  if (((uintptr_t)echo & 7u) || ((uintptr_t)gain_out & 3u)) return fail(SAS_BP_EINVAL, "echo or gain_out misaligned");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SAS_BP_EINVAL, "alpha must be finite and >= 0");
+  const auto& d = p->sw[swath].d;
+  DeviceGuard guard(p->device);
+  if (!p->tvg_buf) {
+    int max_ns = 0;
+    for (const auto& s : p->sw) max_ns = std::max(max_ns, s.d.n_sample);
+    if (hipMalloc(&p->tvg_buf, sizeof(float) * 2 * (size_t)max_ns) != hipSuccess) {
+      p->tvg_buf = nullptr;
+      return fail(SAS_BP_ENOMEM, "time-varying gain workspace of %zu bytes could not be allocated",
+                  sizeof(float) * 2 * (size_t)max_ns);
+    }
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(launch_tvg(echo, (long long)d.n_ping * d.n_elem, d.n_sample, alpha, reinterpret_cast<float*>(p->tvg_buf),
+                     gain_out, st));
   return SAS_BP_OK;
 }
 
