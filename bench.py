@@ -291,6 +291,26 @@ def tvg_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
             "hbm_peak_frac": moved / (ms * 1e-3) / 8e12}
 
 
+def whiten_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
+    """Spectral whitening (Eq. 9) of the operational echo cube on a copy:
+    forward FFT, power estimate, gain, inverse FFT (16384 rows of 16384
+    points)."""
+    x = echo.clone()
+    api.sas_bp_whiten(plan, 0, x, 0.1)   # warm-up (also makes the FFT plan)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        api.sas_bp_whiten(plan, 0, x, 0.1)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    log(f"whiten: {ms:.3f} ms for {x.numel()} samples")
+    del x
+    return {"samples": int(echo.numel()), "ms": ms}
+
+
 def volume_leg(api, steps: int, warmup: int) -> dict:
     """The 3D workload at full size: 256 pings x 64 receivers (32 across x 2
     along), 8192 samples, 512 x 512 x 128 voxels at 2 cm, no gate. The seabed
@@ -422,6 +442,7 @@ def main() -> int:
     ap.add_argument("--no-sinc", action="store_true")
     ap.add_argument("--no-drc", action="store_true")
     ap.add_argument("--no-tvg", action="store_true")
+    ap.add_argument("--no-whiten", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -433,7 +454,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
-        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = True
+        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -531,6 +552,8 @@ def main() -> int:
         out["drc"] = drc_leg(api, plan, buf.image, max(3, args.steps // 4), 1)
     if not args.no_tvg:
         out["tvg"] = tvg_leg(api, plan, echo, 3)
+    if not args.no_whiten:
+        out["whiten"] = whiten_leg(api, plan, echo, 3)
     if not args.no_sinc:
         out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_reprojection:

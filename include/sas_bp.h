@@ -195,6 +195,18 @@ int sas_bp_useful_updates(sas_bp_plan_t plan, const sas_bp_swath_io* io, int n_s
 int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, double* out_S,
                      void* grad_image, void* stream);
 
+/* Spectral whitening of swath `swath`'s echo cube, in place (Eq. 9, Sec.
+ * II-E): with X the DFT of each (ping, element) row of N_s samples, the power
+ * estimate P^(f) = mean over rows of |X(f)|^2 and the power gain
+ * G(f) = h(1 / (gamma mean_f P^ + P^(f))), h the normalisation to max G = 1
+ * (0 dB smallest attenuation); every row's spectrum is multiplied by
+ * sqrt(G(f)) and transformed back. echo is complex64 [P][E][N_s] with the
+ * swath's sizes. gamma >= 0. Transforms are rocFFT's (through hipFFT); the
+ * power sums are FP64 in a fixed order. The plan makes the swath's FFT plan
+ * and a workspace of 8 (65 N_s) + 4 N_s bytes on the first call.
+ * Asynchronous on `stream`. */
+int sas_bp_whiten(sas_bp_plan_t plan, int swath, void* echo, double gamma, void* stream);
+
 /* Time-varying gain of swath `swath`'s echo cube, in place (Eq. 10, Sec.
  * II-E): per sample time t, P~(t) = the population median of |E|^2 over all
  * (ping, element) (the element of rank floor((P E - 1) / 2)), and the power

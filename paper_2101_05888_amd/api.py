@@ -206,6 +206,14 @@ def sas_bp_reproject(plan: Plan, bufs: Sequence[SwathBuffers], images_in: Sequen
     check(N.lib().sas_bp_reproject(plan.handle, arr, yi, eo, n, _stream(plan.device, stream)), "sas_bp_reproject")
 
 
+def sas_bp_whiten(plan: Plan, swath: int, echo: torch.Tensor, gamma: float, stream=None) -> None:
+    """Spectral whitening of a complex64 echo cube [P, E, N_s], in place."""
+    d = plan.descs[swath]
+    _need(echo, "echo", torch.complex64, (d.n_ping, d.n_elem, d.n_sample), plan.device)
+    check(N.lib().sas_bp_whiten(plan.handle, int(swath), echo.data_ptr(), float(gamma),
+                                _stream(plan.device, stream)), "sas_bp_whiten")
+
+
 def sas_bp_tvg(plan: Plan, swath: int, echo: torch.Tensor, alpha: float,
                gain_out: Optional[torch.Tensor] = None, stream=None) -> None:
     """Time-varying gain of a complex64 echo cube [P, E, N_s], in place;

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsas_bp.so")
-SOURCES = ["plan.hip", "tdbp_image.hip", "tdbp_adjoint.hip", "tdbp_reproject.hip", "tdbp_drc.hip", "tdbp_tvg.hip"]
+SOURCES = ["plan.hip", "tdbp_image.hip", "tdbp_adjoint.hip", "tdbp_reproject.hip", "tdbp_drc.hip", "tdbp_tvg.hip", "tdbp_whiten.hip"]
 PROBE = os.path.join(HERE, "issue_probe")   # VALU issue-rate microbenchmark (standalone program)
 ARCH = os.environ.get("SAS_BP_ARCH", "gfx950")
 
@@ -55,7 +55,9 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(hipcc()))), "lib")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           f"-L{rocm_lib}", f"-Wl,-rpath,{rocm_lib}", "-lhipfft"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

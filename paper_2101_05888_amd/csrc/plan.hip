@@ -57,6 +57,10 @@ hipError_t launch_drc(const void* image, long long n, double brightness, float* 
 size_t drc_work_bytes();
 hipError_t launch_tvg(void* echo, long long rows, int Ns, double alpha, float* work, float* gain_out,
                       hipStream_t st);
+size_t whiten_work_bytes(int Ns);
+int launch_whiten(void* fft_plan, void* echo, long long rows, int Ns, double gamma, void* work, hipStream_t st);
+int make_fft_plan(int Ns, long long rows, void** out);
+void destroy_fft_plan(void* p);
 hipError_t launch_adjoint_reduce(const Workspace& ws, int n_swaths, int max_p, hipStream_t st);
 hipError_t launch_count(const Workspace& ws, int s, int P, int E, int rows, unsigned long long* out, hipStream_t st);
 hipError_t launch_sharpness(const void* image, long long n, double* partials, double* out_S, void* grad,
@@ -136,6 +140,8 @@ struct sas_bp_plan_s {
   bool use_graph = true;
   void* adj_buf = nullptr;   // adjoint partials + sound-speed partials
   void* tvg_buf = nullptr;   // time-varying gain: medians and factors per sample time
+  void* whiten_buf = nullptr;          // whitening: partial power sums, estimate, factors
+  std::vector<void*> fft_plans;        // per swath, made on the first whitening call
   std::vector<SwathPlan> sw;
   Layout lay{};
   unsigned char* slab = nullptr;
@@ -476,6 +482,8 @@ void release(sas_bp_plan_s* p) {
   if (p->host_sw) (void)hipHostFree(p->host_sw);
   if (p->adj_buf) (void)hipFree(p->adj_buf);
   if (p->tvg_buf) (void)hipFree(p->tvg_buf);
+  if (p->whiten_buf) (void)hipFree(p->whiten_buf);
+  for (void* f : p->fft_plans) destroy_fft_plan(f);
   if (p->slab) (void)hipFree(p->slab);
   (void)hipSetDevice(cur);
   delete p;
@@ -862,6 +870,36 @@ int sas_bp_drc(sas_bp_plan_t p, const void* image, int64_t n_pix, double brightn
   DeviceGuard guard(p->device);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(launch_drc(image, (long long)n_pix, brightness, out, params, p->slab + p->lay.drc, st));
+  return SAS_BP_OK;
+}
+
+int sas_bp_whiten(sas_bp_plan_t p, int swath, void* echo, double gamma, void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  if (swath < 0 || swath >= p->n_swaths) return fail(SAS_BP_EINVAL, "swath %d out of range", swath);
+  if (!echo) return fail(SAS_BP_EINVAL, "echo is NULL");
+  if ((uintptr_t)echo & 7u) return fail(SAS_BP_EINVAL, "echo misaligned");
+  if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(SAS_BP_EINVAL, "gamma must be finite and >= 0");
+  const auto& d = p->sw[swath].d;
+  const long long rows = (long long)d.n_ping * d.n_elem;
+  if (rows > 0x7fffffffll) return fail(SAS_BP_EUNSUPPORTED, "too many rows for one batched transform");
+  DeviceGuard guard(p->device);
+  if (!p->whiten_buf) {
+    size_t bytes = 0;
+    for (const auto& s : p->sw) bytes = std::max(bytes, whiten_work_bytes(s.d.n_sample));
+    if (hipMalloc(&p->whiten_buf, bytes) != hipSuccess) {
+      p->whiten_buf = nullptr;
+      return fail(SAS_BP_ENOMEM, "whitening workspace of %zu bytes could not be allocated", bytes);
+    }
+  }
+  if (p->fft_plans.empty()) p->fft_plans.assign(p->n_swaths, nullptr);
+  if (!p->fft_plans[swath] && make_fft_plan(d.n_sample, rows, &p->fft_plans[swath]) != 0) {
+    p->fft_plans[swath] = nullptr;
+    return fail(SAS_BP_EDEVICE, "FFT plan for %d x %lld samples could not be made", d.n_sample, rows);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int rc = launch_whiten(p->fft_plans[swath], echo, rows, d.n_sample, gamma, p->whiten_buf, st);
+  if (rc) return fail(SAS_BP_EDEVICE, "whitening failed (%s)", rc == 2 ? "FFT" : rc == 1 ? "FFT stream" : "kernel");
   return SAS_BP_OK;
 }
 
