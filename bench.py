@@ -51,7 +51,11 @@ def flops_per_update(n_elem: int) -> float:
     return 32.0 + 9.0 / n_elem
 
 
-IMAGE_KERNEL_SOURCES = ("plan.hip", "tdbp_dev.h", "tdbp_geom.h", "tdbp_image.hip")
+IMAGE_KERNEL_SOURCES = ("tdbp_dev.h", "tdbp_geom.h", "tdbp_image.hip")
+# Plan fields that fix the image kernel's launch (tile, chunking, LDS, grid,
+# occupancy); the committed counters hold the values they were taken with.
+LAUNCH_KEYS = ("tile_x", "tile_y", "tile_z", "pings_per_chunk", "window", "lds_bytes", "grid", "threads",
+               "records_per_chunk", "workgroups_per_cu")
 
 
 def _code_only(text: str) -> str:
@@ -63,8 +67,7 @@ def _code_only(text: str) -> str:
 
 def kernel_sources_digest() -> str:
     """SHA-256 over the code (comments and layout ignored) of the sources the
-    image kernel and its launch configuration are built from, to tell whether
-    counters still describe the kernel."""
+    image kernel is compiled from, to tell whether counters still describe it."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2101_05888_amd", "csrc")
     for fn in sorted(os.listdir(d)):
@@ -75,19 +78,28 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def committed_counters():
-    """Key/value lines of the committed counter summary, or {} when the kernel
-    sources changed since the counters were taken."""
+def launch_config_string(info: dict) -> str:
+    return " ".join(f"{k}={int(info[k])}" for k in LAUNCH_KEYS)
+
+
+def committed_counters(info: dict):
+    """Key/value lines of the committed counter summary, or {} when the image
+    kernel's code or its launch configuration (``info``, the plan's fields)
+    differ from those the counters were taken with."""
     try:
         with open(TRAFFIC_SUMMARY) as f:
             kv = dict((k.strip(), v.strip()) for k, v in
                       (l.split(":", 1) for l in f.read().splitlines() if ":" in l and not l.startswith(" ")))
     except OSError:
         return {}
-    return kv if kv.get("kernel_sources_sha256") == kernel_sources_digest() else {}
+    if kv.get("kernel_sources_sha256") != kernel_sources_digest():
+        return {}
+    if kv.get("launch_config") != launch_config_string(info):
+        return {}
+    return kv
 
 
-def issue_roofline(kernel_ms: float):
+def issue_roofline(kernel_ms: float, info: dict):
     """Instruction-issue roofline of the image kernel: VALU wave-instructions
     per launch (committed counters) per CU clock (256 CUs at 2.4 GHz).
 
@@ -98,7 +110,7 @@ def issue_roofline(kernel_ms: float):
     (the issue_probe microbenchmark) at 8 waves per SIMD: 1.44 with one VGPR
     operand, 1.18 with three (1.00 with three at the 3 waves per SIMD the
     image kernel runs with)."""
-    kv = committed_counters()
+    kv = committed_counters(info)
     try:
         valu = float(kv["valu_wave_instructions_per_launch"])
         trans = float(kv["trans_wave_instructions_per_launch"])
@@ -114,19 +126,12 @@ def issue_roofline(kernel_ms: float):
             "frac_of_measured_ceilings": {k: rate / v for k, v in ceilings.items()}}
 
 
-def measured_traffic():
+def measured_traffic(info: dict):
     """HBM bytes per image-kernel launch from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE scaled by the copy calibration), or None when the
-    kernel sources changed since the counters were taken."""
+    kernel or its launch configuration changed since the counters were taken."""
     try:
-        with open(TRAFFIC_SUMMARY) as f:
-            kv = dict(l.split(":", 1) for l in f.read().splitlines() if ":" in l and not l.startswith(" "))
-    except OSError:
-        return None
-    if kv.get("kernel_sources_sha256", "").strip() != kernel_sources_digest():
-        return None
-    try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(committed_counters(info)["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -529,10 +534,10 @@ def main() -> int:
         "graph_ms_per_step": graph_ms,
         "image_kernel_ms": kernel_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(info),
                      "flops_per_update": fpu, "kernel": "image_kernel", "launch_ms": kernel_ms,
                      "updates_per_launch": int(useful)},
-        "issue_roofline": issue_roofline(kernel_ms),
+        "issue_roofline": issue_roofline(kernel_ms, info),
     }
 
     if not args.no_mixed:
