@@ -11,7 +11,8 @@ Sec. II-C evaluated per term, and of its gradient with respect to the
 navigation and the sound speed, and of its linear adjoint with respect to the
 echo (reprojection), and of the dynamic range compression applied to the
 image for display (Eqs. 11-12) and of the time-varying gain and spectral
-whitening applied to the echoes (Eqs. 9-10). It shares no code with the HIP path.
+whitening applied to the echoes (Eqs. 9-10) and of the range compression
+that produces them (the matched filter with Eq. 1's waveform q). It shares no code with the HIP path.
 """
 from .tdbp import (pixel_points, backproject, backproject_image, gated_term_count,
                    gated_term_count_rows, vjp, vjp_segment_bound, reproject, sharpness,
@@ -20,8 +21,9 @@ from .metrics import rel_l2, phase_error_mrad
 from .drc import drc
 from .tvg import tvg
 from .whiten import whiten
+from .rangec import range_compress
 
 __all__ = ["pixel_points", "backproject", "backproject_image", "gated_term_count",
            "gated_term_count_rows", "vjp", "vjp_segment_bound", "reproject", "sharpness",
            "sharpness_cotangent", "sinc_kernel", "SINC_HALF",
-           "rel_l2", "phase_error_mrad", "drc", "tvg", "whiten"]
+           "rel_l2", "phase_error_mrad", "drc", "tvg", "whiten", "range_compress"]
