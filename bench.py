@@ -316,6 +316,30 @@ def whiten_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
     return {"samples": int(echo.numel()), "ms": ms}
 
 
+def rangec_leg(api, plan, echo: torch.Tensor, fs: float, steps: int) -> dict:
+    """Range compression and basebanding of the operational echo cube on a
+    copy, with a 5 ms, 20 kHz linear-FM replica (400 taps): padded rows,
+    forward FFT, matched-filter multiply, inverse FFT (16384 rows of 16875
+    points)."""
+    from synth.waveform import lfm_replica
+    x = echo.clone()
+    q = torch.as_tensor(lfm_replica(20e3, 5e-3, fs).astype(np.complex64), device="cuda")
+    api.sas_bp_range_compress(plan, 0, x, q)   # warm-up (also makes the FFT plans)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        api.sas_bp_range_compress(plan, 0, x, q)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    n = x.numel()
+    log(f"range compression: {ms:.3f} ms for {n} samples, {n / (ms * 1e-3) / 1e9:.1f} G samples/s")
+    del x
+    return {"samples": int(n), "taps": int(q.numel()), "ms": ms, "samples_per_s": n / (ms * 1e-3)}
+
+
 def volume_leg(api, steps: int, warmup: int) -> dict:
     """The 3D workload at full size: 256 pings x 64 receivers (32 across x 2
     along), 8192 samples, 512 x 512 x 128 voxels at 2 cm, no gate. The seabed
@@ -448,6 +472,7 @@ def main() -> int:
     ap.add_argument("--no-drc", action="store_true")
     ap.add_argument("--no-tvg", action="store_true")
     ap.add_argument("--no-whiten", action="store_true")
+    ap.add_argument("--no-rangec", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -459,7 +484,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
-        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = True
+        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = args.no_rangec = True
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo
@@ -559,6 +584,8 @@ def main() -> int:
         out["tvg"] = tvg_leg(api, plan, echo, 3)
     if not args.no_whiten:
         out["whiten"] = whiten_leg(api, plan, echo, 3)
+    if not args.no_rangec:
+        out["range_compression"] = rangec_leg(api, plan, echo, scn.fs, 3)
     if not args.no_sinc:
         out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_reprojection:

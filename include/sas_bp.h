@@ -195,6 +195,30 @@ int sas_bp_useful_updates(sas_bp_plan_t plan, const sas_bp_swath_io* io, int n_s
 int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, double* out_S,
                      void* grad_image, void* stream);
 
+/* Range compression and basebanding of swath `swath`'s echo cube, in place:
+ * the matched filter with the transmitted waveform q of Eq. 1 (Sec. II-A),
+ * which yields the compressed complex baseband echo the image reads. For each
+ * (ping, element) row x[k] of N_s samples at t_k = t0 + k / f_s (the swath's
+ * t0 and f_s):
+ *   b[k] = x[k] exp(-j 2 pi f_c t_k)          (mix != 0: x is the analytic
+ *                                              received signal; mix == 0: x is
+ *                                              already at baseband, b = x)
+ *   y[n] = sum_{m<M} b[n + m] conj(q[m]) / sum_m |q[m]|^2,  b[k] = 0 for k >= N_s,
+ * so a delayed copy of q compresses to a peak of one at its delay.
+ * echo: complex64 [P][E][N_s] with the swath's sizes, device memory, 8-byte
+ * aligned, overwritten with y. replica: complex64 q[0..n_taps) device memory,
+ * the waveform's baseband samples at f_s from the start of transmission,
+ * 1 <= n_taps <= N_s; a replica of zero energy gives zeros. Fast correlation
+ * through FP32 transforms (rocFFT through hipFFT) of a length L >= N_s +
+ * n_taps - 1 with only the factors 2, 3 and 5, in batches of at most 1024
+ * rows and 256 MiB; the carrier phase is reduced in FP64 and the replica
+ * energy summed in FP64. The plan keeps the transforms and an 8 B L (rows per
+ * batch + 1) + 8 N_s byte workspace of the last call's size (remade when the
+ * size changes), so calls on one plan must be ordered on one stream.
+ * Asynchronous on `stream`. */
+int sas_bp_range_compress(sas_bp_plan_t plan, int swath, void* echo, const void* replica, int32_t n_taps,
+                          int mix, void* stream);
+
 /* Spectral whitening of swath `swath`'s echo cube, in place (Eq. 9, Sec.
  * II-E): with X the DFT of each (ping, element) row of N_s samples, the power
  * estimate P^(f) = mean over rows of |X(f)|^2 and the power gain

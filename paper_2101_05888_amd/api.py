@@ -214,6 +214,21 @@ def sas_bp_whiten(plan: Plan, swath: int, echo: torch.Tensor, gamma: float, stre
                                 _stream(plan.device, stream)), "sas_bp_whiten")
 
 
+def sas_bp_range_compress(plan: Plan, swath: int, echo: torch.Tensor, replica: torch.Tensor, mix: bool = True,
+                          stream=None) -> None:
+    """Range compression (matched filter with the complex64 replica [M]) of a
+    complex64 echo cube [P, E, N_s], in place; with mix the rows are first
+    brought to baseband by exp(-j 2 pi f_c t)."""
+    d = plan.descs[swath]
+    _need(echo, "echo", torch.complex64, (d.n_ping, d.n_elem, d.n_sample), plan.device)
+    if replica.dim() != 1:
+        raise ValueError("replica must be one-dimensional")
+    _need(replica, "replica", torch.complex64, (replica.shape[0],), plan.device)
+    check(N.lib().sas_bp_range_compress(plan.handle, int(swath), echo.data_ptr(), replica.data_ptr(),
+                                        int(replica.shape[0]), 1 if mix else 0, _stream(plan.device, stream)),
+          "sas_bp_range_compress")
+
+
 def sas_bp_tvg(plan: Plan, swath: int, echo: torch.Tensor, alpha: float,
                gain_out: Optional[torch.Tensor] = None, stream=None) -> None:
     """Time-varying gain of a complex64 echo cube [P, E, N_s], in place;

@@ -61,6 +61,11 @@ size_t whiten_work_bytes(int Ns);
 int launch_whiten(void* fft_plan, void* echo, long long rows, int Ns, double gamma, void* work, hipStream_t st);
 int make_fft_plan(int Ns, long long rows, void** out);
 void destroy_fft_plan(void* p);
+int rc_transform_length(long long n);
+int rc_make_plans(int L, int B, void** batch, void** single);
+int launch_range_compress(void* batch_plan, void* single_plan, void* echo, long long rows, int Ns, int L, int B,
+                          const void* replica, int M, double fc, double t0, double fs, int apply_mix, void* buf,
+                          void* filt, void* mixtab, void* energy, hipStream_t st);
 hipError_t launch_adjoint_reduce(const Workspace& ws, int n_swaths, int max_p, hipStream_t st);
 hipError_t launch_count(const Workspace& ws, int s, int P, int E, int rows, unsigned long long* out, hipStream_t st);
 hipError_t launch_sharpness(const void* image, long long n, double* partials, double* out_S, void* grad,
@@ -142,6 +147,15 @@ struct sas_bp_plan_s {
   void* tvg_buf = nullptr;   // time-varying gain: medians and factors per sample time
   void* whiten_buf = nullptr;          // whitening: partial power sums, estimate, factors
   std::vector<void*> fft_plans;        // per swath, made on the first whitening call
+  struct {                             // range compression: transforms and buffers of the last call's size
+    int L = 0, B = 0;                  // transform length, rows per batch
+    void* batch = nullptr;             // FFT plans: B rows, one row
+    void* single = nullptr;
+    void* buf = nullptr;               // B x L complex rows
+    size_t buf_bytes = 0;
+    void* small = nullptr;             // filter (L), mix table (N_s), replica energy
+    size_t small_bytes = 0;
+  } rc;
   std::vector<SwathPlan> sw;
   Layout lay{};
   unsigned char* slab = nullptr;
@@ -484,6 +498,10 @@ void release(sas_bp_plan_s* p) {
   if (p->tvg_buf) (void)hipFree(p->tvg_buf);
   if (p->whiten_buf) (void)hipFree(p->whiten_buf);
   for (void* f : p->fft_plans) destroy_fft_plan(f);
+  destroy_fft_plan(p->rc.batch);
+  destroy_fft_plan(p->rc.single);
+  if (p->rc.buf) (void)hipFree(p->rc.buf);
+  if (p->rc.small) (void)hipFree(p->rc.small);
   if (p->slab) (void)hipFree(p->slab);
   (void)hipSetDevice(cur);
   delete p;
@@ -900,6 +918,63 @@ int sas_bp_whiten(sas_bp_plan_t p, int swath, void* echo, double gamma, void* st
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int rc = launch_whiten(p->fft_plans[swath], echo, rows, d.n_sample, gamma, p->whiten_buf, st);
   if (rc) return fail(SAS_BP_EDEVICE, "whitening failed (%s)", rc == 2 ? "FFT" : rc == 1 ? "FFT stream" : "kernel");
+  return SAS_BP_OK;
+}
+
+int sas_bp_range_compress(sas_bp_plan_t p, int swath, void* echo, const void* replica, int32_t n_taps, int mix,
+                          void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  if (swath < 0 || swath >= p->n_swaths) return fail(SAS_BP_EINVAL, "swath %d out of range", swath);
+  if (!echo || !replica) return fail(SAS_BP_EINVAL, "echo or replica is NULL");
+  if (((uintptr_t)echo & 7u) || ((uintptr_t)replica & 7u)) return fail(SAS_BP_EINVAL, "echo or replica misaligned");
+  const auto& d = p->sw[swath].d;
+  if (n_taps < 1 || n_taps > d.n_sample)
+    return fail(SAS_BP_EINVAL, "n_taps %d must lie in [1, %d] (the swath's samples)", (int)n_taps, d.n_sample);
+  const long long rows = (long long)d.n_ping * d.n_elem;
+  const int L = rc_transform_length((long long)d.n_sample + n_taps - 1);
+  if (L < 0) return fail(SAS_BP_EUNSUPPORTED, "transform length beyond 2^31");
+  // Rows per batch: a padded batch of at most 256 MiB and 1024 rows.
+  long long B = (256ll << 20) / (8ll * L);
+  B = std::max(1ll, std::min(B, std::min(1024ll, rows)));
+  DeviceGuard guard(p->device);
+  auto& rc = p->rc;
+  if (rc.L != L || rc.B != (int)B) {
+    destroy_fft_plan(rc.batch);
+    destroy_fft_plan(rc.single);
+    rc.batch = rc.single = nullptr;
+    rc.L = rc.B = 0;
+    if (rc_make_plans(L, (int)B, &rc.batch, &rc.single) != 0)
+      return fail(SAS_BP_EDEVICE, "FFT plans of length %d could not be made", L);
+    rc.L = L;
+    rc.B = (int)B;
+  }
+  const size_t buf_bytes = 8u * (size_t)B * L;
+  const size_t filt_off = 0, mix_off = align_up(8u * (size_t)L), eq_off = mix_off + align_up(8u * (size_t)d.n_sample);
+  const size_t small_bytes = eq_off + kAlign;
+  if (rc.buf_bytes < buf_bytes) {
+    if (rc.buf) (void)hipFree(rc.buf);
+    rc.buf_bytes = 0;
+    if (hipMalloc(&rc.buf, buf_bytes) != hipSuccess) {
+      rc.buf = nullptr;
+      return fail(SAS_BP_ENOMEM, "range compression workspace of %zu bytes could not be allocated", buf_bytes);
+    }
+    rc.buf_bytes = buf_bytes;
+  }
+  if (rc.small_bytes < small_bytes) {
+    if (rc.small) (void)hipFree(rc.small);
+    rc.small_bytes = 0;
+    if (hipMalloc(&rc.small, small_bytes) != hipSuccess) {
+      rc.small = nullptr;
+      return fail(SAS_BP_ENOMEM, "range compression filter of %zu bytes could not be allocated", small_bytes);
+    }
+    rc.small_bytes = small_bytes;
+  }
+  unsigned char* sm = static_cast<unsigned char*>(rc.small);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int r = launch_range_compress(rc.batch, rc.single, echo, rows, d.n_sample, L, (int)B, replica, n_taps, d.f_c,
+                                      d.t0, d.f_s, mix ? 1 : 0, rc.buf, sm + filt_off, sm + mix_off, sm + eq_off, st);
+  if (r) return fail(SAS_BP_EDEVICE, "range compression failed (%s)", r == 2 ? "FFT" : r == 1 ? "FFT stream" : "kernel");
   return SAS_BP_OK;
 }
 

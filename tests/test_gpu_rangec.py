@@ -1,0 +1,123 @@
+"""Range compression and basebanding through the C ABI against the FP64
+oracle on the same complex64 cubes.
+
+Bound: 1e-5 relative L2 per case. The transforms are FP32 of at most a few
+ten thousand points, whose error grows like eps log2 L (about 1e-6 here per
+transform pair); the carrier mix is rounded to FP32 after an FP64 phase
+reduction (about 1e-7).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import make_config
+from synth.waveform import lfm_replica, raw_echo
+from tests.helpers import desc_for
+
+pytestmark = pytest.mark.gpu
+
+T0 = 0.0123457   # f_c t0 is not a whole number of cycles, so the mix's time origin matters
+
+
+@pytest.fixture(scope="module")
+def api():
+    import paper_2101_05888_amd as m
+    return m
+
+
+def _scene(P, E, Ns):
+    return dataclasses.replace(make_config("c1", n_ping=P, n_elem=E, n_sample=Ns), t0=T0)
+
+
+def _run(api, scn, x, q, mix, plan=None):
+    plan = plan or api.sas_bp_plan([desc_for(api, scn)])
+    xt = torch.as_tensor(x.astype(np.complex64), device="cuda").contiguous()
+    qt = torch.as_tensor(q.astype(np.complex64), device="cuda").contiguous()
+    api.sas_bp_range_compress(plan, 0, xt, qt, mix=mix)
+    torch.cuda.synchronize()
+    return xt.cpu().numpy(), plan
+
+
+def _check(tag, got, x, q, scn, mix, bound=1e-5):
+    ref = oracle.range_compress(x.astype(np.complex64).astype(np.complex128),
+                                q.astype(np.complex64).astype(np.complex128), scn.fc, scn.fs, scn.t0, mix=mix)
+    r = oracle.rel_l2(got, ref)
+    print(f"[rangec {tag}] rel_l2={r:.2e}", flush=True)
+    assert r <= bound
+
+
+@pytest.mark.parametrize("mix", [True, False])
+def test_point_scatterers_match_oracle(api, mix):
+    P, E, Ns = 10, 3, 1000
+    scn = _scene(P, E, Ns)
+    q = lfm_replica(20e3, 2.5e-3, scn.fs)
+    x, d, a = raw_echo(P * E, Ns, q, scn.fc, scn.fs, scn.t0, n_targets=3, seed=11, noise=0.05)
+    x = x.reshape(P, E, Ns)
+    got, _ = _run(api, scn, x, q, mix)
+    _check(f"points mix={mix}", got, x, q, scn, mix)
+    if mix:
+        # a compressed target peaks at its delay with the baseband phase exp(-j 2 pi f_c tau)
+        row = got.reshape(-1, Ns)[0]
+        k = int(d[0, np.argmax(np.abs(a[0]))])
+        assert abs(int(np.argmax(np.abs(row))) - k) <= 1
+
+
+def test_two_batches_with_ragged_tail(api):
+    # 1300 rows: one full batch of 1024 rows, then 276 rows and 748 padding rows
+    P, E, Ns = 52, 25, 384
+    scn = _scene(P, E, Ns)
+    rng = np.random.default_rng(5)
+    x = (rng.normal(size=(P, E, Ns)) + 1j * rng.normal(size=(P, E, Ns))) / np.sqrt(2)
+    q = lfm_replica(20e3, 0.8e-3, scn.fs)
+    got, _ = _run(api, scn, x, q, True)
+    _check("1300 rows", got, x, q, scn, True)
+
+
+def test_tap_count_edges_and_plan_reuse(api):
+    P, E, Ns = 4, 2, 257
+    scn = _scene(P, E, Ns)
+    rng = np.random.default_rng(6)
+    x = (rng.normal(size=(P, E, Ns)) + 1j * rng.normal(size=(P, E, Ns))) / np.sqrt(2)
+    plan = None
+    for M in (1, Ns, 40, 1):          # one tap (a pure mix), the longest replica, then sizes again
+        q = (rng.normal(size=M) + 1j * rng.normal(size=M)) / np.sqrt(2)
+        got, plan = _run(api, scn, x, q, True, plan)
+        _check(f"taps={M}", got, x, q, scn, True)
+
+
+def test_zero_replica_gives_zeros_and_bad_taps_rejected(api):
+    P, E, Ns = 2, 2, 128
+    scn = _scene(P, E, Ns)
+    x = np.ones((P, E, Ns), dtype=np.complex64)
+    got, plan = _run(api, scn, x, np.zeros(16, dtype=np.complex64), True)
+    assert np.all(got == 0)
+    xt = torch.ones((P, E, Ns), dtype=torch.complex64, device="cuda")
+    for M in (Ns + 1,):
+        qt = torch.ones(M, dtype=torch.complex64, device="cuda")
+        with pytest.raises(RuntimeError):
+            api.sas_bp_range_compress(plan, 0, xt, qt)
+
+
+def test_operational_cube_sampled_rows(api):
+    """The operational cube (512 pings x 32 elements x 16384 samples) with a
+    5 ms, 20 kHz pulse, as the benchmark runs it; rows sampled for the oracle."""
+    scn = make_config("c2")
+    P, E, Ns = scn.n_ping, scn.n_elem, scn.n_sample
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1234)
+    x = torch.randn((P, E, Ns), dtype=torch.complex64, device="cuda", generator=g)
+    q = lfm_replica(20e3, 5e-3, scn.fs)
+    rows = [0, 1, 1023, 1024, 7777, P * E - 1]
+    before = x.reshape(-1, Ns)[rows].cpu().numpy()
+    plan = api.sas_bp_plan([desc_for(api, scn)])
+    api.sas_bp_range_compress(plan, 0, x, torch.as_tensor(q.astype(np.complex64), device="cuda"))
+    torch.cuda.synchronize()
+    after = x.reshape(-1, Ns)[rows].cpu().numpy()
+    ref = oracle.range_compress(before.astype(np.complex128), q.astype(np.complex64).astype(np.complex128),
+                                scn.fc, scn.fs, scn.t0, mix=True)
+    r = oracle.rel_l2(after, ref)
+    print(f"[rangec operational rows {rows}] rel_l2={r:.2e}", flush=True)
+    assert r <= 1e-5
