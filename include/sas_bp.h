@@ -209,13 +209,15 @@ int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, doubl
  * aligned, overwritten with y. replica: complex64 q[0..n_taps) device memory,
  * the waveform's baseband samples at f_s from the start of transmission,
  * 1 <= n_taps <= N_s; a replica of zero energy gives zeros. Fast correlation
- * through FP32 transforms (rocFFT through hipFFT) of a length L >= N_s +
- * n_taps - 1 with only the factors 2, 3 and 5, in batches of at most 1024
- * rows and 256 MiB; the carrier phase is reduced in FP64 and the replica
- * energy summed in FP64. The plan keeps the transforms and an 8 B L (rows per
- * batch + 1) + 8 N_s byte workspace of the last call's size (remade when the
- * size changes), so calls on one plan must be ordered on one stream.
- * Asynchronous on `stream`. */
+ * with FP32 transforms; the carrier phase is reduced in FP64 and the replica
+ * energy summed in FP64. n_taps <= 2048: one fused kernel (overlap-save in
+ * 4096-point segments, transforms in LDS, one workgroup per row); the plan
+ * keeps a 32 KiB + 8 N_s byte workspace. Longer replicas: rocFFT (through
+ * hipFFT) over rows zero-padded to a length L >= N_s + n_taps - 1 with only
+ * the factors 2, 3 and 5, in batches of at most 1024 rows and 256 MiB; the
+ * plan keeps those transforms and an 8 B L (rows per batch + 1) + 8 N_s byte
+ * workspace of the last call's size (remade when the size changes). Calls
+ * on one plan must be ordered on one stream. Asynchronous on `stream`. */
 int sas_bp_range_compress(sas_bp_plan_t plan, int swath, void* echo, const void* replica, int32_t n_taps,
                           int mix, void* stream);
 

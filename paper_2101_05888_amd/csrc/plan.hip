@@ -62,6 +62,10 @@ int launch_whiten(void* fft_plan, void* echo, long long rows, int Ns, double gam
 int make_fft_plan(int Ns, long long rows, void** out);
 void destroy_fft_plan(void* p);
 int rc_transform_length(long long n);
+int rc_fused_taps();
+int launch_range_compress_fused(void* echo, long long rows, int Ns, const void* replica, int M, double fc, double t0,
+                                double fs, int apply_mix, void* filt, void* tw, void* mixtab, void* energy,
+                                hipStream_t st);
 int rc_make_plans(int L, int B, void** batch, void** single);
 int launch_range_compress(void* batch_plan, void* single_plan, void* echo, long long rows, int Ns, int L, int B,
                           const void* replica, int M, double fc, double t0, double fs, int apply_mix, void* buf,
@@ -153,7 +157,7 @@ struct sas_bp_plan_s {
     void* single = nullptr;
     void* buf = nullptr;               // B x L complex rows
     size_t buf_bytes = 0;
-    void* small = nullptr;             // filter (L), mix table (N_s), replica energy
+    void* small = nullptr;             // filter (L), twiddles, mix table (N_s), replica energy
     size_t small_bytes = 0;
   } rc;
   std::vector<SwathPlan> sw;
@@ -932,35 +936,14 @@ int sas_bp_range_compress(sas_bp_plan_t p, int swath, void* echo, const void* re
   if (n_taps < 1 || n_taps > d.n_sample)
     return fail(SAS_BP_EINVAL, "n_taps %d must lie in [1, %d] (the swath's samples)", (int)n_taps, d.n_sample);
   const long long rows = (long long)d.n_ping * d.n_elem;
-  const int L = rc_transform_length((long long)d.n_sample + n_taps - 1);
+  const bool fused = n_taps <= rc_fused_taps();
+  const int L = fused ? 4096 : rc_transform_length((long long)d.n_sample + n_taps - 1);
   if (L < 0) return fail(SAS_BP_EUNSUPPORTED, "transform length beyond 2^31");
-  // Rows per batch: a padded batch of at most 256 MiB and 1024 rows.
-  long long B = (256ll << 20) / (8ll * L);
-  B = std::max(1ll, std::min(B, std::min(1024ll, rows)));
   DeviceGuard guard(p->device);
   auto& rc = p->rc;
-  if (rc.L != L || rc.B != (int)B) {
-    destroy_fft_plan(rc.batch);
-    destroy_fft_plan(rc.single);
-    rc.batch = rc.single = nullptr;
-    rc.L = rc.B = 0;
-    if (rc_make_plans(L, (int)B, &rc.batch, &rc.single) != 0)
-      return fail(SAS_BP_EDEVICE, "FFT plans of length %d could not be made", L);
-    rc.L = L;
-    rc.B = (int)B;
-  }
-  const size_t buf_bytes = 8u * (size_t)B * L;
-  const size_t filt_off = 0, mix_off = align_up(8u * (size_t)L), eq_off = mix_off + align_up(8u * (size_t)d.n_sample);
-  const size_t small_bytes = eq_off + kAlign;
-  if (rc.buf_bytes < buf_bytes) {
-    if (rc.buf) (void)hipFree(rc.buf);
-    rc.buf_bytes = 0;
-    if (hipMalloc(&rc.buf, buf_bytes) != hipSuccess) {
-      rc.buf = nullptr;
-      return fail(SAS_BP_ENOMEM, "range compression workspace of %zu bytes could not be allocated", buf_bytes);
-    }
-    rc.buf_bytes = buf_bytes;
-  }
+  // small buffer: filter (L), twiddle tables (128), mix table (N_s), replica energy
+  const size_t tw_off = align_up(8u * (size_t)L), mix_off = tw_off + align_up(8u * 128);
+  const size_t eq_off = mix_off + align_up(8u * (size_t)d.n_sample), small_bytes = eq_off + kAlign;
   if (rc.small_bytes < small_bytes) {
     if (rc.small) (void)hipFree(rc.small);
     rc.small_bytes = 0;
@@ -972,8 +955,37 @@ int sas_bp_range_compress(sas_bp_plan_t p, int swath, void* echo, const void* re
   }
   unsigned char* sm = static_cast<unsigned char*>(rc.small);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (fused) {
+    const int r = launch_range_compress_fused(echo, rows, d.n_sample, replica, n_taps, d.f_c, d.t0, d.f_s, mix ? 1 : 0,
+                                              sm, sm + tw_off, sm + mix_off, sm + eq_off, st);
+    if (r) return fail(SAS_BP_EDEVICE, "range compression kernel launch failed");
+    return SAS_BP_OK;
+  }
+  // Rows per batch: a padded batch of at most 256 MiB and 1024 rows.
+  long long B = (256ll << 20) / (8ll * L);
+  B = std::max(1ll, std::min(B, std::min(1024ll, rows)));
+  if (rc.L != L || rc.B != (int)B) {
+    destroy_fft_plan(rc.batch);
+    destroy_fft_plan(rc.single);
+    rc.batch = rc.single = nullptr;
+    rc.L = rc.B = 0;
+    if (rc_make_plans(L, (int)B, &rc.batch, &rc.single) != 0)
+      return fail(SAS_BP_EDEVICE, "FFT plans of length %d could not be made", L);
+    rc.L = L;
+    rc.B = (int)B;
+  }
+  const size_t buf_bytes = 8u * (size_t)B * L;
+  if (rc.buf_bytes < buf_bytes) {
+    if (rc.buf) (void)hipFree(rc.buf);
+    rc.buf_bytes = 0;
+    if (hipMalloc(&rc.buf, buf_bytes) != hipSuccess) {
+      rc.buf = nullptr;
+      return fail(SAS_BP_ENOMEM, "range compression workspace of %zu bytes could not be allocated", buf_bytes);
+    }
+    rc.buf_bytes = buf_bytes;
+  }
   const int r = launch_range_compress(rc.batch, rc.single, echo, rows, d.n_sample, L, (int)B, replica, n_taps, d.f_c,
-                                      d.t0, d.f_s, mix ? 1 : 0, rc.buf, sm + filt_off, sm + mix_off, sm + eq_off, st);
+                                      d.t0, d.f_s, mix ? 1 : 0, rc.buf, sm, sm + mix_off, sm + eq_off, st);
   if (r) return fail(SAS_BP_EDEVICE, "range compression failed (%s)", r == 2 ? "FFT" : r == 1 ? "FFT stream" : "kernel");
   return SAS_BP_OK;
 }

@@ -6,19 +6,31 @@
 // Per (ping, element) row x[k] at t_k = t0 + k / f_s:
 //     b[k] = x[k] exp(-j 2 pi f_c t_k)                  (when mixing)
 //     y[n] = sum_{m<M} b[n + m] conj(q[m]) / sum_m |q[m]|^2,   b = 0 past N_s.
-// Fast correlation: rows are zero-padded to a transform length L >= N_s + M - 1
-// (so the circular correlation does not wrap), transformed in batches of B
-// rows (batched complex FFT, rocFFT through hipFFT), multiplied by
-// H = conj(Q) / (L E_q) and transformed back; the first N_s samples are
-// written over the input. The mix table and the replica's spectrum are made
-// once per call: the carrier phase in FP64 (cycles reduced to [0, 1)), the
-// replica energy E_q summed in FP64 in a fixed order. A replica of zero
-// energy gives an all-zero output.
+// Two fast-correlation forms, both with H = conj(Q) / (L E_q), Q the
+// replica's L-point transform, E_q its energy:
+//  * fused (M <= kRcFusedTaps): overlap-save with L = 4096. One workgroup per
+//    row walks its segments in order; segment s reads b[sU, sU + 4096)
+//    (U = 4097 - M useful outputs), transforms it in LDS, multiplies by H,
+//    transforms back and writes y[sU, sU + U) over the input. Later segments
+//    only read beyond what earlier ones wrote, so the row is done in place
+//    with one HBM read (plus the (M - 1) / U overlap) and one write.
+//  * batched (longer replicas): rows zero-padded to L >= N_s + M - 1 (so the
+//    circular correlation does not wrap), transformed in batches of B rows
+//    (rocFFT through hipFFT), multiplied by H, transformed back; the first
+//    N_s samples are written over the input.
+// The mix table and H are made once per call: the carrier phase in FP64
+// (cycles reduced to [0, 1)), the replica energy summed in FP64 in a fixed
+// order. A replica of zero energy gives an all-zero output.
 #include <hipfft/hipfft.h>
 
 #include "tdbp_dev.h"
+#include "tdbp_fft.h"
 
 namespace sasbp {
+
+constexpr int kRcFusedTaps = 2048;   // longest replica of the fused form (U >= 2049 of 4096)
+
+int rc_fused_taps() { return kRcFusedTaps; }
 
 __global__ __launch_bounds__(kThreads) void rc_mix_kernel(float2* mix, int Ns, double fc, double t0, double fs,
                                                           int apply) {
@@ -98,6 +110,92 @@ __global__ __launch_bounds__(kThreads) void rc_store_kernel(const float2* buf, l
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < Ns; k += gridDim.x * blockDim.x) dst[k] = src[k];
 }
 
+// Twiddle tables (W^j and W^(64 j), j < 64, W = exp(-2 pi i / 4096), from
+// FP64), the replica energy and H = conj(Q) / (4096 E_q) for the fused form,
+// in natural bin order. One workgroup.
+__global__ __launch_bounds__(kFftThreads) void rc_spectrum_kernel(const float2* q, int M, float2* H, float2* tw,
+                                                                  double* energy) {
+  __shared__ float2 A[kFftLds];
+  __shared__ float2 T[kFftTw];
+  __shared__ double red[kFftThreads];
+  const int t = threadIdx.x;
+  if (t < kFftTw) {
+    const int k = t < 64 ? t : 64 * (t - 64);
+    double sn, cs;
+    sincospi(-2.0 * (double)k / (double)kFftN, &sn, &cs);
+    T[t] = make_float2((float)cs, (float)sn);
+    tw[t] = T[t];
+  }
+  double e = 0.0;
+  for (int m = t; m < M; m += kFftThreads) e += (double)q[m].x * q[m].x + (double)q[m].y * q[m].y;
+  red[t] = e;
+  float2 v[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) {
+    const int m = n1 * kFftThreads + t;
+    v[n1] = m < M ? q[m] : make_float2(0.0f, 0.0f);
+  }
+  __syncthreads();
+  for (int h = kFftThreads / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  const double eq = red[0];
+  fft_pass1_compute<false>(v, t, T);
+  fft_pass1_store(v, t, A);
+  __syncthreads();
+  fft_pass2<false>(t, T, A);
+  __syncthreads();
+  fft_pass3<false>(v, t, A);
+  const float g = eq > 0.0 ? (float)(1.0 / ((double)kFftN * eq)) : 0.0f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) H[t + kFftThreads * j] = make_float2(v[j].x * g, -v[j].y * g);
+  if (t == 0) *energy = eq;
+}
+
+// Fused overlap-save correlation, in place; one workgroup per row (grid-stride).
+__global__ __launch_bounds__(kFftThreads) void rc_fused_kernel(float2* x, long long rows, int Ns, int U, int nseg,
+                                                               const float2* mix, const float2* H, const float2* tw) {
+  __shared__ float2 A[kFftLds];
+  __shared__ float2 T[kFftTw];
+  const int t = threadIdx.x;
+  if (t < kFftTw) T[t] = tw[t];
+  __syncthreads();
+  for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+    float2* xr = x + (size_t)row * Ns;
+    for (int s = 0; s < nseg; ++s) {
+      const int i0 = s * U;
+      float2 v[16];
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) {
+        const int i = i0 + n1 * kFftThreads + t;
+        v[n1] = i < Ns ? fft_cmul(xr[i], mix[i]) : make_float2(0.0f, 0.0f);
+      }
+      fft_pass1_compute<false>(v, t, T);
+      __syncthreads();   // the previous segment's last LDS reads are done
+      fft_pass1_store(v, t, A);
+      __syncthreads();
+      fft_pass2<false>(t, T, A);
+      __syncthreads();
+      fft_pass3<false>(v, t, A);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = fft_cmul(v[j], H[t + kFftThreads * j]);
+      fft_pass1_compute<true>(v, t, T);
+      __syncthreads();
+      fft_pass1_store(v, t, A);
+      __syncthreads();
+      fft_pass2<true>(t, T, A);
+      __syncthreads();
+      fft_pass3<true>(v, t, A);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int n = t + kFftThreads * j;
+        if (n < U && i0 + n < Ns) xr[i0 + n] = v[j];
+      }
+    }
+  }
+}
+
 // Smallest L >= n whose only prime factors are 2, 3 and 5 (sizes rocFFT
 // transforms without a Bluestein stage).
 int rc_transform_length(long long n) {
@@ -128,6 +226,23 @@ static dim3 row_grid(int n, int rows) {
   int bx = (n + kThreads - 1) / kThreads;
   if (bx > 16) bx = 16;   // a few row segments per workgroup keep the grid modest
   return dim3((unsigned)bx, (unsigned)rows);
+}
+
+int launch_range_compress_fused(void* echo, long long rows, int Ns, const void* replica, int M, double fc, double t0,
+                                double fs, int apply_mix, void* filt, void* tw, void* mixtab, void* energy,
+                                hipStream_t st) {
+  const int U = kFftN + 1 - M;
+  const int nseg = (Ns + U - 1) / U;
+  hipLaunchKernelGGL(rc_mix_kernel, dim3((Ns + kThreads - 1) / kThreads), dim3(kThreads), 0, st,
+                     reinterpret_cast<float2*>(mixtab), Ns, fc, t0, fs, apply_mix);
+  hipLaunchKernelGGL(rc_spectrum_kernel, dim3(1), dim3(kFftThreads), 0, st, (const float2*)replica, M,
+                     reinterpret_cast<float2*>(filt), reinterpret_cast<float2*>(tw),
+                     reinterpret_cast<double*>(energy));
+  const long long grid = rows < (1ll << 20) ? rows : (1ll << 20);
+  hipLaunchKernelGGL(rc_fused_kernel, dim3((unsigned)grid), dim3(kFftThreads), 0, st,
+                     reinterpret_cast<float2*>(echo), rows, Ns, U, nseg, (const float2*)mixtab, (const float2*)filt,
+                     (const float2*)tw);
+  return hipGetLastError() == hipSuccess ? 0 : 3;
 }
 
 // work: B L float2 rows, then L float2 filter, N_s float2 mix table, one double.

@@ -66,14 +66,40 @@ def test_point_scatterers_match_oracle(api, mix):
 
 
 def test_two_batches_with_ragged_tail(api):
-    # 1300 rows: one full batch of 1024 rows, then 276 rows and 748 padding rows
-    P, E, Ns = 52, 25, 384
+    # 2100 taps take the batched transforms; 1300 rows: one full batch of
+    # 1024 rows, then 276 rows and 748 padding rows
+    P, E, Ns = 52, 25, 2200
     scn = _scene(P, E, Ns)
     rng = np.random.default_rng(5)
     x = (rng.normal(size=(P, E, Ns)) + 1j * rng.normal(size=(P, E, Ns))) / np.sqrt(2)
-    q = lfm_replica(20e3, 0.8e-3, scn.fs)
+    q = lfm_replica(20e3, 2100 / scn.fs, scn.fs)
     got, _ = _run(api, scn, x, q, True)
-    _check("1300 rows", got, x, q, scn, True)
+    rows = [0, 1, 511, 1023, 1024, 1025, 1298, 1299]     # both batches and the tail, for the oracle
+    g, xs = got.reshape(-1, Ns)[rows], x.reshape(-1, Ns)[rows]
+    _check("1300 rows", g, xs, q, scn, True)
+
+
+def test_fused_segments_with_ragged_tail(api):
+    # 1500 taps: 2597 outputs per 4096-point segment, 4 segments, the last one partial
+    P, E, Ns = 3, 2, 9000
+    scn = _scene(P, E, Ns)
+    q = lfm_replica(20e3, 1500 / scn.fs, scn.fs)
+    x, _, _ = raw_echo(P * E, Ns, q, scn.fc, scn.fs, scn.t0, n_targets=6, seed=12, noise=0.05)
+    got, _ = _run(api, scn, x.reshape(P, E, Ns), q, True)
+    _check("fused 4 segments", got, x.reshape(P, E, Ns), q, scn, True)
+
+
+def test_long_replica_uses_batched_transforms(api):
+    # 2500 taps (beyond the fused form): rows padded to a 2-3-5 length >= 5499
+    P, E, Ns = 2, 2, 3000
+    scn = _scene(P, E, Ns)
+    q = lfm_replica(20e3, 2500 / scn.fs, scn.fs)
+    x, _, _ = raw_echo(P * E, Ns, q, scn.fc, scn.fs, scn.t0, n_targets=2, seed=13, noise=0.05)
+    got, plan = _run(api, scn, x.reshape(P, E, Ns), q, True)
+    _check("batched 2500 taps", got, x.reshape(P, E, Ns), q, scn, True)
+    q2 = lfm_replica(20e3, 300 / scn.fs, scn.fs)      # then the fused form on the same plan
+    got, _ = _run(api, scn, x.reshape(P, E, Ns), q2, False, plan)
+    _check("fused after batched", got, x.reshape(P, E, Ns), q2, scn, False)
 
 
 def test_tap_count_edges_and_plan_reuse(api):
