@@ -477,6 +477,8 @@ def main() -> int:
     ap.add_argument("--no-whiten", action="store_true")
     ap.add_argument("--no-rangec", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
+    ap.add_argument("--profile-leg", choices=["rangec", "tvg", "drc", "whiten"], default=None,
+                    help="with --profile, also run this one leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -488,6 +490,8 @@ def main() -> int:
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
         args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = args.no_rangec = True
+        if args.profile_leg:
+            setattr(args, "no_" + args.profile_leg, False)
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo

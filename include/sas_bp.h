@@ -212,7 +212,7 @@ int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, doubl
  * with FP32 transforms; the carrier phase is reduced in FP64 and the replica
  * energy summed in FP64. n_taps <= 2048: one fused kernel (overlap-save in
  * 4096-point segments, transforms in LDS, one workgroup per row); the plan
- * keeps a 32 KiB + 8 N_s byte workspace. Longer replicas: rocFFT (through
+ * keeps a 64 KiB + 8 N_s byte workspace. Longer replicas: rocFFT (through
  * hipFFT) over rows zero-padded to a length L >= N_s + n_taps - 1 with only
  * the factors 2, 3 and 5, in batches of at most 1024 rows and 256 MiB; the
  * plan keeps those transforms and an 8 B L (rows per batch + 1) + 8 N_s byte

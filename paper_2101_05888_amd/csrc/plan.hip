@@ -941,8 +941,8 @@ int sas_bp_range_compress(sas_bp_plan_t p, int swath, void* echo, const void* re
   if (L < 0) return fail(SAS_BP_EUNSUPPORTED, "transform length beyond 2^31");
   DeviceGuard guard(p->device);
   auto& rc = p->rc;
-  // small buffer: filter (L), twiddle tables (128), mix table (N_s), replica energy
-  const size_t tw_off = align_up(8u * (size_t)L), mix_off = tw_off + align_up(8u * 128);
+  // small buffer: filter (L), twiddle table (4080), mix table (N_s), replica energy
+  const size_t tw_off = align_up(8u * (size_t)L), mix_off = tw_off + align_up(8u * 4080);
   const size_t eq_off = mix_off + align_up(8u * (size_t)d.n_sample), small_bytes = eq_off + kAlign;
   if (rc.small_bytes < small_bytes) {
     if (rc.small) (void)hipFree(rc.small);

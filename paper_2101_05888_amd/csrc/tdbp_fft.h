@@ -13,8 +13,9 @@
 // LDS holds the 4096 values at 290 a + 17 b + c for the digit triple
 // (a, b, c) of 256 a + 16 b + c (17 b + c < 290, and 290 = 2 mod 32): the
 // 64 lanes of passes 2 and 3 then touch each 8-byte bank pair exactly twice.
-// Twiddles come from two 64-entry tables, W^k = T[64 + (k >> 6)] T[k & 63]
-// with W = exp(-2 pi i / 4096).
+// Twiddles come from one table of kFftTw entries, rounded from FP64: pass 1's
+// W^(t k1) at (k1 - 1) 256 + t and pass 2's W^(16 c j1) at 3840 + (j1 - 1) 16
+// + c (k1, j1 = 1..15), W = exp(-2 pi i / 4096); the inverse conjugates them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,7 +25,8 @@ namespace sasbp {
 constexpr int kFftN = 4096;
 constexpr int kFftThreads = 256;
 constexpr int kFftLds = 15 * 290 + 15 * 17 + 15 + 1;
-constexpr int kFftTw = 128;
+constexpr int kFftTw = 15 * 256 + 15 * 16;
+constexpr int kFftTw2 = 15 * 256;   // start of pass 2's twiddles
 
 __host__ __device__ __forceinline__ int fft_lds(int a, int b, int c) { return a * 290 + b * 17 + c; }
 
@@ -35,11 +37,16 @@ __host__ __device__ __forceinline__ float2 fft_cmul(float2 a, float2 b) {
 __host__ __device__ __forceinline__ float2 fft_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __host__ __device__ __forceinline__ float2 fft_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
-// W_4096^k (forward) or its conjugate (inverse), 0 <= k < 4096
+// Table entry i (forward) or its conjugate (inverse)
 template <bool INV>
-__host__ __device__ __forceinline__ float2 fft_twiddle(const float2* T, int k) {
-  const float2 w = fft_cmul(T[64 + (k >> 6)], T[k & 63]);
+__host__ __device__ __forceinline__ float2 fft_tw(const float2* T, int i) {
+  const float2 w = T[i];
   return INV ? make_float2(w.x, -w.y) : w;
+}
+
+// The table's entry i in FP64: the exponent k of W^k it holds
+__host__ __device__ __forceinline__ int fft_tw_exponent(int i) {
+  return i < kFftTw2 ? (i / 256 + 1) * (i % 256) : 16 * ((i - kFftTw2) / 16 + 1) * ((i - kFftTw2) % 16);
 }
 
 // Length-4 transform in place: forward uses W_4 = -i, inverse +i.
@@ -89,7 +96,7 @@ template <bool INV>
 __host__ __device__ __forceinline__ void fft_pass1_compute(float2 (&v)[16], int t, const float2* T) {
   fft_dft16<INV>(v);
 #pragma unroll
-  for (int k1 = 1; k1 < 16; ++k1) v[k1] = fft_cmul(v[k1], fft_twiddle<INV>(T, t * k1));
+  for (int k1 = 1; k1 < 16; ++k1) v[k1] = fft_cmul(v[k1], fft_tw<INV>(T, (k1 - 1) * 256 + t));
 }
 
 __host__ __device__ __forceinline__ void fft_pass1_store(const float2 (&v)[16], int t, float2* A) {
@@ -106,7 +113,7 @@ __host__ __device__ __forceinline__ void fft_pass2(int t, const float2* T, float
   for (int m1 = 0; m1 < 16; ++m1) v[m1] = A[fft_lds(a, m1, c)];
   fft_dft16<INV>(v);
 #pragma unroll
-  for (int j1 = 1; j1 < 16; ++j1) v[j1] = fft_cmul(v[j1], fft_twiddle<INV>(T, 16 * c * j1));
+  for (int j1 = 1; j1 < 16; ++j1) v[j1] = fft_cmul(v[j1], fft_tw<INV>(T, kFftTw2 + (j1 - 1) * 16 + c));
 #pragma unroll
   for (int j1 = 0; j1 < 16; ++j1) A[fft_lds(a, j1, c)] = v[j1];
 }

@@ -110,21 +110,20 @@ __global__ __launch_bounds__(kThreads) void rc_store_kernel(const float2* buf, l
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < Ns; k += gridDim.x * blockDim.x) dst[k] = src[k];
 }
 
-// Twiddle tables (W^j and W^(64 j), j < 64, W = exp(-2 pi i / 4096), from
-// FP64), the replica energy and H = conj(Q) / (4096 E_q) for the fused form,
-// in natural bin order. One workgroup.
+// The transform's twiddle table (from FP64), the replica energy and
+// H = conj(Q) / (4096 E_q) for the fused form, in natural bin order. One
+// workgroup.
 __global__ __launch_bounds__(kFftThreads) void rc_spectrum_kernel(const float2* q, int M, float2* H, float2* tw,
                                                                   double* energy) {
   __shared__ float2 A[kFftLds];
   __shared__ float2 T[kFftTw];
   __shared__ double red[kFftThreads];
   const int t = threadIdx.x;
-  if (t < kFftTw) {
-    const int k = t < 64 ? t : 64 * (t - 64);
+  for (int i = t; i < kFftTw; i += kFftThreads) {
     double sn, cs;
-    sincospi(-2.0 * (double)k / (double)kFftN, &sn, &cs);
-    T[t] = make_float2((float)cs, (float)sn);
-    tw[t] = T[t];
+    sincospi(-2.0 * (double)fft_tw_exponent(i) / (double)kFftN, &sn, &cs);
+    T[i] = make_float2((float)cs, (float)sn);
+    tw[i] = T[i];
   }
   double e = 0.0;
   for (int m = t; m < M; m += kFftThreads) e += (double)q[m].x * q[m].x + (double)q[m].y * q[m].y;
@@ -159,7 +158,7 @@ __global__ __launch_bounds__(kFftThreads) void rc_fused_kernel(float2* x, long l
   __shared__ float2 A[kFftLds];
   __shared__ float2 T[kFftTw];
   const int t = threadIdx.x;
-  if (t < kFftTw) T[t] = tw[t];
+  for (int i = t; i < kFftTw; i += kFftThreads) T[i] = tw[i];
   __syncthreads();
   for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
     float2* xr = x + (size_t)row * Ns;
