@@ -16,7 +16,7 @@ that produces them (the matched filter with Eq. 1's waveform q). It shares no co
 """
 from .tdbp import (pixel_points, backproject, backproject_image, gated_term_count,
                    gated_term_count_rows, vjp, vjp_segment_bound, reproject, sharpness,
-                   sharpness_cotangent, sinc_kernel, SINC_HALF)
+                   sharpness_cotangent, sinc_kernel, SINC_HALF, motion_delay)
 from .metrics import rel_l2, phase_error_mrad
 from .drc import drc
 from .tvg import tvg
@@ -25,5 +25,5 @@ from .rangec import range_compress
 
 __all__ = ["pixel_points", "backproject", "backproject_image", "gated_term_count",
            "gated_term_count_rows", "vjp", "vjp_segment_bound", "reproject", "sharpness",
-           "sharpness_cotangent", "sinc_kernel", "SINC_HALF",
+           "sharpness_cotangent", "sinc_kernel", "SINC_HALF", "motion_delay",
            "rel_l2", "phase_error_mrad", "drc", "tvg", "whiten", "range_compress"]

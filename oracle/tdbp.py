@@ -19,6 +19,17 @@ zero extension (a Hann-windowed sinc over 8 samples is available as a
 variant of the image); t_k = t0 + k / f_s; echoes at complex baseband so the carrier
 phase is re-applied; no amplitude weighting; positions fixed per ping.
 
+Continuous motion (variant of the image; the receiver location x_RX(t) of
+Eq. 1, with the transmitter stationary while it transmits): with a per-ping
+velocity v_i the receivers move during reception, R_ie(t) = R_ie + v_i t
+(t after transmit), and tau solves c tau = d_T + |p - R_ie - v_i tau|. With
+a = p - R_ie this is the quadratic
+
+    (c^2 - |v|^2) tau^2 - 2 (c d_T - a.v) tau + (d_T^2 - |a|^2) = 0,
+
+whose larger root is the one with c tau - d_T >= 0 (``motion_delay``). The
+beam gate keeps the ping-time positions.
+
 Gradient (vector-Jacobian product) for a cotangent Gbar = dJ/dRe I + j dJ/dIm I:
 
     dJ/dtheta = sum_p Re( conj(Gbar(p)) * sum_ie g * D_ie(p) * dtau_ie/dtheta )
@@ -91,7 +102,18 @@ def _sinc_interp(row: np.ndarray, u: np.ndarray, half: int = SINC_HALF) -> np.nd
     return out
 
 
-def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear"):
+def motion_delay(d_T, a, v, c):
+    """Two-way delay with the receiver moving at v during reception: the root
+    of c tau = d_T + |a - v tau| (a = p - R at transmit; a [N, 3], v [3])."""
+    av = a @ v
+    vv = float(v @ v)
+    aa = np.sum(a * a, axis=1)
+    A = c * c - vv
+    Bh = c * d_T - av
+    return (Bh + np.sqrt(Bh * Bh - A * (d_T * d_T - aa))) / A
+
+
+def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear", vel=None):
     P, E = rx.shape[0], rx.shape[1]
     acc = np.zeros(pts.shape[0], dtype=np.complex128)
     count = 0
@@ -102,7 +124,7 @@ def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear"):
         for e in range(E):
             R = rx[i, e]
             dR = np.sqrt(((pts - R) ** 2).sum(axis=1))
-            tau = (dT + dR) / c
+            tau = (dT + dR) / c if vel is None else motion_delay(dT, pts - R, vel[i], c)
             u = (tau - t0) * fs
             if interp == "sinc":
                 L = _sinc_interp(echo[i, e], u)
@@ -129,35 +151,37 @@ def _worker(args):
     lo, hi = args
     s = _SHARED
     return _bp_chunk(s["echo"], s["tx"], s["rx"], s["c"], s["fc"], s["fs"], s["t0"],
-                     s["pts"][lo:hi], s["gate"], s["interp"])
+                     s["pts"][lo:hi], s["gate"], s["interp"], s["vel"])
 
 
 def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
-                workers=1, chunk=4096, return_count=False, interp="linear"):
+                workers=1, chunk=4096, return_count=False, interp="linear", rx_vel=None):
     """Backprojected complex values at arbitrary points [N,3] (float64 in, complex128 out).
 
     echo: complex [P,E,N_s]; tx: [P,3]; rx: [P,E,3]; gate_half_angle in radians
     (0 = no gate). ``workers`` > 1 splits the points over forked processes.
     ``interp`` = "linear" (the definition above) or "sinc": the interpolation
     variant L = sum over the 2 SINC_HALF samples m around u of E~[m] h(u - m),
-    h the Hann-windowed sinc of ``sinc_kernel``.
+    h the Hann-windowed sinc of ``sinc_kernel``. ``rx_vel`` ([P, 3], m/s)
+    selects continuous receiver motion (``motion_delay``).
     """
     echo = np.ascontiguousarray(np.asarray(echo).astype(np.complex128, copy=False))
     tx = np.asarray(tx, dtype=np.float64)
     rx = np.asarray(rx, dtype=np.float64)
     pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    vel = None if rx_vel is None else np.asarray(rx_vel, dtype=np.float64).reshape(-1, 3)
     N = pts.shape[0]
     spans = [(lo, min(N, lo + chunk)) for lo in range(0, N, chunk)]
     out = np.zeros(N, dtype=np.complex128)
     total = 0
     if workers <= 1 or len(spans) <= 1:
         for lo, hi in spans:
-            v, cnt = _bp_chunk(echo, tx, rx, float(c), fc, fs, t0, pts[lo:hi], gate_half_angle, interp)
+            v, cnt = _bp_chunk(echo, tx, rx, float(c), fc, fs, t0, pts[lo:hi], gate_half_angle, interp, vel)
             out[lo:hi] = v
             total += cnt
     else:
         _SHARED.update(echo=echo, tx=tx, rx=rx, c=float(c), fc=fc, fs=fs, t0=t0, pts=pts,
-                       gate=gate_half_angle, interp=interp)
+                       gate=gate_half_angle, interp=interp, vel=vel)
         ctx = mp.get_context("fork")
         with ctx.Pool(workers) as pool:
             res = pool.map(_worker, spans, chunksize=1)
@@ -169,11 +193,11 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
 
 
 def backproject_image(echo, tx, rx, c, fc, fs, t0, origin, spacing, n, gate_half_angle=0.0,
-                      workers=1, return_count=False, interp="linear"):
+                      workers=1, return_count=False, interp="linear", rx_vel=None):
     """Full image [nz, ny, nx] complex128 on the grid origin + index * spacing."""
     pts = pixel_points(origin, spacing, n)
     r = backproject(echo, tx, rx, c, fc, fs, t0, pts, gate_half_angle, workers=workers,
-                    return_count=return_count, interp=interp)
+                    return_count=return_count, interp=interp, rx_vel=rx_vel)
     nx, ny, nz = (int(v) for v in n)
     if return_count:
         return r[0].reshape(nz, ny, nx), r[1]

@@ -10,6 +10,11 @@ u_s = (tau_s - t0) * f_s its position in samples. The pulse shape
 h(d) = sinc(d * B / f_s) * taper(d) is the compressed pulse of bandwidth B,
 truncated to |d| < H samples by a flat-top (Tukey) taper that equals 1 for
 |d| <= H/2, so the two samples nearest the true delay carry the exact sinc.
+With ``rx_vel`` (per-ping velocity [P, 3]) the receivers move during
+reception, R_ie(t) = R_ie + v_i t (t after transmit; the transmitter is
+stationary while it transmits), and tau_s solves
+c tau = |x_s - T_i| + |x_s - R_ie - v_i tau|, found by fixed-point iteration
+(contraction |v| / c). The gate stays that of the ping-time positions.
 There is no spherical spreading: time-varying gain is taken as already applied
 (Eq. 10, Sec. II-E). The gate g is the +-theta transmit AND receive cone about
 the broadside plane, the same one the imager applies; g = 1 when no gate.
@@ -46,7 +51,8 @@ def pulse(d, bandwidth: float, fs: float, half: int):
 
 def synthesize_echo(scn: Scenario, device="cpu", dtype=torch.complex128,
                     tx: np.ndarray | None = None, rx: np.ndarray | None = None,
-                    max_chunk: int = 1 << 22, noise: bool = True, noise_on_device: bool = False) -> torch.Tensor:
+                    max_chunk: int = 1 << 22, noise: bool = True, noise_on_device: bool = False,
+                    rx_vel: np.ndarray | None = None) -> torch.Tensor:
     """Echo cube [P, E, N_s] for the scenario, optionally with its seeded noise.
 
     ``tx``/``rx`` default to the positions the scene was recorded with
@@ -64,6 +70,7 @@ def synthesize_echo(scn: Scenario, device="cpu", dtype=torch.complex128,
     amp = torch.as_tensor(scn.scat_amp, dtype=torch.complex128, device=dev)
     txd = torch.as_tensor(tx, dtype=f64, device=dev)
     rxd = torch.as_tensor(rx, dtype=f64, device=dev)
+    veld = None if rx_vel is None else torch.as_tensor(rx_vel, dtype=f64, device=dev)
     H = int(scn.taper_half)
     taps = torch.arange(-H + 1, H + 1, device=dev, dtype=f64)
     sin_g = math.sin(scn.gate_half_angle) if scn.gate_half_angle > 0 else None
@@ -77,6 +84,12 @@ def synthesize_echo(scn: Scenario, device="cpu", dtype=torch.complex128,
         dT = torch.linalg.norm(pos[None, :, :] - T[:, None, :], dim=-1)              # [p,S]
         dR = torch.linalg.norm(pos[None, :, None, :] - R[:, None, :, :], dim=-1)     # [p,S,E]
         tau = (dT[:, :, None] + dR) / scn.c                                           # [p,S,E]
+        if veld is not None:
+            V = veld[i0:i1]                                                           # [p,3]
+            rel = pos[None, :, None, :] - R[:, None, :, :]                            # [p,S,E,3]
+            for _ in range(8):
+                moved = rel - V[:, None, None, :] * tau[..., None]
+                tau = (dT[:, :, None] + torch.linalg.norm(moved, dim=-1)) / scn.c
         if sin_g is not None:
             gT = (pos[None, :, 0] - T[:, None, 0]).abs() <= sin_g * dT               # [p,S]
             gR = (pos[None, :, None, 0] - R[:, None, :, 0]).abs() <= sin_g * dR       # [p,S,E]

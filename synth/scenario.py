@@ -339,6 +339,18 @@ def make_config(name: str, **overrides) -> Scenario:
     raise ValueError(f"unknown workload {name!r}")
 
 
+def receiver_velocity(scn: Scenario, pri: float | None = None) -> np.ndarray:
+    """Per-ping platform velocity [P, 3] (m/s) for continuous-motion tests:
+    central differences of the navigated transmitter track over the ping
+    repetition interval (default one record, N_s / f_s), one-sided at the ends.
+    The receivers share it (a rigid array)."""
+    pri = scn.n_sample / scn.fs if pri is None else pri
+    t = np.asarray(scn.tx, dtype=np.float64)
+    if t.shape[0] < 2:
+        return np.zeros_like(t)
+    return np.gradient(t, axis=0) / pri
+
+
 def subset_indices(scn: Scenario, count: int) -> np.ndarray:
     """Seeded pixel subset (flat image indices, sorted) drawn without replacement."""
     rng = scn.streams()["subset"]
