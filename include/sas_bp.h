@@ -15,8 +15,13 @@
  *         half-angle about the broadside plane; g = 1 when a = 0)
  *   I(p) = sum_i sum_e g * L * exp(+j 2 pi f_c tau)
  *
- * Positions are fixed during a ping (stop-and-hop). Echoes are range
- * compressed and at complex baseband, so the carrier phase is re-applied.
+ * Positions are fixed during a ping (stop-and-hop) unless a swath selects
+ * continuous motion (desc.motion = 1, the receiver location x_RX(t) of Eq. 1
+ * with the transmitter stationary while it transmits): the receivers then move
+ * at the ping's velocity v_i during reception, R_ie(t) = R_ie + v_i t, and tau
+ * is the root of c tau = d_T + |p - R_ie - v_i tau| (the gate keeps the
+ * ping-time positions). Echoes are range compressed and at complex baseband,
+ * so the carrier phase is re-applied.
  * Axes are north-east-down (Sec. II-B): x along-track, y across, z down.
  * A pixel centre is origin + index * spacing on each axis.
  *
@@ -51,7 +56,7 @@
 extern "C" {
 #endif
 
-#define SAS_BP_ABI_VERSION 3
+#define SAS_BP_ABI_VERSION 4
 
 typedef struct sas_bp_plan_s* sas_bp_plan_t;
 
@@ -101,6 +106,12 @@ typedef struct {
     double gate_half_angle; /* radians in [0, pi/2); 0 disables the beam gate */
     double c_min;           /* smallest sound speed the plan must accept, m/s; 0 selects 1400 */
     int32_t interp;         /* enum sas_bp_interp; all swaths of a plan share it */
+    int32_t motion;         /* 0: stop-and-hop; 1: receivers move at io.rx_vel during
+                               reception (linear interpolation only; image only: the
+                               adjoint and reprojection refuse it). All swaths of a
+                               plan share it. A velocity that is not finite, |v| >= c/2,
+                               or one that moves a delay by more than one sample across
+                               a tile, is reported like bad navigation (SAS_BP_ENAV). */
 } sas_bp_swath_desc;
 
 /* Plan options; a NULL options pointer selects every default. */
@@ -125,6 +136,8 @@ typedef struct {
     const double* rx_pos;    /* f64[P][E][3] receiver positions                             */
     const double* c;         /* f64[1] sound speed, read on the device at every call        */
     void* image;             /* complex64 [nz][ny][nx] output (x fastest), overwritten      */
+    const double* rx_vel;    /* f64[P][3] receiver velocity during reception of each ping,
+                                m/s; required when desc.motion = 1, ignored otherwise       */
 } sas_bp_swath_io;
 
 /* Make a plan for n_swaths swaths (1..4096). Validates every descriptor,

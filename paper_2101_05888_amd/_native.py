@@ -31,6 +31,7 @@ class SwathDesc(C.Structure):
         ("n", C.c_int64 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
         ("f_c", C.c_double), ("f_s", C.c_double), ("t0", C.c_double),
         ("gate_half_angle", C.c_double), ("c_min", C.c_double), ("interp", C.c_int32),
+        ("motion", C.c_int32),
     ]
 
 
@@ -45,7 +46,7 @@ class Options(C.Structure):
 class SwathIO(C.Structure):
     _fields_ = [
         ("echo", C.c_void_p), ("echo_scale", C.c_void_p), ("tx_pos", C.c_void_p),
-        ("rx_pos", C.c_void_p), ("c", C.c_void_p), ("image", C.c_void_p),
+        ("rx_pos", C.c_void_p), ("c", C.c_void_p), ("image", C.c_void_p), ("rx_vel", C.c_void_p),
     ]
 
 

@@ -24,9 +24,10 @@ INTERPS = {"linear": N.INTERP_LINEAR, "sinc8": N.INTERP_SINC8}
 def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin: Sequence[float],
                spacing: Sequence[float], f_c: float, f_s: float, t0: float = 0.0,
                gate_half_angle: float = 0.0, echo_dtype: str = "c64", c_min: float = 0.0,
-               interp: str = "linear") -> N.SwathDesc:
+               interp: str = "linear", motion: bool = False) -> N.SwathDesc:
     """Descriptor of one swath; ``interp`` is "linear" or "sinc8" (the
-    Hann-windowed sinc over 8 samples)."""
+    Hann-windowed sinc over 8 samples); ``motion`` selects receivers moving
+    during reception (``SwathBuffers.rx_vel``)."""
     if interp not in INTERPS:
         raise ValueError(f"interp must be one of {sorted(INTERPS)}")
     d = N.SwathDesc()
@@ -39,6 +40,7 @@ def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin
     d.f_c, d.f_s, d.t0 = float(f_c), float(f_s), float(t0)
     d.gate_half_angle, d.c_min = float(gate_half_angle), float(c_min)
     d.interp = INTERPS[interp]
+    d.motion = 1 if motion else 0
     return d
 
 
@@ -115,6 +117,7 @@ class SwathBuffers:
     c: torch.Tensor                     # float64 [1]
     image: torch.Tensor                 # complex64 [nz,ny,nx]
     echo_scale: Optional[torch.Tensor] = None   # float32 [P] for 16-bit echoes
+    rx_vel: Optional[torch.Tensor] = None       # float64 [P,3], receiver velocity (continuous motion)
 
 
 def _need(t: torch.Tensor, name: str, dtype, shape, device) -> None:
@@ -152,12 +155,15 @@ def _io_for(descs, device, bufs: Sequence[SwathBuffers]):
         _need(b.rx, f"rx[{i}]", torch.float64, (P, E, 3), device)
         _need(b.c, f"c[{i}]", torch.float64, (1,), device)
         _need(b.image, f"image[{i}]", torch.complex64, (d.n[2], d.n[1], d.n[0]), device)
+        if d.motion:
+            _need(b.rx_vel, f"rx_vel[{i}]", torch.float64, (P, 3), device)
         arr[i].echo = b.echo.data_ptr()
         arr[i].echo_scale = b.echo_scale.data_ptr() if b.echo_scale is not None else None
         arr[i].tx_pos = b.tx.data_ptr()
         arr[i].rx_pos = b.rx.data_ptr()
         arr[i].c = b.c.data_ptr()
         arr[i].image = b.image.data_ptr()
+        arr[i].rx_vel = b.rx_vel.data_ptr() if b.rx_vel is not None else None
     return arr
 
 

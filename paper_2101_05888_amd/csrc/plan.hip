@@ -28,7 +28,7 @@
 namespace sasbp {
 typedef void (*ImageKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
 ImageKernelFn image_kernel_for(int layout, bool gate, int dt, int interp);
-int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate);
+int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate, bool motion);
 hipError_t launch_init(const Workspace& ws, hipStream_t st);
 hipError_t launch_cull(const Workspace& ws, int n_tiles, int TX, int TY, int TZ, int bucket_shift, hipStream_t st);
 hipError_t launch_order(const Workspace& ws, int n_tiles, int bucket_shift, hipStream_t st);
@@ -139,6 +139,7 @@ struct sas_bp_plan_s {
   bool gate_any = false;
   int dtype = 0;
   int interp = 0;                  // SAS_BP_INTERP_*, shared by all swaths of the plan
+  int motion = 0;                  // continuous receiver motion, shared by all swaths of the plan
   int bucket_shift = 0;
   int lds_bytes = 0, adj_lds_bytes = 0;
   int grid = 0, adj_grid = 0;
@@ -206,6 +207,9 @@ int validate(const sas_bp_swath_desc* d, int i) {
   if (!(d->c_min >= 0.0) || !finite(d->c_min)) return fail(SAS_BP_EINVAL, "swath %d: c_min must be >= 0", i);
   if (d->interp != SAS_BP_INTERP_LINEAR && d->interp != SAS_BP_INTERP_SINC8)
     return fail(SAS_BP_EINVAL, "swath %d: unknown interpolator %d", i, d->interp);
+  if (d->motion != 0 && d->motion != 1) return fail(SAS_BP_EINVAL, "swath %d: motion must be 0 or 1", i);
+  if (d->motion && d->interp != SAS_BP_INTERP_LINEAR)
+    return fail(SAS_BP_EUNSUPPORTED, "swath %d: continuous motion is built for linear interpolation only", i);
   return SAS_BP_OK;
 }
 
@@ -285,19 +289,23 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
     // inequality on both legs). With the window start rounded down to an even
     // sample (the staging load width), entries up to 4 r f_s / c + 4 are read;
     // one more entry of margin for FP32 rounding of the sample position.
-    s.W = (int)std::ceil(4.0 * s.half_diag * d[i].f_s / s.c_min) + 6;
+    // Continuous motion moves a pixel's delay by at most one sample from the
+    // tile centre's (the record build refuses more) and starts the window one
+    // sample earlier: two more entries.
+    s.W = (int)std::ceil(4.0 * s.half_diag * d[i].f_s / s.c_min) + 6 + (d[i].motion ? 2 : 0);
     if (s.W > 8192) return fail(SAS_BP_EUNSUPPORTED, "swath %d: tile spans %d samples; use a smaller tile", i, s.W);
     const int E = d[i].n_elem;
     const int ppc = (o && o->pings_per_chunk > 0) ? o->pings_per_chunk : 0;
     const int epc = (o && o->elems_per_chunk > 0) ? std::min(o->elems_per_chunk, E) : 0;
     const bool gate = d[i].gate_half_angle > 0.0;
+    const bool mot = d[i].motion != 0;
     // adjoint chunk: whole pings
     int cp = ppc;
     if (cp == 0) {
       cp = 1;
-      while (cp < 8 && image_lds_bytes(cp * 2 * E, E, s.W, rows, gate) <= kLdsBudget) cp *= 2;
+      while (cp < 8 && image_lds_bytes(cp * 2 * E, E, s.W, rows, gate, false) <= kLdsBudget) cp *= 2;
     }
-    if (ppc > 0 && image_lds_bytes(cp * E, E, s.W, rows, gate) > kLdsMax - 1024)
+    if (ppc > 0 && image_lds_bytes(cp * E, E, s.W, rows, gate, mot) > kLdsMax - 1024)
       return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d pings x %d elements x %d samples exceed LDS", i, cp, E, s.W);
     s.CP = cp;   // if even one whole ping does not fit, the plan has no adjoint
     // image chunk in records: explicit elements (part of a ping), explicit
@@ -310,8 +318,8 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
     else {
       const int target = image_lds_target(t.NT);
       rc = 8 * E;
-      while (rc > E && image_lds_bytes(rc, E, s.W, rows, gate) > target) rc /= 2;
-      while (rc > 1 && image_lds_bytes(rc, E, s.W, rows, gate) > target) --rc;
+      while (rc > E && image_lds_bytes(rc, E, s.W, rows, gate, mot) > target) rc /= 2;
+      while (rc > 1 && image_lds_bytes(rc, E, s.W, rows, gate, mot) > target) --rc;
       // part of a ping: a whole number of quarter pings where possible (measured
       // faster than the largest fitting count on both the 2D and 3D workloads)
       if (rc < E && E >= 4 && rc >= E / 4) rc = rc / (E / 4) * (E / 4);
@@ -319,7 +327,7 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
     // the geometry build keeps its list of partially gated records (one int
     // each) in the window area, which must hold at least one ping's list
     rc = std::max(rc, (E + 4 * (s.W + 1) - 1) / (4 * (s.W + 1)));
-    if (image_lds_bytes(rc, E, s.W, rows, gate) > kLdsMax - 1024)
+    if (image_lds_bytes(rc, E, s.W, rows, gate, mot) > kLdsMax - 1024)
       return fail(SAS_BP_EUNSUPPORTED, "swath %d: %d records x %d samples exceed LDS", i, rc, s.W);
     s.RC = rc;
     const int cap = (int)std::min<long long>(32, 4ll * rc * (s.W + 1) / E);   // pings whose list fits
@@ -376,6 +384,7 @@ SwathDev make_dev(const SwathPlan& s) {
   v.Ns = s.d.n_sample;
   v.dtype = s.d.echo_dtype;
   v.interp = s.d.interp;
+  v.motion = s.d.motion;
   v.nx = (int)s.d.n[0];
   v.ny = (int)s.d.n[1];
   v.nz = (int)s.d.n[2];
@@ -414,6 +423,8 @@ int check_io(const sas_bp_plan_s* p, const sas_bp_swath_io* io, int n) {
       return fail(SAS_BP_EINVAL, "swath %d: navigation not 8-byte aligned", i);
     if (s.d.echo_dtype != SAS_BP_ECHO_C64 && !io[i].echo_scale)
       return fail(SAS_BP_EINVAL, "swath %d: echo_scale required for 16-bit echoes", i);
+    if (s.d.motion && (!io[i].rx_vel || ((uintptr_t)io[i].rx_vel & 7u)))
+      return fail(SAS_BP_EINVAL, "swath %d: continuous motion needs an 8-byte aligned rx_vel", i);
   }
   return SAS_BP_OK;
 }
@@ -542,8 +553,8 @@ int plan_sizes(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, Ti
   size_t stride = 0;
   int lds = 0;
   for (const auto& s : *sw) {
-    stride = std::max(stride, (size_t)geo_layout(s.SC, s.d.n_elem, rows, gate_any).bytes);
-    lds = std::max(lds, std::min(image_lds_bytes(s.RC, s.d.n_elem, s.W, rows, gate_any),
+    stride = std::max(stride, (size_t)geo_layout(s.SC, s.d.n_elem, rows, gate_any, s.d.motion != 0).bytes);
+    lds = std::max(lds, std::min(image_lds_bytes(s.RC, s.d.n_elem, s.W, rows, gate_any, s.d.motion != 0),
                                  adjoint_lds_bytes(s.CP, s.d.n_elem, s.W, rows, gate_any, t->NT)));
   }
   const int per_cu = std::max(1, std::min(8, kLdsMax / std::max(1, lds)));
@@ -632,6 +643,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   if (!options) p->use_graph = true;
   p->dtype = sw[0].d.echo_dtype;
   p->interp = sw[0].d.interp;
+  p->motion = sw[0].d.motion;
   int max_pe = 1, max_lds = 0, max_adj_lds = 0;
   for (const auto& s : sw) {
     const bool gate = s.d.gate_half_angle > 0.0;
@@ -644,11 +656,15 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
       release(p);
       return fail(SAS_BP_EUNSUPPORTED, "all swaths of a plan must share one interpolator");
     }
+    if (s.d.motion != p->motion) {
+      release(p);
+      return fail(SAS_BP_EUNSUPPORTED, "all swaths of a plan must share one motion model");
+    }
     max_pe = std::max(max_pe, s.d.n_ping * s.d.n_elem);
     p->max_p = std::max(p->max_p, s.d.n_ping);
   }
   for (const auto& s : sw) {
-    max_lds = std::max(max_lds, image_lds_bytes(s.RC, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any));
+    max_lds = std::max(max_lds, image_lds_bytes(s.RC, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any, p->motion != 0));
     max_adj_lds = std::max(max_adj_lds, adjoint_lds_bytes(s.CP, s.d.n_elem, s.W, t.TY * t.TZ, p->gate_any, t.NT));
   }
   p->max_pe = max_pe;
@@ -657,7 +673,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->bucket_shift = shift;
   p->lds_bytes = max_lds;
   p->adj_lds_bytes = max_adj_lds;
-  p->image_fn = image_kernel_for(t.layout, p->gate_any, p->dtype, p->interp);
+  p->image_fn = image_kernel_for(t.layout, p->gate_any, p->dtype, p->motion ? 2 : p->interp);
   p->adjoint_fn = adjoint_kernel_for(t.layout, p->gate_any, p->dtype);
   p->reproject_fn = reproject_kernel_for(t.layout, p->gate_any);
   if (!p->image_fn || !p->adjoint_fn || !p->reproject_fn) {
@@ -749,6 +765,7 @@ int sas_bp_image(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swaths, void*
     v[i].scale = io[i].echo_scale;
     v[i].tx = io[i].tx_pos;
     v[i].rx = io[i].rx_pos;
+    v[i].vel = io[i].rx_vel;
     v[i].c = io[i].c;
     v[i].image = reinterpret_cast<float2*>(io[i].image);
   }
@@ -769,8 +786,8 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   if (!grad_image || !grad_tx || !grad_rx || !grad_c) return fail(SAS_BP_EINVAL, "gradient array is NULL");
-  if (p->interp != SAS_BP_INTERP_LINEAR)
-    return fail(SAS_BP_EUNSUPPORTED, "the adjoint is built for linear interpolation only");
+  if (p->interp != SAS_BP_INTERP_LINEAR || p->motion)
+    return fail(SAS_BP_EUNSUPPORTED, "the adjoint is built for linear interpolation with stop-and-hop positions only");
   if (!p->adj_ok)
     return fail(SAS_BP_EUNSUPPORTED, "the adjoint stages whole pings and needs %d bytes of LDS with this tiling; "
                 "plan with a smaller tile", p->adj_lds_bytes);
@@ -791,6 +808,7 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
     v[i].scale = io[i].echo_scale;
     v[i].tx = io[i].tx_pos;
     v[i].rx = io[i].rx_pos;
+    v[i].vel = io[i].rx_vel;
     v[i].c = io[i].c;
     v[i].image = reinterpret_cast<float2*>(io[i].image);
     v[i].gimage = reinterpret_cast<const float2*>(grad_image[i]);
@@ -836,8 +854,8 @@ int sas_bp_reproject(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* con
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   if (!image_in || !echo_out) return fail(SAS_BP_EINVAL, "image_in or echo_out is NULL");
-  if (p->interp != SAS_BP_INTERP_LINEAR)
-    return fail(SAS_BP_EUNSUPPORTED, "reprojection is built for linear interpolation only");
+  if (p->interp != SAS_BP_INTERP_LINEAR || p->motion)
+    return fail(SAS_BP_EUNSUPPORTED, "reprojection is built for linear interpolation with stop-and-hop positions only");
   for (int i = 0; i < n_swaths; ++i) {
     if (!image_in[i] || !echo_out[i]) return fail(SAS_BP_EINVAL, "swath %d: NULL image_in or echo_out", i);
     if (((uintptr_t)image_in[i] & 7u) || ((uintptr_t)echo_out[i] & 7u))
@@ -852,6 +870,7 @@ int sas_bp_reproject(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* con
     v[i].scale = io[i].echo_scale;
     v[i].tx = io[i].tx_pos;
     v[i].rx = io[i].rx_pos;
+    v[i].vel = io[i].rx_vel;
     v[i].c = io[i].c;
     v[i].image = reinterpret_cast<float2*>(io[i].image);
     v[i].gimage = reinterpret_cast<const float2*>(image_in[i]);
@@ -1029,6 +1048,7 @@ int sas_bp_useful_updates(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swat
     v[i].scale = io[i].echo_scale;
     v[i].tx = io[i].tx_pos;
     v[i].rx = io[i].rx_pos;
+    v[i].vel = io[i].rx_vel;
     v[i].c = io[i].c;
     v[i].image = reinterpret_cast<float2*>(io[i].image);
   }

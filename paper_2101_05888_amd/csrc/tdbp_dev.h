@@ -47,8 +47,10 @@ struct SwathDev {
   double* grad_rx;
   double* grad_c;
   float2* gecho;          // reprojection output (complex64, echo layout)
+  const double* vel;      // receiver velocity during reception [P][3] (continuous motion)
   int P, E, Ns, dtype;
   int interp;             // 0 linear, 1 windowed sinc over 2 * kSincHalf samples
+  int motion;             // 1: receivers move at vel during reception
   int nx, ny, nz;
   int ntx, nty, ntz;      // tiles per axis
   int tile0;              // index of this swath's first tile in the global tile list
@@ -90,14 +92,16 @@ struct Workspace {
 // the workgroup's region):
 //   receiver records [SC][E] (48 B)   window starts [SC][E] (int)
 //   transmitter records [SC] (32 B)   gate rows [SC][E][ROWS] (int, gate only)
+//   continuous motion only: motion offsets at the tile centre [SC][E] (float),
+//   ping velocities [SC] (float4: vx, vy, vz, |v|^2)
 constexpr int kRxRecBytes = 48;
 constexpr int kTxRecBytes = 32;
 
 struct GeoLayout {
-  long long rec, n0, tx, rows, bytes;
+  long long rec, n0, tx, rows, dc, vel, bytes;
 };
 
-__host__ __device__ inline GeoLayout geo_layout(int SC, int E, int ROWS, bool gate) {
+__host__ __device__ inline GeoLayout geo_layout(int SC, int E, int ROWS, bool gate, bool motion = false) {
   GeoLayout g;
   long long o = 0;
   g.rec = o;  o += (long long)SC * E * kRxRecBytes;
@@ -105,6 +109,10 @@ __host__ __device__ inline GeoLayout geo_layout(int SC, int E, int ROWS, bool ga
   o = (o + 15) & ~15ll;
   g.tx = o;   o += (long long)SC * kTxRecBytes;
   g.rows = o; o += gate ? (long long)SC * E * ROWS * 4 : 0;
+  o = (o + 15) & ~15ll;
+  g.dc = o;   o += motion ? (long long)SC * E * 4 : 0;
+  o = (o + 15) & ~15ll;
+  g.vel = o;  o += motion ? (long long)SC * 16 : 0;
   g.bytes = (o + 255) & ~255ll;
   return g;
 }

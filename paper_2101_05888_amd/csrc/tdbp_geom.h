@@ -78,8 +78,19 @@ __device__ __forceinline__ int gate_class(double tan2, double x, double y, doubl
 
 // Receiver record and window start for (ping p, element e) of the tile centred
 // at C. Returns false if the navigation is not finite (record marked skip).
+//
+// MOTION (receivers moving at v_p during reception, R(t) = R + v_p t): the
+// reference delay is the exact root of c tau = d_T + |C - R - v_p tau| at the
+// tile centre (the larger root of (c^2 - |v|^2) tau^2 - 2 (c d_T - a.v) tau +
+// d_T^2 - |a|^2 = 0, a = C - R), *dc_out the extra path c tau - d_T - d_R it
+// implies, and the window starts one sample earlier (the plan adds two samples
+// to W). A bound on how much that extra path changes across the tile,
+// r (2 |v| tau_max / (d_R - r) + 4 |v| / c), must stay within one sample;
+// otherwise, or for a velocity not finite or of |v| >= c / 2, the record is
+// refused like bad navigation.
+template <bool MOTION = false>
 __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c, const double C[3], int p, int e,
-                                               RxRec* rec, int* n0_out) {
+                                               RxRec* rec, int* n0_out, double c = 0.0, float* dc_out = nullptr) {
   const double* T = sw.tx + (size_t)p * 3;
   const double* R = sw.rx + ((size_t)p * sw.E + e) * 3;
   const double tx0 = T[0], tx1 = T[1], tx2 = T[2];
@@ -88,11 +99,29 @@ __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c,
   const double uR0 = C[0] - rx0, uR1 = C[1] - rx1, uR2 = C[2] - rx2;
   const double d0T = sqrt(uT0 * uT0 + uT1 * uT1 + uT2 * uT2);
   const double d0R = sqrt(uR0 * uR0 + uR1 * uR1 + uR2 * uR2);
-  const bool ok = finite3(tx0, tx1, tx2) && finite3(rx0, rx1, rx2);
-  const double tau = (d0T + d0R) * inv_c;
+  bool ok = finite3(tx0, tx1, tx2) && finite3(rx0, rx1, rx2);
+  double tau = (d0T + d0R) * inv_c;
+  if constexpr (MOTION) {
+    const double* V = sw.vel + (size_t)p * 3;
+    const double v0 = V[0], v1 = V[1], v2 = V[2];
+    const double vv = v0 * v0 + v1 * v1 + v2 * v2;
+    const double av = uR0 * v0 + uR1 * v1 + uR2 * v2;
+    const double A = c * c - vv;
+    const double Bh = c * d0T - av;
+    const double tm = (Bh + sqrt(Bh * Bh - A * (d0T * d0T - d0R * d0R))) / A;
+    const double r = sw.half_diag, vm = sqrt(vv);
+    const double bound = r * (2.0 * vm * (tm + 2.0 * r * inv_c) / fmax(d0R - r, 1e-3) + 4.0 * vm * inv_c);
+    ok = ok && finite3(v0, v1, v2) && vv < 0.25 * c * c && isfinite(tm) && bound * sw.fs * inv_c <= 1.0;
+    double dcm = 0.0;
+    if (ok) {
+      dcm = c * tm - d0T - d0R;
+      tau = tm;
+    }
+    *dc_out = (float)dcm;
+  }
   const double uref = (tau - sw.t0) * sw.fs;
   const double span = 2.0 * sw.half_diag * sw.fs * inv_c;
-  double nstart = floor(uref - span) - 2.0;
+  double nstart = floor(uref - span) - (MOTION ? 3.0 : 2.0);
   if (!(nstart > -1.0e9)) nstart = -1.0e9;          // also maps NaN to a harmless value
   if (nstart > 1.0e9) nstart = 1.0e9;
   // window start even: staging loads two samples per lane, aligned
@@ -213,10 +242,12 @@ __device__ __forceinline__ float2 load_sample(const void* base, size_t idx, int 
 // (a tie, s an integer rounded down to n = s - 1, gives w = 1/2 and the same
 // value). Gated-out pixels read the zero entry.
 struct LdsLayout {
-  int off_tx, off_rx, off_n0, off_rows, off_win, bytes;
+  int off_tx, off_rx, off_n0, off_rows, off_win, off_dc, off_vel, bytes;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int NR, int NS, int W, int ROWS, bool gate) {
+// Continuous motion appends the records' motion offsets (float [NR]) and the
+// pings' velocities (float4 [NS]) after the windows.
+__host__ __device__ inline LdsLayout lds_layout(int NR, int NS, int W, int ROWS, bool gate, bool motion = false) {
   LdsLayout L;
   int o = 0;
   L.off_tx = o;   o += NS * (int)sizeof(TxRec);
@@ -226,6 +257,8 @@ __host__ __device__ inline LdsLayout lds_layout(int NR, int NS, int W, int ROWS,
   L.off_rows = o; o += gate ? NR * ROWS * 4 : 0;
   o = (o + 15) & ~15;
   L.off_win = o;  o += NR * (W + 1) * 16;
+  L.off_dc = o;   o += motion ? ((NR * 4 + 15) & ~15) : 0;
+  L.off_vel = o;  o += motion ? NS * 16 : 0;
   L.bytes = o;
   return L;
 }
@@ -239,16 +272,20 @@ struct Geo {
   int* n0;
   TxRec* tx;
   int* rows;
+  float* dc;      // continuous motion only
+  float4* vel;
 };
 
 __device__ __forceinline__ Geo geo_for(const Workspace& ws, const SwathDev& sw, int ROWS, bool gate) {
-  const GeoLayout gl = geo_layout(sw.SC, sw.E, ROWS, gate);
+  const GeoLayout gl = geo_layout(sw.SC, sw.E, ROWS, gate, sw.motion != 0);
   unsigned char* base = ws.geo + (size_t)blockIdx.x * (size_t)ws.geo_stride;
   Geo g;
   g.rec = reinterpret_cast<RxRec*>(base + gl.rec);
   g.n0 = reinterpret_cast<int*>(base + gl.n0);
   g.tx = reinterpret_cast<TxRec*>(base + gl.tx);
   g.rows = reinterpret_cast<int*>(base + gl.rows);
+  g.dc = reinterpret_cast<float*>(base + gl.dc);
+  g.vel = reinterpret_cast<float4*>(base + gl.vel);
   return g;
 }
 
@@ -259,7 +296,7 @@ __device__ __forceinline__ Geo geo_for(const Workspace& ws, const SwathDev& sw, 
 // that the long FP64 dependency chains of many records overlap; the list of
 // partial records is kept in LDS scratch (lpart, *lnpart) that the caller
 // lends (the window area, unused between chunks). Ends with a barrier.
-template <int NT, int TX, int LY, int LZ, bool GATE>
+template <int NT, int TX, int LY, int LZ, bool GATE, bool MOTION = false>
 __device__ __forceinline__ void build_geometry(const Geo& g, int* lpart, int* lnpart, const Workspace& ws,
                                                const SwathDev& sw, double c, const double* C, int P0, int sc,
                                                int x0, int y0, int z0, int tid) {
@@ -280,7 +317,9 @@ __device__ __forceinline__ void build_geometry(const Geo& g, int* lpart, int* ln
     const int p = P0 + slot;
     RxRec rec;
     int n0;
-    if (!make_rx_record(sw, inv_c, C, p, e, &rec, &n0)) atomicOr(&ws.counters[1], kStatusNav);
+    float dcv = 0.0f;
+    if (!make_rx_record<MOTION>(sw, inv_c, C, p, e, &rec, &n0, c, &dcv)) atomicOr(&ws.counters[1], kStatusNav);
+    if (MOTION) g.dc[r] = dcv;
     unsigned f = __float_as_uint(rec.q0.w);
     if (!gate_on) {
       f |= kFlagFull;
@@ -298,7 +337,13 @@ __device__ __forceinline__ void build_geometry(const Geo& g, int* lpart, int* ln
     g.n0[r] = n0;
   }
 #pragma unroll 1
-  for (int s = tid; s < sc; s += NT) make_tx_record(sw, C, P0 + s, &g.tx[s]);
+  for (int s = tid; s < sc; s += NT) {
+    make_tx_record(sw, C, P0 + s, &g.tx[s]);
+    if (MOTION) {
+      const double* V = sw.vel + (size_t)(P0 + s) * 3;
+      g.vel[s] = make_float4((float)V[0], (float)V[1], (float)V[2], (float)(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]));
+    }
+  }
   __syncthreads();
   if (gate_on) {
     const int np = *lnpart;
@@ -516,7 +561,7 @@ __device__ __forceinline__ void stage_windows_raw(float2* lwin, const RxRec* lrx
 // q0 .. q0 + nr - 1 of the run (record q is ping P0 + q / E, element q % E),
 // spanning the ns pings s0 .. s0 + ns - 1 of the run. Receiver records,
 // window starts, transmitter records and gate rows go into LDS. No barrier.
-template <int NT, int ROWS, bool GATE>
+template <int NT, int ROWS, bool GATE, bool MOTION = false>
 __device__ __forceinline__ void load_records(unsigned char* lds, const Geo& g, const SwathDev& sw, int q0, int nr,
                                              int s0, int ns, const LdsLayout& L, int tid) {
   TxRec* ltx = reinterpret_cast<TxRec*>(lds + L.off_tx);
@@ -529,6 +574,12 @@ __device__ __forceinline__ void load_records(unsigned char* lds, const Geo& g, c
     ln0[r] = gn0[r];
   }
   for (int s = tid; s < ns; s += NT) ltx[s] = g.tx[s0 + s];
+  if (MOTION) {
+    float* ldc = reinterpret_cast<float*>(lds + L.off_dc);
+    float4* lvel = reinterpret_cast<float4*>(lds + L.off_vel);
+    for (int r = tid; r < nr; r += NT) ldc[r] = g.dc[q0 + r];
+    for (int s = tid; s < ns; s += NT) lvel[s] = g.vel[s0 + s];
+  }
   if (GATE && sw.tan_g > 0.0) {
     // rows of records that are not partial hold stale values and are never read
     const int4* src = reinterpret_cast<const int4*>(g.rows + (size_t)q0 * ROWS);
@@ -540,11 +591,11 @@ __device__ __forceinline__ void load_records(unsigned char* lds, const Geo& g, c
 // One chunk (as for load_records): the records into LDS, then the echo
 // windows (midpoint form, or raw samples for the windowed-sinc variant).
 // Ends with a barrier.
-template <int NT, int ROWS, bool GATE, int DT, bool RAW = false>
+template <int NT, int ROWS, bool GATE, int DT, bool RAW = false, bool MOTION = false>
 __device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, const SwathDev& sw, int P0, int q0,
                                            int nr, int s0, int ns, const LdsLayout& L, int tid, int lane,
                                            int wave) {
-  load_records<NT, ROWS, GATE>(lds, g, sw, q0, nr, s0, ns, L, tid);
+  load_records<NT, ROWS, GATE, MOTION>(lds, g, sw, q0, nr, s0, ns, L, tid);
   __syncthreads();
   if (RAW)
     stage_windows_raw<NT, DT>(reinterpret_cast<float2*>(lds + L.off_win), reinterpret_cast<const RxRec*>(lds + L.off_rx),

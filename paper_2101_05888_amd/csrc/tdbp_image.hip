@@ -66,6 +66,12 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
       // record test: the two-way delay of the tile lies within [dT0+dR0 - 2r, dT0+dR0 + 2r]
       const double u0 = C[0] - T[0], u1 = C[1] - T[1], u2 = C[2] - T[2];
       const double dT = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+      // continuous motion moves a delay by at most |v| tau (the receiver's displacement)
+      double vm = 0.0;
+      if (sw.motion) {
+        const double* V = sw.vel + (size_t)p * 3;
+        vm = sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
+      }
       bool in_record = false;
       bool rx_hit = false;
       for (int e = 0; e < sw.E; ++e) {
@@ -74,7 +80,8 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
         const double dR = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
         const double ulo = ((dT + dR - 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
         const double uhi = ((dT + dR + 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
-        const double reach = sw.interp ? (double)kSincHalf : 0.0;   // taps beyond the delay
+        double reach = sw.interp == 1 ? (double)kSincHalf : 0.0;   // taps beyond the delay
+        if (sw.motion) reach += vm * (dT + dR + 2.0 * sw.half_diag) / c * sw.fs / c + 1.0;
         const bool rec_e = (uhi >= -2.0 - reach) && (ulo <= (double)sw.Ns + 1.0 + reach);
         const bool gate_e = sw.tan_g > 0.0 ? cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, R) : true;
         in_record |= rec_e && gate_e;
@@ -83,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
       if (sw.tan_g > 0.0) hit = cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, T) && rx_hit;
       // non-finite navigation makes every comparison false; keep such pings so
       // that the image kernel can flag them
-      const bool bad = !(isfinite(dT));
+      const bool bad = !(isfinite(dT)) || !isfinite(vm);
       if ((hit && in_record) || bad) {
         atomicMin(&s_lo, p);
         atomicMax(&s_hi, p);
@@ -128,15 +135,36 @@ __global__ __launch_bounds__(kThreads) void order_kernel(Workspace ws, int n_til
   }
 }
 
+// Continuous motion: per-record constants of the per-pixel correction.
+//   hx = (C - R)_x, avyz = ((C - R)_y + dy) v_y + ((C - R)_z + dz) v_z for the
+//   lane's row, (vx, vv) = (v_x, |v|^2), tc = (d0_T + d0_R + dc) / c with dc
+//   the motion path at the tile centre, ic = 1 / c.
+struct MotionTerm {
+  float hx, avyz, vx, vv, tc, dc, ic;
+};
+
 // One (ping, element) record applied to the K pixels of a lane. DEG selects
 // the receiver-leg offset (0 the exact form, 4 or 5 the series of that
 // degree), TEST the per-pixel gate test of a partially gated record; both are
 // uniform over the workgroup.
-template <int K, int LX, int DEG, bool TEST>
+//
+// MOT adds the receiver's motion during reception. With a = p - R (ping-time
+// receiver), D the stop-and-hop path offset and tau_1 = tc + D / c (the
+// pixel's delay with the centre's motion path dc), the motion path
+// delta = |a - v tau| - |a| solves delta = f(delta); one Newton step from dc,
+//     g = n / (|a - v tau_1| + |a|),  n = tau_1 (tau_1 |v|^2 - 2 a.v),
+//     F = g - dc,  eps = (a.v - tau_1 |v|^2) / (c |a - v tau_1|),
+//     delta = dc + F (1 - eps)
+// (the cancellation-free form of |a - w| - |a|; 1/(1 + eps) to first order,
+// eps ~ |v|/c, and 1/|a - v tau_1| as 2 / (|a - v tau_1| + |a|); the step
+// leaves errors far below a micrometre while |F| stays within the sample the
+// plan allows). The record's reference already holds dc, so the offset grows
+// by F (1 - eps).
+template <int K, int LX, int DEG, bool TEST, bool MOT = false>
 __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __restrict__ win, const float* dx,
                                            const float* dsq, const float* dT, float dyl, float dzl, float fs_c,
                                            float fc_c, float szero, int da, int span, float* accr,
-                                           float* acci) {
+                                           float* acci, const MotionTerm& mt = MotionTerm{}) {
   const float ryz = fmaf(rec.q0.y, dyl, rec.q0.z * dzl);
   const float d0 = rec.q1.w;
   const float d0sq = d0 * d0;
@@ -146,7 +174,29 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
   for (int k = 0; k < K; ++k) {
     const float num = fmaf(rec.q0.x, dx[k], ryz + dsq[k]);
     float D;   // two-way path offset from the (tile, ping, element) reference, metres
-    if (DEG > 0) {
+    if constexpr (MOT) {
+      float dR;
+      if (DEG > 0) {
+        float h = DEG == 5 ? fmaf(rec.q1.z, num, rec.q2.w) : rec.q2.w;
+        h = fmaf(h, num, rec.q2.z);
+        h = fmaf(h, num, rec.q2.y);
+        h = fmaf(h, num, rec.q2.x);
+        dR = h * num;
+      } else {
+        const float sq = __builtin_amdgcn_sqrtf(d0sq + num);
+        dR = num * __builtin_amdgcn_rcpf(d0 + sq);
+      }
+      D = dR + dT[k];
+      const float av = fmaf(mt.hx + dx[k], mt.vx, mt.avyz);
+      const float am = d0 + dR;
+      const float t1 = fmaf(D, mt.ic, mt.tc);
+      const float tvv = t1 * mt.vv;
+      const float n = t1 * fmaf(-2.0f, av, tvv);
+      const float rr = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(am, am, n)) + am);
+      const float F = fmaf(n, rr, -mt.dc);
+      const float eps = (av - tvv) * (2.0f * mt.ic * rr);
+      D += fmaf(-F, eps, F);
+    } else if (DEG > 0) {
       float h = DEG == 5 ? fmaf(rec.q1.z, num, rec.q2.w) : rec.q2.w;
       h = fmaf(h, num, rec.q2.z);
       h = fmaf(h, num, rec.q2.y);
@@ -315,8 +365,10 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
     const double c = *sw.c;
     const float fs_c = (float)(sw.fs / c);
     const float fc_c = (float)(sw.fc / c);
+    const float ic = (float)(1.0 / c);
     const PingRange pr = prange[t];
-    const LdsLayout Ld = lds_layout(RC, chunk_pings(RC, E), W, ROWS, GATE);
+    constexpr bool MOT = INTERP == 2;   // linear interpolation, receivers moving during reception
+    const LdsLayout Ld = lds_layout(RC, chunk_pings(RC, E), W, ROWS, GATE, MOT);
     const TxRec* ltx = reinterpret_cast<const TxRec*>(lds + Ld.off_tx);
     const RxRec* lrx = reinterpret_cast<const RxRec*>(lds + Ld.off_rx);
     const int* lrows = reinterpret_cast<const int*>(lds + Ld.off_rows);
@@ -343,17 +395,20 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
     for (int P0 = pr.lo; P0 <= pr.hi; P0 += sw.SC) {
       const int sc = min(sw.SC, pr.hi - P0 + 1);
       __syncthreads();
-      build_geometry<NT, TX, LY, LZ, GATE>(geo, lpart, &s_npart, ws, sw, c, C, P0, sc, x0, y0, z0, tid);
+      build_geometry<NT, TX, LY, LZ, GATE, MOT>(geo, lpart, &s_npart, ws, sw, c, C, P0, sc, x0, y0, z0, tid);
       // chunks of RC records (ping-major) of the run; a chunk may hold part
       // of a ping, a whole ping or several pings. The transmitter leg dT of
       // a ping split over two chunks is formed once.
       float dT[K];
       int dT_slot = -1;
+      float d0T = 0.0f;
+      float4 vel = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       for (int q0 = 0; q0 < sc * E; q0 += RC) {
         const int nr = min(RC, sc * E - q0);
         const int sa = q0 / E, sb = (q0 + nr - 1) / E;
         if (q0 > 0) __syncthreads();
-        load_chunk<NT, ROWS, GATE, DT, INTERP == 1>(lds, geo, sw, P0, q0, nr, sa, sb - sa + 1, Ld, tid, lane, wave);
+        load_chunk<NT, ROWS, GATE, DT, INTERP == 1, MOT>(lds, geo, sw, P0, q0, nr, sa, sb - sa + 1, Ld, tid, lane,
+                                                         wave);
         for (int slot = sa; slot <= sb; ++slot) {
           if (slot != dT_slot) {
             const TxRec tr = ltx[slot - sa];
@@ -365,6 +420,10 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
               dT[k] = num * __builtin_amdgcn_rcpf(tr.d0 + sq);
             }
             dT_slot = slot;
+            if (MOT) {
+              d0T = tr.d0;
+              vel = reinterpret_cast<const float4*>(lds + Ld.off_vel)[slot - sa];
+            }
           }
           const int r_lo = max(slot * E, q0) - q0, r_hi = min(slot * E + E, q0 + nr) - q0;
           for (int r = r_lo; r < r_hi; ++r) {
@@ -387,6 +446,31 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
               } else {
                 if (test) accumulate_sinc<K, LX, 0, true>(rec, rwin, dx, dsq, dT, dyl, dzl, fs_c, fc_c, da, span, accr, acci);
                 else accumulate_sinc<K, LX, 0, false>(rec, rwin, dx, dsq, dT, dyl, dzl, fs_c, fc_c, 0, 0, accr, acci);
+              }
+              continue;
+            }
+            if constexpr (MOT) {
+              MotionTerm mt;
+              mt.hx = 0.5f * rec.q0.x;
+              mt.avyz = fmaf(fmaf(0.5f, rec.q0.y, dyl), vel.y, fmaf(0.5f, rec.q0.z, dzl) * vel.z);
+              mt.vx = vel.x;
+              mt.vv = vel.w;
+              mt.ic = ic;
+              mt.dc = reinterpret_cast<const float*>(lds + Ld.off_dc)[r];
+              mt.tc = (d0T + rec.q1.w + mt.dc) * ic;
+              int da = 0, span = 0;
+              const bool test = GATE && !(f & kFlagFull);
+              if (test) {
+                const int v = lrows[r * ROWS + row];
+                da = lx - row_lo(v);
+                span = row_hi(v) - row_lo(v);
+              }
+              if (f & kFlagPoly) {
+                if (test) accumulate<K, LX, 5, true, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, da, span, accr, acci, mt);
+                else accumulate<K, LX, 5, false, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci, mt);
+              } else {
+                if (test) accumulate<K, LX, 0, true, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, da, span, accr, acci, mt);
+                else accumulate<K, LX, 0, false, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci, mt);
               }
               continue;
             }
@@ -463,12 +547,17 @@ static ImageKernelFn image_for_interp(int layout, bool gate, int dt) {
   }
 }
 
+// interp: 0 linear, 1 windowed sinc, 2 linear with the receivers moving during reception
 ImageKernelFn image_kernel_for(int layout, bool gate, int dt, int interp) {
-  return interp == 1 ? image_for_interp<1>(layout, gate, dt) : image_for_interp<0>(layout, gate, dt);
+  switch (interp) {
+    case 1: return image_for_interp<1>(layout, gate, dt);
+    case 2: return image_for_interp<2>(layout, gate, dt);
+    default: return image_for_interp<0>(layout, gate, dt);
+  }
 }
 
-int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate) {
-  return lds_layout(RC, chunk_pings(RC, E), W, ROWS, gate).bytes;
+int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate, bool motion) {
+  return lds_layout(RC, chunk_pings(RC, E), W, ROWS, gate, motion).bytes;
 }
 
 hipError_t launch_init(const Workspace& ws, hipStream_t st) {

@@ -29,14 +29,15 @@ def workers() -> int:
     return max(1, min(16, n))
 
 
-def desc_for(api, scn: Scenario, echo_dtype: str = "c64", c_min: float = 0.0, interp: str = "linear"):
+def desc_for(api, scn: Scenario, echo_dtype: str = "c64", c_min: float = 0.0, interp: str = "linear",
+             motion: bool = False):
     g = scn.grid
     return api.swath_desc(scn.n_ping, scn.n_elem, scn.n_sample, g.n, g.origin, g.spacing,
-                          scn.fc, scn.fs, scn.t0, scn.gate_half_angle, echo_dtype, c_min, interp)
+                          scn.fc, scn.fs, scn.t0, scn.gate_half_angle, echo_dtype, c_min, interp, motion)
 
 
 def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scale=None,
-                tx=None, rx=None, c=None):
+                tx=None, rx=None, c=None, rx_vel=None):
     g = scn.grid
     dev = torch.device(device)
     tx = scn.tx if tx is None else tx
@@ -48,25 +49,27 @@ def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scal
         c=torch.tensor([scn.c if c is None else c], dtype=torch.float64, device=dev),
         image=torch.zeros((g.n[2], g.n[1], g.n[0]), dtype=torch.complex64, device=dev),
         echo_scale=None if echo_scale is None else echo_scale.to(dev).contiguous(),
+        rx_vel=None if rx_vel is None else torch.as_tensor(np.ascontiguousarray(rx_vel), dtype=torch.float64,
+                                                           device=dev),
     )
 
 
 def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_scale=None, interp="linear",
-              **plan_kw):
-    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype, interp=interp)], **plan_kw)
-    buf = buffers_for(api, scn, echo, echo_scale=echo_scale)
+              rx_vel=None, **plan_kw):
+    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype, interp=interp, motion=rx_vel is not None)], **plan_kw)
+    buf = buffers_for(api, scn, echo, echo_scale=echo_scale, rx_vel=rx_vel)
     api.sas_bp_image(plan, [buf])
     torch.cuda.synchronize()
     assert plan.status() == 0
     return buf.image.cpu().numpy(), plan, buf
 
 
-def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None, interp="linear"):
+def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None, interp="linear", rx_vel=None):
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, index)
     return oracle.backproject(echo_np, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
                               scn.gate_half_angle, workers=workers(),
-                              interp="sinc" if interp == "sinc8" else interp)
+                              interp="sinc" if interp == "sinc8" else interp, rx_vel=rx_vel)
 
 
 def report(name, img, ref):
