@@ -252,6 +252,44 @@ def sinc_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_kerne
             "rel_l2": r, "max_phase_mrad": ph, "sample_pixels": sample}
 
 
+def motion_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_kernel_ms: float, sample: int) -> dict:
+    """Continuous receiver motion during reception on the same swath (the
+    receivers moving at the track's 1.46 m/s during each ping's reception):
+    image kernel time, and its error against the oracle's exact delay root on
+    a seeded pixel sample (same echo cube; the timing does not depend on it)."""
+    import oracle
+    from synth import subset_indices, receiver_velocity
+    vel = receiver_velocity(scn)
+    d = _desc(api, scn)
+    d.motion = 1
+    plan = api.sas_bp_plan([d])
+    buf = _buffers(api, scn, echo)
+    buf.rx_vel = torch.as_tensor(vel, dtype=torch.float64, device="cuda")
+    api.sas_bp_set_kernel_timing(plan, True)
+    for _ in range(warmup):
+        api.sas_bp_image(plan, [buf])
+    api.sas_bp_kernel_time(plan)
+    ms = time_steps(lambda: api.sas_bp_image(plan, [buf]), steps, 0)
+    k_total, k_n = api.sas_bp_kernel_time(plan)
+    kms = k_total / k_n
+    status = plan.status()
+    idx = subset_indices(scn, sample)
+    got = buf.image.reshape(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    g = scn.grid
+    pts = oracle.pixel_points(g.origin, g.spacing, g.n, idx)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    ref = oracle.backproject(echo.cpu().numpy(), scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
+                             scn.gate_half_angle, workers=workers, rx_vel=vel)
+    r, ph = oracle.rel_l2(got, ref), oracle.phase_error_mrad(got, ref)
+    log(f"motion: {ms:.3f} ms/step, image kernel {kms:.3f} ms ({kms / forward_kernel_ms:.2f}x stop-and-hop), "
+        f"rel_l2 {r:.2e}, max phase {ph:.3f} mrad on {sample} pixels, status {status}")
+    plan.destroy()
+    return {"model": "receivers moving during reception (exact FP64 centre root, per-pixel Newton step)",
+            "ms_per_step": ms, "image_kernel_ms": kms, "useful_updates_per_s": useful / (kms * 1e-3),
+            "vs_stop_and_hop_kernel": kms / forward_kernel_ms, "rel_l2": r, "max_phase_mrad": ph,
+            "sample_pixels": sample, "status": status}
+
+
 def drc_leg(api, plan, image: torch.Tensor, steps: int, warmup: int) -> dict:
     """Dynamic range compression of the operational image (16.7 M pixels) for
     display at brightness 0.3: time, HBM bytes the algorithm moves (the image
@@ -476,6 +514,7 @@ def main() -> int:
     ap.add_argument("--no-tvg", action="store_true")
     ap.add_argument("--no-whiten", action="store_true")
     ap.add_argument("--no-rangec", action="store_true")
+    ap.add_argument("--no-motion", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
     ap.add_argument("--profile-leg", choices=["rangec", "tvg", "drc", "whiten"], default=None,
                     help="with --profile, also run this one leg")
@@ -489,7 +528,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
-        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = args.no_rangec = True
+        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = args.no_rangec = args.no_motion = True
         if args.profile_leg:
             setattr(args, "no_" + args.profile_leg, False)
 
@@ -595,6 +634,8 @@ def main() -> int:
         out["range_compression"] = rangec_leg(api, plan, echo, scn.fs, 3)
     if not args.no_sinc:
         out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
+    if not args.no_motion:
+        out["motion"] = motion_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_reprojection:
         out["reprojection"] = reprojection_leg(api, plan, buf, useful, max(3, args.steps // 4), 1, kernel_ms)
     if not args.no_volume:
