@@ -12,7 +12,9 @@ navigation and the sound speed, and of its linear adjoint with respect to the
 echo (reprojection), and of the dynamic range compression applied to the
 image for display (Eqs. 11-12) and of the time-varying gain and spectral
 whitening applied to the echoes (Eqs. 9-10) and of the range compression
-that produces them (the matched filter with Eq. 1's waveform q). It shares no code with the HIP path.
+that produces them (the matched filter with Eq. 1's waveform q), and of the
+time-delay estimation between consecutive pings that feeds the DPC motion
+estimate (Sec. II-D). It shares no code with the HIP path.
 """
 from .tdbp import (pixel_points, backproject, backproject_image, gated_term_count,
                    gated_term_count_rows, vjp, vjp_segment_bound, reproject, sharpness,
@@ -22,8 +24,9 @@ from .drc import drc
 from .tvg import tvg
 from .whiten import whiten
 from .rangec import range_compress
+from . import dpc
 
 __all__ = ["pixel_points", "backproject", "backproject_image", "gated_term_count",
            "gated_term_count_rows", "vjp", "vjp_segment_bound", "reproject", "sharpness",
            "sharpness_cotangent", "sinc_kernel", "SINC_HALF", "motion_delay",
-           "rel_l2", "phase_error_mrad", "drc", "tvg", "whiten", "range_compress"]
+           "rel_l2", "phase_error_mrad", "drc", "tvg", "whiten", "range_compress", "dpc"]
