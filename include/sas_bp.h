@@ -234,6 +234,29 @@ int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, doubl
 int sas_bp_range_compress(sas_bp_plan_t plan, int swath, void* echo, const void* replica, int32_t n_taps,
                           int mix, void* stream);
 
+/* Time-delay estimation between consecutive pings for the displaced-phase-
+ * centre motion estimate (Sec. II-D: the measured delay of Eq. 4 from
+ * overlapped coherent looks of the seafloor). For every ping pair (i, i + 1)
+ * and window k (samples [k hop, k hop + win), K = (N_s - win) / hop + 1
+ * windows, reference time t0 + (k hop + win / 2) / f_s), with the n_pairs
+ * element pairs (e1 of ping i, e2 of ping i + 1) whose phase centres overlap:
+ *   r(l) = sum_j sum_n echo[i][e1_j][n] conj(echo[i + 1][e2_j][n + l]),
+ *          |l| <= max_lag, samples outside the record read zero;
+ *   l* = first maximum of |r| over |l| < max_lag; mu = (m_- - m_+) /
+ *   (2 (m_- - 2 m_0 + m_+)) from |r| at l* - 1, l*, l* + 1 (0 on a flat top);
+ *   out[i][k] = { (l* + mu) / f_s  (coarse delay of ping i + 1 after ping i, s),
+ *                 arg of the quadratic interpolation of r at l* + mu (rad; for a
+ *                 common return delayed by delta it is 2 pi f_c delta mod 2 pi),
+ *                 rho = |r(l*)| / sqrt(sum |a|^2 sum |b(l*)|^2),  l* }.
+ * echo: complex64 [P][E][N_s] with the swath's sizes (device, 8-byte aligned);
+ * pairs: host int32 [n_pairs][2], 1 <= n_pairs <= 256, elements in [0, E);
+ * 2 <= win <= min(2048, N_s); hop >= 1; 1 <= max_lag <= 64; out: device float
+ * [P - 1][K][4], 16-byte aligned. Correlations accumulate in FP32, the peak
+ * step is FP64. The plan keeps a 2 KiB pair buffer and pinned staging (the
+ * caller's pairs array may be reused on return). Asynchronous on `stream`. */
+int sas_bp_dpc_tde(sas_bp_plan_t plan, int swath, const void* echo, const int32_t* pairs, int n_pairs,
+                   int32_t win, int32_t hop, int32_t max_lag, float* out, void* stream);
+
 /* Spectral whitening of swath `swath`'s echo cube, in place (Eq. 9, Sec.
  * II-E): with X the DFT of each (ping, element) row of N_s samples, the power
  * estimate P^(f) = mean over rows of |X(f)|^2 and the power gain

@@ -12,6 +12,7 @@ import dataclasses
 import math
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _native as N
@@ -233,6 +234,25 @@ def sas_bp_range_compress(plan: Plan, swath: int, echo: torch.Tensor, replica: t
     check(N.lib().sas_bp_range_compress(plan.handle, int(swath), echo.data_ptr(), replica.data_ptr(),
                                         int(replica.shape[0]), 1 if mix else 0, _stream(plan.device, stream)),
           "sas_bp_range_compress")
+
+
+def sas_bp_dpc_tde(plan: Plan, swath: int, echo: torch.Tensor, pairs, win: int, hop: int, max_lag: int,
+                   out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Time-delay estimation between consecutive pings over element pairs
+    [(e1 of ping i, e2 of ping i + 1), ...]: returns float32 [P - 1, K, 4]
+    (coarse delay s, phase rad, rho, peak lag) per ping pair and window."""
+    d = plan.descs[swath]
+    _need(echo, "echo", torch.complex64, (d.n_ping, d.n_elem, d.n_sample), plan.device)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    K = (d.n_sample - int(win)) // int(hop) + 1 if d.n_sample >= int(win) and int(hop) > 0 else 0
+    if out is None:
+        out = torch.empty((max(d.n_ping - 1, 0), max(K, 0), 4), dtype=torch.float32, device=echo.device)
+    else:
+        _need(out, "out", torch.float32, (d.n_ping - 1, K, 4), plan.device)
+    check(N.lib().sas_bp_dpc_tde(plan.handle, int(swath), echo.data_ptr(), pr.ctypes.data, int(pr.shape[0]),
+                                 int(win), int(hop), int(max_lag), out.data_ptr(), _stream(plan.device, stream)),
+          "sas_bp_dpc_tde")
+    return out
 
 
 def sas_bp_tvg(plan: Plan, swath: int, echo: torch.Tensor, alpha: float,

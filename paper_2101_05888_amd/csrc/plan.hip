@@ -62,6 +62,10 @@ int launch_whiten(void* fft_plan, void* echo, long long rows, int Ns, double gam
 int make_fft_plan(int Ns, long long rows, void** out);
 void destroy_fft_plan(void* p);
 int rc_transform_length(long long n);
+int tde_max_lag();
+size_t tde_lds_bytes(int W, int L);
+hipError_t launch_dpc_tde(const void* echo, int P, int E, int Ns, const int* pairs, int J, int W, int hop, int L,
+                          double fs, float* out, hipStream_t st);
 int rc_fused_taps();
 int launch_range_compress_fused(void* echo, long long rows, int Ns, const void* replica, int M, double fc, double t0,
                                 double fs, int apply_mix, void* filt, void* tw, void* mixtab, void* energy,
@@ -161,6 +165,9 @@ struct sas_bp_plan_s {
     void* small = nullptr;             // filter (L), twiddles, mix table (N_s), replica energy
     size_t small_bytes = 0;
   } rc;
+  int* tde_pairs = nullptr;            // time-delay estimation: element pairs on the device (kMaxTdePairs)
+  int* tde_pairs_host = nullptr;       // pinned staging for them
+  hipEvent_t tde_copied = nullptr;     // the last staging copy has been consumed
   std::vector<SwathPlan> sw;
   Layout lay{};
   unsigned char* slab = nullptr;
@@ -517,6 +524,12 @@ void release(sas_bp_plan_s* p) {
   destroy_fft_plan(p->rc.single);
   if (p->rc.buf) (void)hipFree(p->rc.buf);
   if (p->rc.small) (void)hipFree(p->rc.small);
+  if (p->tde_copied) {
+    (void)hipEventSynchronize(p->tde_copied);
+    (void)hipEventDestroy(p->tde_copied);
+  }
+  if (p->tde_pairs) (void)hipFree(p->tde_pairs);
+  if (p->tde_pairs_host) (void)hipHostFree(p->tde_pairs_host);
   if (p->slab) (void)hipFree(p->slab);
   (void)hipSetDevice(cur);
   delete p;
@@ -1006,6 +1019,47 @@ int sas_bp_range_compress(sas_bp_plan_t p, int swath, void* echo, const void* re
   const int r = launch_range_compress(rc.batch, rc.single, echo, rows, d.n_sample, L, (int)B, replica, n_taps, d.f_c,
                                       d.t0, d.f_s, mix ? 1 : 0, rc.buf, sm, sm + mix_off, sm + eq_off, st);
   if (r) return fail(SAS_BP_EDEVICE, "range compression failed (%s)", r == 2 ? "FFT" : r == 1 ? "FFT stream" : "kernel");
+  return SAS_BP_OK;
+}
+
+int sas_bp_dpc_tde(sas_bp_plan_t p, int swath, const void* echo, const int32_t* pairs, int n_pairs, int32_t win,
+                   int32_t hop, int32_t max_lag, float* out, void* stream) {
+  constexpr int kMaxTdePairs = 256;
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  if (swath < 0 || swath >= p->n_swaths) return fail(SAS_BP_EINVAL, "swath %d out of range", swath);
+  if (!echo || !pairs || !out) return fail(SAS_BP_EINVAL, "echo, pairs or out is NULL");
+  if (((uintptr_t)echo & 7u) || ((uintptr_t)out & 15u)) return fail(SAS_BP_EINVAL, "echo or out misaligned");
+  const auto& d = p->sw[swath].d;
+  if (d.echo_dtype != SAS_BP_ECHO_C64) return fail(SAS_BP_EUNSUPPORTED, "time-delay estimation reads complex64 echoes");
+  if (d.n_ping < 2 || d.n_ping - 1 > 65535) return fail(SAS_BP_EUNSUPPORTED, "need 2..65536 pings, got %d", d.n_ping);
+  if (n_pairs < 1 || n_pairs > kMaxTdePairs) return fail(SAS_BP_EINVAL, "n_pairs must lie in [1, %d]", kMaxTdePairs);
+  if (win < 2 || win > 2048 || win > d.n_sample) return fail(SAS_BP_EINVAL, "win must lie in [2, min(2048, N_s)]");
+  if (hop < 1) return fail(SAS_BP_EINVAL, "hop must be >= 1");
+  if (max_lag < 1 || max_lag > tde_max_lag()) return fail(SAS_BP_EINVAL, "max_lag must lie in [1, %d]", tde_max_lag());
+  for (int j = 0; j < n_pairs; ++j)
+    if (pairs[2 * j] < 0 || pairs[2 * j] >= d.n_elem || pairs[2 * j + 1] < 0 || pairs[2 * j + 1] >= d.n_elem)
+      return fail(SAS_BP_EINVAL, "pair %d names an element outside [0, %d)", j, d.n_elem);
+  DeviceGuard guard(p->device);
+  if (!p->tde_pairs) {
+    if (hipMalloc(&p->tde_pairs, sizeof(int) * 2 * kMaxTdePairs) != hipSuccess) {
+      p->tde_pairs = nullptr;
+      return fail(SAS_BP_ENOMEM, "time-delay estimation pair buffer could not be allocated");
+    }
+    if (hipHostMalloc(&p->tde_pairs_host, sizeof(int) * 2 * kMaxTdePairs) != hipSuccess) {
+      p->tde_pairs_host = nullptr;
+      return fail(SAS_BP_ENOMEM, "time-delay estimation staging buffer could not be allocated");
+    }
+    HIP_TRY(hipEventCreateWithFlags(&p->tde_copied, hipEventDisableTiming));
+  } else {
+    HIP_TRY(hipEventSynchronize(p->tde_copied));   // the previous call's copy has left the staging buffer
+  }
+  std::memcpy(p->tde_pairs_host, pairs, sizeof(int) * 2 * n_pairs);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(p->tde_pairs, p->tde_pairs_host, sizeof(int) * 2 * n_pairs, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(p->tde_copied, st));
+  HIP_TRY(launch_dpc_tde(echo, d.n_ping, d.n_elem, d.n_sample, p->tde_pairs, n_pairs, win, hop, max_lag, d.f_s, out,
+                         st));
   return SAS_BP_OK;
 }
 
