@@ -381,6 +381,35 @@ def rangec_leg(api, plan, echo: torch.Tensor, fs: float, steps: int) -> dict:
             "hbm_peak_frac": moved / (ms * 1e-3) / 8e12}
 
 
+def dpc_tde_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
+    """Time-delay estimation between consecutive pings of the operational cube
+    for the DPC motion estimate: 16 element pairs (e + 16 of ping i, e of ping
+    i + 1: the phase centres that coincide after the 0.3 m advance), 128-sample
+    windows every 64 samples, lags to +-16: 511 ping pairs x 255 windows.
+    Algorithmic bytes: both looks of every window read once."""
+    pairs = [(e + 16, e) for e in range(16)]
+    out = api.sas_bp_dpc_tde(plan, 0, echo, pairs, 128, 64, 16)   # warm-up (also allocates the pair buffer)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        api.sas_bp_dpc_tde(plan, 0, echo, pairs, 128, 64, 16, out=out)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    P1, K = out.shape[0], out.shape[1]
+    macs = P1 * K * len(pairs) * 128 * 33
+    moved = P1 * K * len(pairs) * (128 + 128 + 32) * 8
+    sig = (out[..., 2] > 0.2).sum().item()
+    log(f"dpc tde: {ms:.3f} ms for {P1 * K} windows ({sig} with rho > 0.2), "
+        f"{macs * 8 / (ms * 1e-3) / 1e12:.1f} TFLOP/s of correlation, {moved / (ms * 1e-3) / 1e9:.0f} GB/s")
+    return {"ping_pairs": P1, "windows": int(P1 * K), "element_pairs": len(pairs), "window": 128, "hop": 64,
+            "max_lag": 16, "ms": ms, "windows_per_s": P1 * K / (ms * 1e-3),
+            "correlation_tflops": macs * 8 / (ms * 1e-3) / 1e12, "algorithmic_bytes": moved,
+            "gb_per_s": moved / (ms * 1e-3) / 1e9, "windows_rho_above_0.2": int(sig)}
+
+
 def volume_leg(api, steps: int, warmup: int) -> dict:
     """The 3D workload at full size: 256 pings x 64 receivers (32 across x 2
     along), 8192 samples, 512 x 512 x 128 voxels at 2 cm, no gate. The seabed
@@ -515,8 +544,9 @@ def main() -> int:
     ap.add_argument("--no-whiten", action="store_true")
     ap.add_argument("--no-rangec", action="store_true")
     ap.add_argument("--no-motion", action="store_true")
+    ap.add_argument("--no-dpc", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
-    ap.add_argument("--profile-leg", choices=["rangec", "tvg", "drc", "whiten"], default=None,
+    ap.add_argument("--profile-leg", choices=["rangec", "tvg", "drc", "whiten", "dpc"], default=None,
                     help="with --profile, also run this one leg")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -528,7 +558,7 @@ def main() -> int:
         return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
-        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = args.no_rangec = args.no_motion = True
+        args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = args.no_rangec = args.no_motion = args.no_dpc = True
         if args.profile_leg:
             setattr(args, "no_" + args.profile_leg, False)
 
@@ -632,6 +662,8 @@ def main() -> int:
         out["whiten"] = whiten_leg(api, plan, echo, 3)
     if not args.no_rangec:
         out["range_compression"] = rangec_leg(api, plan, echo, scn.fs, 3)
+    if not args.no_dpc:
+        out["dpc_tde"] = dpc_tde_leg(api, plan, echo, 3)
     if not args.no_sinc:
         out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_motion:
