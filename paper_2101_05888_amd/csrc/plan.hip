@@ -63,7 +63,7 @@ int make_fft_plan(int Ns, long long rows, void** out);
 void destroy_fft_plan(void* p);
 int rc_transform_length(long long n);
 int tde_max_lag();
-size_t tde_lds_bytes(int W, int L);
+size_t tde_lds_bytes(int W, int L, int J);
 hipError_t launch_dpc_tde(const void* echo, int P, int E, int Ns, const int* pairs, int J, int W, int hop, int L,
                           double fs, float* out, hipStream_t st);
 int rc_fused_taps();

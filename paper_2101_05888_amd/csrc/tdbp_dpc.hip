@@ -3,16 +3,18 @@
 // overlapped coherent looks of the seafloor; coarse delay from quadratic
 // interpolation of the correlation magnitude, phase at the interpolated point).
 //
-// One workgroup per (window k, ping pair i). For each of the J element pairs
-// (e1 of ping i, e2 of ping i + 1) the window a = echo[i][e1][n0, n0 + W) and
-// the lag-extended window b = echo[i + 1][e2][n0 - L, n0 + W + L) (zero outside
-// the record) go to LDS; wave w accumulates the lags w, w + 4, ...:
-//     r(l) += sum_n a[n] conj(b[n + l]),  eb(l) += sum_n |b[n + l]|^2
-// (lanes split n, then a wave reduction), in FP32. The peak search, the
-// quadratic step mu = (m_- - m_+) / (2 (m_- - 2 m_0 + m_+)) (0 on a flat top),
-// the complex correlation at l* + mu and rho = |r(l*)| / sqrt(ea eb(l*)) are
-// then formed in FP64 by one thread. The peak is the first maximum of |r| over
-// |l| < L (both neighbours exist).
+// One workgroup per (window k, ping pair i). The element pairs go through LDS
+// in groups of G: for each pair j of a group, the window a = echo[i][e1][n0,
+// n0 + W) and the lag-extended window b = echo[i + 1][e2][n0 - L, n0 + W + L)
+// (zero outside the record). One thread owns a (pair, block of kTdeBlock
+// lags) and forms its full sums in registers, sliding a window of b values
+// along n (two LDS reads per sample for kTdeBlock lags):
+//     r(l) = sum_n a[n] conj(b[n + l]),  eb(l) = sum_n |b[n + l]|^2   (FP32)
+// then the group's partial sums are added over pairs, per lag, in pair order.
+// The peak search, the quadratic step mu = (m_- - m_+) / (2 (m_- - 2 m_0 +
+// m_+)) (0 on a flat top), the complex correlation at l* + mu and rho =
+// |r(l*)| / sqrt(ea eb(l*)) are then formed in FP64 by one thread. The peak
+// is the first maximum of |r| over |l| < L (both neighbours exist).
 #include "tdbp_dev.h"
 
 namespace sasbp {
@@ -20,70 +22,111 @@ namespace sasbp {
 constexpr int kTdeThreads = 256;
 constexpr int kTdeMaxLag = 64;
 constexpr int kTdeMaxLags = 2 * kTdeMaxLag + 1;
+constexpr int kTdeBlock = 4;             // lags per thread
+constexpr int kTdeLdsTarget = 24576;     // bytes of looks per group (several workgroups per CU)
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Pairs per LDS group for windows of W samples and lags to +-L.
+__host__ __device__ inline int tde_group(int W, int L, int J) {
+  const int per = (2 * W + 2 * L + kTdeBlock) * 8 + (2 * L + 1) * 12;
+  int g = kTdeLdsTarget / per;
+  g = g < 1 ? 1 : g;
+  return g < J ? g : J;
 }
 
 __global__ __launch_bounds__(kTdeThreads) void dpc_tde_kernel(const float2* __restrict__ echo, int E, int Ns,
                                                               const int2* __restrict__ pairs, int J, int W, int hop,
                                                               int L, double fs, float4* __restrict__ out, int K) {
-  extern __shared__ float2 tde_lds[];
+  extern __shared__ __align__(16) unsigned char tde_lds[];
   __shared__ float2 r_acc[kTdeMaxLags];
   __shared__ float eb_acc[kTdeMaxLags];
-  __shared__ float ea_part[kTdeThreads / 64];
+  __shared__ float ea_acc;
   const int k = blockIdx.x, i = blockIdx.y;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x;
   const int NL = 2 * L + 1;
+  const int NB = (NL + kTdeBlock - 1) / kTdeBlock;
+  const int WB = W + 2 * L + kTdeBlock;   // b window with zero tail for the last lag block
   const int n0 = k * hop;
-  float2* sa = tde_lds;
-  float2* sb = tde_lds + W;
+  const int G = tde_group(W, L, J);
+  float2* sa = reinterpret_cast<float2*>(tde_lds);            // [G][W]
+  float2* sb = sa + (size_t)G * W;                            // [G][WB]
+  float2* pr_r = sb + (size_t)G * WB;                         // [G][NL]
+  float* pr_e = reinterpret_cast<float*>(pr_r + (size_t)G * NL);   // [G][NL]
   for (int li = t; li < NL; li += kTdeThreads) {
     r_acc[li] = make_float2(0.0f, 0.0f);
     eb_acc[li] = 0.0f;
   }
-  float ea = 0.0f;
-  for (int j = 0; j < J; ++j) {
-    __syncthreads();   // the previous pair's LDS reads are done (and the accumulators cleared)
-    const int2 pr = pairs[j];
-    const float2* ra = echo + ((size_t)i * E + pr.x) * (size_t)Ns;
-    const float2* rb = echo + ((size_t)(i + 1) * E + pr.y) * (size_t)Ns;
-    for (int n = t; n < W; n += kTdeThreads) {
-      const float2 v = ra[n0 + n];
-      sa[n] = v;
-      ea = fmaf(v.x, v.x, fmaf(v.y, v.y, ea));
-    }
-    for (int m = t; m < W + 2 * L; m += kTdeThreads) {
-      const int idx = n0 - L + m;
-      sb[m] = (idx >= 0 && idx < Ns) ? rb[idx] : make_float2(0.0f, 0.0f);
+  if (t == 0) ea_acc = 0.0f;
+  for (int g0 = 0; g0 < J; g0 += G) {
+    const int gJ = min(G, J - g0);
+    __syncthreads();   // the previous group's LDS reads are done (and the accumulators cleared)
+    for (int j = 0; j < gJ; ++j) {
+      const int2 pr = pairs[g0 + j];
+      const float2* ra = echo + ((size_t)i * E + pr.x) * (size_t)Ns;
+      const float2* rb = echo + ((size_t)(i + 1) * E + pr.y) * (size_t)Ns;
+      for (int n = t; n < W; n += kTdeThreads) sa[j * W + n] = ra[n0 + n];
+      for (int m = t; m < WB; m += kTdeThreads) {
+        const int idx = n0 - L + m;
+        sb[j * WB + m] = (m < W + 2 * L && idx >= 0 && idx < Ns) ? rb[idx] : make_float2(0.0f, 0.0f);
+      }
     }
     __syncthreads();
-    for (int li = wave; li < NL; li += kTdeThreads / 64) {
-      float re = 0.0f, im = 0.0f, e = 0.0f;
-      for (int n = lane; n < W; n += 64) {
-        const float2 a = sa[n], b = sb[n + li];
-        re = fmaf(a.x, b.x, fmaf(a.y, b.y, re));
-        im = fmaf(a.y, b.x, fmaf(-a.x, b.y, im));
-        e = fmaf(b.x, b.x, fmaf(b.y, b.y, e));
+    if (t < 64) {   // window energy of this group's first looks, one wave, pair order
+      float e = 0.0f;
+      for (int j = 0; j < gJ; ++j)
+        for (int n = t; n < W; n += 64) {
+          const float2 v = sa[j * W + n];
+          e = fmaf(v.x, v.x, fmaf(v.y, v.y, e));
+        }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
+      if (t == 0) ea_acc += e;
+    }
+    for (int it = t; it < gJ * NB; it += kTdeThreads) {
+      const int j = it / NB, l0 = (it - j * NB) * kTdeBlock;
+      const float2* a = sa + j * W;
+      const float2* b = sb + j * WB + l0;
+      float re[kTdeBlock], im[kTdeBlock], en[kTdeBlock];
+      float2 bw[kTdeBlock];
+#pragma unroll
+      for (int r = 0; r < kTdeBlock; ++r) {
+        re[r] = im[r] = en[r] = 0.0f;
+        bw[r] = b[r];
       }
-      re = wave_sum(re);
-      im = wave_sum(im);
-      e = wave_sum(e);
-      if (lane == 0) {
-        r_acc[li].x += re;
-        r_acc[li].y += im;
-        eb_acc[li] += e;
+      for (int n = 0; n < W; ++n) {
+        const float2 av = a[n];
+#pragma unroll
+        for (int r = 0; r < kTdeBlock; ++r) {   // a[n] conj(b[n + l])
+          re[r] = fmaf(av.x, bw[r].x, fmaf(av.y, bw[r].y, re[r]));
+          im[r] = fmaf(av.y, bw[r].x, fmaf(-av.x, bw[r].y, im[r]));
+          en[r] = fmaf(bw[r].x, bw[r].x, fmaf(bw[r].y, bw[r].y, en[r]));
+        }
+#pragma unroll
+        for (int r = 0; r < kTdeBlock - 1; ++r) bw[r] = bw[r + 1];
+        bw[kTdeBlock - 1] = b[n + kTdeBlock];
       }
+#pragma unroll
+      for (int r = 0; r < kTdeBlock; ++r)
+        if (l0 + r < NL) {
+          pr_r[j * NL + l0 + r] = make_float2(re[r], im[r]);
+          pr_e[j * NL + l0 + r] = en[r];
+        }
+    }
+    __syncthreads();
+    for (int li = t; li < NL; li += kTdeThreads) {
+      float2 racc = r_acc[li];
+      float eacc = eb_acc[li];
+      for (int j = 0; j < gJ; ++j) {
+        racc.x += pr_r[j * NL + li].x;
+        racc.y += pr_r[j * NL + li].y;
+        eacc += pr_e[j * NL + li];
+      }
+      r_acc[li] = racc;
+      eb_acc[li] = eacc;
     }
   }
-  ea = wave_sum(ea);
-  if (lane == 0) ea_part[wave] = ea;
   __syncthreads();
   if (t == 0) {
-    double ea_tot = 0.0;
-    for (int w = 0; w < kTdeThreads / 64; ++w) ea_tot += (double)ea_part[w];
+    const double ea_tot = (double)ea_acc;
     int ic = 1;
     double best = -1.0;
     for (int li = 1; li < NL - 1; ++li) {
@@ -110,12 +153,15 @@ __global__ __launch_bounds__(kTdeThreads) void dpc_tde_kernel(const float2* __re
 
 int tde_max_lag() { return kTdeMaxLag; }
 
-size_t tde_lds_bytes(int W, int L) { return sizeof(float2) * (size_t)(2 * W + 2 * L); }
+size_t tde_lds_bytes(int W, int L, int J) {
+  const int G = tde_group(W, L, J);
+  return (size_t)G * ((size_t)(2 * W + 2 * L + kTdeBlock) * 8 + (size_t)(2 * L + 1) * 12);
+}
 
 hipError_t launch_dpc_tde(const void* echo, int P, int E, int Ns, const int* pairs, int J, int W, int hop, int L,
                           double fs, float* out, hipStream_t st) {
   const int K = (Ns - W) / hop + 1;
-  hipLaunchKernelGGL(dpc_tde_kernel, dim3((unsigned)K, (unsigned)(P - 1)), dim3(kTdeThreads), tde_lds_bytes(W, L), st,
+  hipLaunchKernelGGL(dpc_tde_kernel, dim3((unsigned)K, (unsigned)(P - 1)), dim3(kTdeThreads), tde_lds_bytes(W, L, J), st,
                      reinterpret_cast<const float2*>(echo), E, Ns, reinterpret_cast<const int2*>(pairs), J, W, hop,
                      L, fs, reinterpret_cast<float4*>(out), K);
   return hipGetLastError();
