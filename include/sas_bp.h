@@ -257,6 +257,63 @@ int sas_bp_range_compress(sas_bp_plan_t plan, int swath, void* echo, const void*
 int sas_bp_dpc_tde(sas_bp_plan_t plan, int swath, const void* echo, const int32_t* pairs, int n_pairs,
                    int32_t win, int32_t hop, int32_t max_lag, float* out, void* stream);
 
+/* Motion estimate of Sec. II-D from the measured delays (Eqs. 3-8): the
+ * per-ping sway and heave velocities v_y, v_z (the surge v_x is known)
+ * minimising L = sum w h(g / sigma) + lambda_smooth sum (v'')^2 +
+ * lambda_dvl sum (z_i - z_DVL[i])^2, with the Eq. 4 residual of ping pair i
+ * and window k
+ *   g = c^-1 mean_j (|TX_i - p_s| + |p_s - RX_i,e1j(t_k)| - |TX_i+1 - p_s| - |p_s - RX_i+1,e2j(t_k)|) + delay,
+ * positions integrated from the velocities, p_i(0) = p0 + sum_{n<i} v_n dt_n,
+ * moving on during reception (p_i(t) = p_i(0) + v_i t), TX = p + lever_tx,
+ * RX_e = p + lever_rx[e] (fixed attitude), z_i = p_z,i(0), h the square
+ * (robust = 0, Eq. 5) or the Huber function of Eq. 3 (robust = 1). */
+typedef struct {
+    int32_t n_ping;        /* P, 2..65536 (the solve: 2..4096)                  */
+    int32_t n_window;      /* K >= 1 windows per ping pair                      */
+    int32_t n_pairs;       /* J, 1..256 element pairs (e1 of ping i, e2 of ping i + 1) */
+    int32_t n_elem;        /* elements with lever arms                          */
+    int32_t robust;        /* 0: h(a) = a^2; 1: Huber (Eq. 3)                   */
+    int32_t max_iter;      /* Levenberg-Marquardt iterations, 1..1000           */
+    double c;              /* sound speed, m/s                                  */
+    double sigma;          /* residual scale, s (> 0)                           */
+    double lambda_smooth;  /* Eq. 6 weight (>= 0)                               */
+    double lambda_dvl;     /* Eq. 7 weight (>= 0)                               */
+    double p0[3];          /* platform position at ping 0's transmission        */
+    double lever_tx[3];    /* transmitter lever arm                             */
+} sas_bp_dpc_desc;
+
+/* Footprints p_s [P-1][K][3] (host) from a nominal navigation (host vel_nominal
+ * [P][3], dt [P-1]): for ping pair i the point of the flat seafloor z = z_floor
+ * abeam (same x) of the pairs' mean phase centre of ping i on the look side
+ * (look = +1: +y, -1: -y) whose two-way time from it is t_ref[k]. Host only. */
+int sas_bp_dpc_footprints(const sas_bp_dpc_desc* desc, const double* vel_nominal, const double* dt,
+                          const double* lever_rx, const int32_t* pairs, const double* t_ref, double z_floor,
+                          double look, double* out);
+
+/* The Eq. 4 residual of every (ping pair, window) and its derivatives, FP64
+ * on the GPU: rows[i][k][7] = { g, dg/dP_i (y, z), dg/dv_i (y, z), dg/dv_i+1
+ * (y, z) } with P_i ping i's position (dg/dv_n = dt_n dg/dP_i for n < i), and
+ * pos_out [P][3] the integrated positions. All pointers are device memory:
+ * vel [P][3], dt [P-1], lever_rx [E][3], pairs int32 [J][2], t_ref [K],
+ * footprint [P-1][K][3], delay [P-1][K]. Asynchronous on `stream`. */
+int sas_bp_dpc_residual(const sas_bp_dpc_desc* desc, const double* vel, const double* dt, const double* lever_rx,
+                        const int32_t* pairs, const double* t_ref, const double* footprint, const double* delay,
+                        double* pos_out, double* rows, void* stream);
+
+/* Levenberg-Marquardt solve of the motion estimate (host arrays: vx [P], dt
+ * [P-1], lever_rx [E][3], pairs [J][2], t_ref [K], footprint [P-1][K][3],
+ * delay and weight [P-1][K], z_dvl [P]; vyz [P][2] holds the start and
+ * receives the solution; *loss_out (optional) the final L). Residuals and
+ * Jacobians on the GPU of `device` each pass; the normal equations, built from
+ * per-pair sums (the integration makes dg/dv_n = dt_n dg/dP_i for every
+ * n < i), and a dense Cholesky solve on the host; the Huber case by iteratively
+ * reweighted least squares. Damping starts at 1e-3 (x1/3 on success, x4 on a
+ * rejected step, 10 tries); stops on no improvement or a step below 1e-12 of
+ * the solution. Synchronous; allocates and frees its device workspace. */
+int sas_bp_dpc_solve(const sas_bp_dpc_desc* desc, const double* vx, const double* dt, const double* lever_rx,
+                     const int32_t* pairs, const double* t_ref, const double* footprint, const double* delay,
+                     const double* weight, const double* z_dvl, double* vyz, double* loss_out, int device);
+
 /* Spectral whitening of swath `swath`'s echo cube, in place (Eq. 9, Sec.
  * II-E): with X the DFT of each (ping, element) row of N_s samples, the power
  * estimate P^(f) = mean over rows of |X(f)|^2 and the power gain

@@ -242,9 +242,9 @@ def solve(vyz0, vx, p0, dt, lever_tx, lever_rx, pairs, t_ref, ps, delay, c, weig
                         lam1, lam2, z_dvl, robust)
     cur = L(x)
     for _ in range(iters):
-        if robust:   # IRLS weights of the Huber function at the current residuals
+        if robust:   # IRLS: h'(a) = omega a, so sqrt(w omega / 2) a has the gradient of w h(a)
             g = residuals(x.reshape(-1, 2), vx, p0, dt, lever_tx, lever_rx, pairs, t_ref, ps, delay, c) / sigma
-            wi = w * np.where(np.abs(g) <= 1.0, 1.0, 1.0 / np.maximum(np.abs(g), 1e-300))
+            wi = 0.5 * w * np.where(np.abs(g) <= 1.0, 1.0, 1.0 / np.maximum(np.abs(g), 1e-300))
         else:
             wi = w
         ws = np.sqrt(wi).ravel()

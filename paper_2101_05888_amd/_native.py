@@ -19,7 +19,8 @@ INTERP_LINEAR, INTERP_SINC8 = 0, 1
 EXPORTED = (
     "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image", "sas_bp_adjoint", "sas_bp_reproject",
     "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_drc", "sas_bp_tvg", "sas_bp_whiten",
-    "sas_bp_range_compress", "sas_bp_dpc_tde", "sas_bp_plan_status", "sas_bp_plan_info",
+    "sas_bp_range_compress", "sas_bp_dpc_tde", "sas_bp_dpc_footprints", "sas_bp_dpc_residual",
+    "sas_bp_dpc_solve", "sas_bp_plan_status", "sas_bp_plan_info",
     "sas_bp_autotune", "sas_bp_set_kernel_timing", "sas_bp_kernel_time", "sas_bp_destroy", "sas_bp_error_string",
     "sas_bp_last_error_detail", "sas_bp_abi_version",
 )
@@ -40,6 +41,15 @@ class Options(C.Structure):
         ("device", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
         ("pings_per_chunk", C.c_int32), ("threads", C.c_int32), ("use_graph", C.c_int32),
         ("elems_per_chunk", C.c_int32), ("workspace_limit", C.c_size_t),
+    ]
+
+
+class DpcDesc(C.Structure):
+    _fields_ = [
+        ("n_ping", C.c_int32), ("n_window", C.c_int32), ("n_pairs", C.c_int32), ("n_elem", C.c_int32),
+        ("robust", C.c_int32), ("max_iter", C.c_int32), ("c", C.c_double), ("sigma", C.c_double),
+        ("lambda_smooth", C.c_double), ("lambda_dvl", C.c_double), ("p0", C.c_double * 3),
+        ("lever_tx", C.c_double * 3),
     ]
 
 
@@ -67,6 +77,10 @@ def _load():
     lib.sas_bp_whiten.argtypes = [P, C.c_int, P, C.c_double, P]
     lib.sas_bp_range_compress.argtypes = [P, C.c_int, P, P, C.c_int32, C.c_int, P]
     lib.sas_bp_dpc_tde.argtypes = [P, C.c_int, P, P, C.c_int, C.c_int32, C.c_int32, C.c_int32, P, P]
+    DP = C.POINTER(DpcDesc)
+    lib.sas_bp_dpc_footprints.argtypes = [DP, P, P, P, P, P, C.c_double, C.c_double, P]
+    lib.sas_bp_dpc_residual.argtypes = [DP, P, P, P, P, P, P, P, P, P, P]
+    lib.sas_bp_dpc_solve.argtypes = [DP, P, P, P, P, P, P, P, P, P, P, P, C.c_int]
     lib.sas_bp_useful_updates.argtypes = [P, C.POINTER(SwathIO), C.c_int, P, C.POINTER(C.c_int64)]
     lib.sas_bp_sharpness.argtypes = [P, P, C.c_int64, P, P, P]
     lib.sas_bp_plan_status.argtypes = [P]

@@ -255,6 +255,80 @@ def sas_bp_dpc_tde(plan: Plan, swath: int, echo: torch.Tensor, pairs, win: int, 
     return out
 
 
+def dpc_desc(n_ping: int, n_window: int, n_pairs: int, n_elem: int, c: float, sigma: float = 1e-7,
+             lambda_smooth: float = 0.0, lambda_dvl: float = 0.0, p0=(0.0, 0.0, 0.0), lever_tx=(0.0, 0.0, 0.0),
+             robust: bool = False, max_iter: int = 30) -> N.DpcDesc:
+    """Descriptor of a motion estimate (see ``sas_bp_dpc_desc`` in the header)."""
+    d = N.DpcDesc()
+    d.n_ping, d.n_window, d.n_pairs, d.n_elem = int(n_ping), int(n_window), int(n_pairs), int(n_elem)
+    d.robust, d.max_iter = 1 if robust else 0, int(max_iter)
+    d.c, d.sigma, d.lambda_smooth, d.lambda_dvl = float(c), float(sigma), float(lambda_smooth), float(lambda_dvl)
+    for a in range(3):
+        d.p0[a] = float(p0[a])
+        d.lever_tx[a] = float(lever_tx[a])
+    return d
+
+
+def _host(a, dtype, shape, name):
+    a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    if a.shape != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {a.shape}")
+    return a
+
+
+def sas_bp_dpc_footprints(desc: N.DpcDesc, vel_nominal, dt, lever_rx, pairs, t_ref, z_floor: float,
+                          look: float = 1.0) -> np.ndarray:
+    """Footprints [P - 1, K, 3] of every ping pair and window (host)."""
+    P, K, J, E = desc.n_ping, desc.n_window, desc.n_pairs, desc.n_elem
+    v = _host(vel_nominal, np.float64, (P, 3), "vel_nominal")
+    d = _host(dt, np.float64, (P - 1,), "dt")
+    lr = _host(lever_rx, np.float64, (E, 3), "lever_rx")
+    pr = _host(pairs, np.int32, (J, 2), "pairs")
+    t = _host(t_ref, np.float64, (K,), "t_ref")
+    out = np.empty((P - 1, K, 3), dtype=np.float64)
+    check(N.lib().sas_bp_dpc_footprints(C.byref(desc), v.ctypes.data, d.ctypes.data, lr.ctypes.data, pr.ctypes.data,
+                                        t.ctypes.data, float(z_floor), float(look), out.ctypes.data),
+          "sas_bp_dpc_footprints")
+    return out
+
+
+def sas_bp_dpc_residual(desc: N.DpcDesc, vel, dt, lever_rx, pairs, t_ref, footprint, delay, device: int = 0,
+                        stream=None):
+    """Eq. 4 residuals and derivatives on the GPU: returns (positions [P, 3],
+    rows [P - 1, K, 7]) as float64 device tensors."""
+    P, K, J, E = desc.n_ping, desc.n_window, desc.n_pairs, desc.n_elem
+    dev = torch.device("cuda", device)
+    f64 = dict(dtype=torch.float64, device=dev)
+    ins = [torch.as_tensor(np.ascontiguousarray(x), **f64) for x in
+           (_host(vel, np.float64, (P, 3), "vel"), _host(dt, np.float64, (P - 1,), "dt"),
+            _host(lever_rx, np.float64, (E, 3), "lever_rx"), _host(t_ref, np.float64, (K,), "t_ref"),
+            _host(footprint, np.float64, (P - 1, K, 3), "footprint"), _host(delay, np.float64, (P - 1, K), "delay"))]
+    pr = torch.as_tensor(_host(pairs, np.int32, (J, 2), "pairs"), device=dev)
+    pos = torch.empty((P, 3), **f64)
+    rows = torch.empty((P - 1, K, 7), **f64)
+    check(N.lib().sas_bp_dpc_residual(C.byref(desc), ins[0].data_ptr(), ins[1].data_ptr(), ins[2].data_ptr(),
+                                      pr.data_ptr(), ins[3].data_ptr(), ins[4].data_ptr(), ins[5].data_ptr(),
+                                      pos.data_ptr(), rows.data_ptr(), _stream(device, stream)),
+          "sas_bp_dpc_residual")
+    return pos, rows
+
+
+def sas_bp_dpc_solve(desc: N.DpcDesc, vx, dt, lever_rx, pairs, t_ref, footprint, delay, weight, z_dvl, vyz0,
+                     device: int = 0):
+    """Levenberg-Marquardt motion estimate: returns (vyz [P, 2], final loss)."""
+    P, K, J, E = desc.n_ping, desc.n_window, desc.n_pairs, desc.n_elem
+    a = [_host(vx, np.float64, (P,), "vx"), _host(dt, np.float64, (P - 1,), "dt"),
+         _host(lever_rx, np.float64, (E, 3), "lever_rx"), _host(pairs, np.int32, (J, 2), "pairs"),
+         _host(t_ref, np.float64, (K,), "t_ref"), _host(footprint, np.float64, (P - 1, K, 3), "footprint"),
+         _host(delay, np.float64, (P - 1, K), "delay"), _host(weight, np.float64, (P - 1, K), "weight"),
+         _host(z_dvl, np.float64, (P,), "z_dvl")]
+    v = _host(vyz0, np.float64, (P, 2), "vyz0").copy()
+    loss = C.c_double(0.0)
+    check(N.lib().sas_bp_dpc_solve(C.byref(desc), *[x.ctypes.data for x in a], v.ctypes.data, C.byref(loss),
+                                   int(device)), "sas_bp_dpc_solve")
+    return v, loss.value
+
+
 def sas_bp_tvg(plan: Plan, swath: int, echo: torch.Tensor, alpha: float,
                gain_out: Optional[torch.Tensor] = None, stream=None) -> None:
     """Time-varying gain of a complex64 echo cube [P, E, N_s], in place;

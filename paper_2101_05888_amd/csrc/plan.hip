@@ -63,6 +63,11 @@ int make_fft_plan(int Ns, long long rows, void** out);
 void destroy_fft_plan(void* p);
 int rc_transform_length(long long n);
 int tde_max_lag();
+hipError_t launch_dpc_residual(int P, int K, int J, const double* pos, const double* vel, const double* dt,
+                               const double* lever_tx, const double* lever_rx, const int* pairs, const double* t_ref,
+                               const double* ps, const double* delay, double c, double* rows, hipStream_t st);
+hipError_t launch_dpc_positions(int P, const double* vel, const double* dt, const double* p0, double* pos,
+                                hipStream_t st);
 size_t tde_lds_bytes(int W, int L, int J);
 hipError_t launch_dpc_tde(const void* echo, int P, int E, int Ns, const int* pairs, int J, int W, int hop, int L,
                           double fs, float* out, hipStream_t st);
@@ -593,6 +598,353 @@ int log2_bucket(long long v) {
 }
 
 }  // namespace
+
+namespace {
+
+int check_dpc_desc(const sas_bp_dpc_desc* d) {
+  if (!d) return fail(SAS_BP_EINVAL, "desc is NULL");
+  if (d->n_ping < 2 || d->n_ping > 65536) return fail(SAS_BP_EINVAL, "n_ping must lie in [2, 65536]");
+  if (d->n_window < 1) return fail(SAS_BP_EINVAL, "n_window must be >= 1");
+  if (d->n_pairs < 1 || d->n_pairs > 256) return fail(SAS_BP_EINVAL, "n_pairs must lie in [1, 256]");
+  if (d->n_elem < 1 || d->n_elem > kMaxElem) return fail(SAS_BP_EINVAL, "n_elem must lie in [1, %d]", kMaxElem);
+  if (!(d->c > 0.0) || !finite(d->c)) return fail(SAS_BP_EINVAL, "c must be > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!finite(d->p0[a]) || !finite(d->lever_tx[a])) return fail(SAS_BP_EINVAL, "p0 and lever_tx must be finite");
+  return SAS_BP_OK;
+}
+
+// Dense Cholesky solve of A x = b (A symmetric positive definite, n x n, row
+// major, overwritten by its factor). Returns false if A is not positive definite.
+bool cholesky_solve(std::vector<double>& A, std::vector<double>& b, int n) {
+  for (int j = 0; j < n; ++j) {
+    double* rj = &A[(size_t)j * n];
+    double djj = rj[j];
+    for (int k = 0; k < j; ++k) djj -= rj[k] * rj[k];
+    if (!(djj > 0.0)) return false;
+    djj = std::sqrt(djj);
+    rj[j] = djj;
+    const double inv = 1.0 / djj;
+    for (int i = j + 1; i < n; ++i) {
+      double* ri = &A[(size_t)i * n];
+      double v = ri[j];
+      for (int k = 0; k < j; ++k) v -= ri[k] * rj[k];
+      ri[j] = v * inv;
+    }
+  }
+  for (int i = 0; i < n; ++i) {   // L y = b
+    const double* ri = &A[(size_t)i * n];
+    double v = b[i];
+    for (int k = 0; k < i; ++k) v -= ri[k] * b[k];
+    b[i] = v / ri[i];
+  }
+  for (int i = n - 1; i >= 0; --i) {   // L^T x = y
+    double v = b[i];
+    for (int k = i + 1; k < n; ++k) v -= A[(size_t)k * n + i] * b[k];
+    b[i] = v / A[(size_t)i * n + i];
+  }
+  return true;
+}
+
+double huber(double a) {
+  a = std::fabs(a);
+  return a <= 1.0 ? 0.5 * a * a : a - 0.5;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sas_bp_dpc_footprints(const sas_bp_dpc_desc* d, const double* vel_nominal, const double* dt,
+                          const double* lever_rx, const int32_t* pairs, const double* t_ref, double z_floor,
+                          double look, double* out) {
+  int rc = check_dpc_desc(d);
+  if (rc) return rc;
+  if (!vel_nominal || !dt || !lever_rx || !pairs || !t_ref || !out) return fail(SAS_BP_EINVAL, "NULL argument");
+  if (look != 1.0 && look != -1.0) return fail(SAS_BP_EINVAL, "look must be +1 or -1");
+  const int P = d->n_ping, K = d->n_window, J = d->n_pairs;
+  double pc_off[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < J; ++j) {
+    const int e = pairs[2 * j];
+    if (e < 0 || e >= d->n_elem) return fail(SAS_BP_EINVAL, "pair %d names an element outside [0, %d)", j, d->n_elem);
+    for (int a = 0; a < 3; ++a) pc_off[a] += lever_rx[3 * e + a];
+  }
+  for (int a = 0; a < 3; ++a) pc_off[a] = 0.5 * (d->lever_tx[a] + pc_off[a] / J);
+  double pos[3] = {d->p0[0], d->p0[1], d->p0[2]};
+  for (int i = 0; i < P - 1; ++i) {
+    const double pc[3] = {pos[0] + pc_off[0], pos[1] + pc_off[1], pos[2] + pc_off[2]};
+    for (int k = 0; k < K; ++k) {
+      const double slant = 0.5 * d->c * t_ref[k], dz = z_floor - pc[2];
+      const double ground = std::sqrt(std::max(slant * slant - dz * dz, 0.0));
+      double* o = out + ((size_t)i * K + k) * 3;
+      o[0] = pc[0];
+      o[1] = pc[1] + look * ground;
+      o[2] = z_floor;
+    }
+    for (int a = 0; a < 3; ++a) pos[a] += vel_nominal[3 * i + a] * dt[i];
+  }
+  return SAS_BP_OK;
+}
+
+int sas_bp_dpc_residual(const sas_bp_dpc_desc* d, const double* vel, const double* dt, const double* lever_rx,
+                        const int32_t* pairs, const double* t_ref, const double* footprint, const double* delay,
+                        double* pos_out, double* rows, void* stream) {
+  int rc = check_dpc_desc(d);
+  if (rc) return rc;
+  if (!vel || !dt || !lever_rx || !pairs || !t_ref || !footprint || !delay || !pos_out || !rows)
+    return fail(SAS_BP_EINVAL, "NULL argument");
+  (void)hipGetLastError();
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HIP_TRY(launch_dpc_positions(d->n_ping, vel, dt, d->p0, pos_out, st));
+  HIP_TRY(launch_dpc_residual(d->n_ping, d->n_window, d->n_pairs, pos_out, vel, dt, d->lever_tx, lever_rx, pairs,
+                              t_ref, footprint, delay, d->c, rows, st));
+  return SAS_BP_OK;
+}
+
+int sas_bp_dpc_solve(const sas_bp_dpc_desc* d, const double* vx, const double* dt, const double* lever_rx,
+                     const int32_t* pairs, const double* t_ref, const double* footprint, const double* delay,
+                     const double* weight, const double* z_dvl, double* vyz, double* loss_out, int device) {
+  int rc = check_dpc_desc(d);
+  if (rc) return rc;
+  if (!vx || !dt || !lever_rx || !pairs || !t_ref || !footprint || !delay || !weight || !z_dvl || !vyz)
+    return fail(SAS_BP_EINVAL, "NULL argument");
+  if (d->n_ping > 4096) return fail(SAS_BP_EUNSUPPORTED, "the dense normal equations are built for <= 4096 pings");
+  if (!(d->sigma > 0.0) || !(d->lambda_smooth >= 0.0) || !(d->lambda_dvl >= 0.0))
+    return fail(SAS_BP_EINVAL, "sigma must be > 0 and the regularisation weights >= 0");
+  if (d->max_iter < 1 || d->max_iter > 1000) return fail(SAS_BP_EINVAL, "max_iter must lie in [1, 1000]");
+  for (int j = 0; j < 2 * d->n_pairs; ++j)
+    if (pairs[j] < 0 || pairs[j] >= d->n_elem) return fail(SAS_BP_EINVAL, "a pair names an element outside [0, %d)",
+                                                          d->n_elem);
+  const int P = d->n_ping, K = d->n_window, J = d->n_pairs, n = 2 * P;
+  const size_t R = (size_t)(P - 1) * K;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (hipSetDevice(device) != hipSuccess) return fail(SAS_BP_EINVAL, "device %d not available", device);
+  (void)hipGetLastError();
+  // device copies of the fixed inputs; velocities, positions and rows per pass
+  const size_t b_vel = sizeof(double) * 3 * P, b_dt = sizeof(double) * (P - 1), b_lr = sizeof(double) * 3 * d->n_elem;
+  const size_t b_pairs = sizeof(int) * 2 * J, b_t = sizeof(double) * K, b_ps = sizeof(double) * 3 * R;
+  const size_t b_del = sizeof(double) * R, b_rows = sizeof(double) * 7 * R;
+  const size_t offs[] = {0, b_vel, b_dt, b_lr, b_pairs, b_t, b_ps, b_del, b_vel, b_rows};
+  size_t total = 0, at[10];
+  for (int q = 0; q < 10; ++q) {
+    total = align_up(total + offs[q]);
+    at[q] = total;
+  }
+  unsigned char* buf = nullptr;
+  if (hipMalloc(&buf, total + kAlign) != hipSuccess) {
+    (void)hipSetDevice(cur);
+    return fail(SAS_BP_ENOMEM, "motion-estimate workspace of %zu bytes could not be allocated", total);
+  }
+  double* g_vel = reinterpret_cast<double*>(buf + at[0]);
+  double* g_dt = reinterpret_cast<double*>(buf + at[1]);
+  double* g_lr = reinterpret_cast<double*>(buf + at[2]);
+  int* g_pairs = reinterpret_cast<int*>(buf + at[3]);
+  double* g_t = reinterpret_cast<double*>(buf + at[4]);
+  double* g_ps = reinterpret_cast<double*>(buf + at[5]);
+  double* g_del = reinterpret_cast<double*>(buf + at[6]);
+  double* g_pos = reinterpret_cast<double*>(buf + at[7]);
+  double* g_rows = reinterpret_cast<double*>(buf + at[8]);
+  int status = SAS_BP_OK;
+  std::vector<double> vel(3 * P), rows(7 * R), x(n), N((size_t)n * n), grad(n), step(n);
+  for (int i = 0; i < P; ++i) {
+    x[2 * i] = vyz[2 * i];
+    x[2 * i + 1] = vyz[2 * i + 1];
+  }
+  auto evaluate = [&](const std::vector<double>& xv, bool want_rows, double* loss) -> bool {
+    for (int i = 0; i < P; ++i) {
+      vel[3 * i] = vx[i];
+      vel[3 * i + 1] = xv[2 * i];
+      vel[3 * i + 2] = xv[2 * i + 1];
+    }
+    if (hipMemcpy(g_vel, vel.data(), b_vel, hipMemcpyHostToDevice) != hipSuccess) return false;
+    if (launch_dpc_positions(P, g_vel, g_dt, d->p0, g_pos, nullptr) != hipSuccess) return false;
+    if (launch_dpc_residual(P, K, J, g_pos, g_vel, g_dt, d->lever_tx, g_lr, g_pairs, g_t, g_ps, g_del, d->c, g_rows,
+                            nullptr) != hipSuccess)
+      return false;
+    if (hipMemcpy(rows.data(), g_rows, b_rows, hipMemcpyDeviceToHost) != hipSuccess) return false;
+    double L = 0.0;
+    for (size_t r = 0; r < R; ++r) {
+      const double a = rows[7 * r] / d->sigma;
+      L += weight[r] * (d->robust ? huber(a) : a * a);
+    }
+    for (int i = 1; i + 1 < P; ++i)
+      for (int c = 0; c < 2; ++c) {
+        const double sv = xv[2 * (i - 1) + c] - 2.0 * xv[2 * i + c] + xv[2 * (i + 1) + c];
+        L += d->lambda_smooth * sv * sv;
+      }
+    double z = d->p0[2];
+    for (int i = 0; i < P; ++i) {
+      const double dv = z - z_dvl[i];
+      L += d->lambda_dvl * dv * dv;
+      if (i + 1 < P) z += xv[2 * i + 1] * dt[i];
+    }
+    (void)want_rows;
+    *loss = L;
+    return true;
+  };
+  do {
+    if (hipMemcpy(g_dt, dt, b_dt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g_lr, lever_rx, b_lr, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g_pairs, pairs, b_pairs, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g_t, t_ref, b_t, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g_ps, footprint, b_ps, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(g_del, delay, b_del, hipMemcpyHostToDevice) != hipSuccess) {
+      status = fail(SAS_BP_EDEVICE, "upload of the motion-estimate inputs failed");
+      break;
+    }
+    double cur_loss = 0.0;
+    if (!evaluate(x, true, &cur_loss)) {
+      status = fail(SAS_BP_EDEVICE, "residual pass failed");
+      break;
+    }
+    double lam = 1e-3;
+    std::vector<double> Saa(4 * (P - 1)), Sab(4 * (P - 1)), Sac(4 * (P - 1)), Sbb(4 * (P - 1)), Sbc(4 * (P - 1)),
+        Scc(4 * (P - 1)), Ga(2 * (P - 1)), Gb(2 * (P - 1)), Gc(2 * (P - 1)), Taa(4 * P), Tga(2 * P);
+    for (int it = 0; it < d->max_iter; ++it) {
+      // weighted normal equations of the stacked residuals at x (rows hold the current pass)
+      std::fill(Saa.begin(), Saa.end(), 0.0);
+      std::fill(Sab.begin(), Sab.end(), 0.0);
+      std::fill(Sac.begin(), Sac.end(), 0.0);
+      std::fill(Sbb.begin(), Sbb.end(), 0.0);
+      std::fill(Sbc.begin(), Sbc.end(), 0.0);
+      std::fill(Scc.begin(), Scc.end(), 0.0);
+      std::fill(Ga.begin(), Ga.end(), 0.0);
+      std::fill(Gb.begin(), Gb.end(), 0.0);
+      std::fill(Gc.begin(), Gc.end(), 0.0);
+      for (int i = 0; i < P - 1; ++i)
+        for (int k = 0; k < K; ++k) {
+          const double* o = &rows[7 * ((size_t)i * K + k)];
+          const double a = o[0] / d->sigma;
+          double om = weight[(size_t)i * K + k];
+          if (d->robust) om *= 0.5 * (std::fabs(a) <= 1.0 ? 1.0 : 1.0 / std::fabs(a));
+          const double f = om / (d->sigma * d->sigma), gr = om * a / d->sigma;
+          const double va[2] = {o[1], o[2]}, vb[2] = {o[3], o[4]}, vc[2] = {o[5], o[6]};
+          for (int p = 0; p < 2; ++p) {
+            for (int q = 0; q < 2; ++q) {
+              Saa[4 * i + 2 * p + q] += f * va[p] * va[q];
+              Sab[4 * i + 2 * p + q] += f * va[p] * vb[q];
+              Sac[4 * i + 2 * p + q] += f * va[p] * vc[q];
+              Sbb[4 * i + 2 * p + q] += f * vb[p] * vb[q];
+              Sbc[4 * i + 2 * p + q] += f * vb[p] * vc[q];
+              Scc[4 * i + 2 * p + q] += f * vc[p] * vc[q];
+            }
+            Ga[2 * i + p] += gr * va[p];
+            Gb[2 * i + p] += gr * vb[p];
+            Gc[2 * i + p] += gr * vc[p];
+          }
+        }
+      // suffix sums over pairs i > m: Taa[m] = sum Saa[i], Tga[m] = sum Ga[i]
+      std::fill(Taa.begin(), Taa.end(), 0.0);
+      std::fill(Tga.begin(), Tga.end(), 0.0);
+      for (int m = P - 2; m >= 0; --m)
+        for (int q = 0; q < 4; ++q) Taa[4 * m + q] = Taa[4 * (m + 1) + q] + (m + 1 < P - 1 ? Saa[4 * (m + 1) + q] : 0.0);
+      for (int m = P - 2; m >= 0; --m)
+        for (int q = 0; q < 2; ++q) Tga[2 * m + q] = Tga[2 * (m + 1) + q] + (m + 1 < P - 1 ? Ga[2 * (m + 1) + q] : 0.0);
+      std::fill(N.begin(), N.end(), 0.0);
+      auto add = [&](int nb, int mb, int p, int q, double v) { N[(size_t)(2 * nb + p) * n + 2 * mb + q] += v; };
+      for (int m = 0; m < P; ++m)
+        for (int nb = 0; nb <= m; ++nb)
+          for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) {
+              double v = 0.0;
+              if (m < P - 1 && nb < P - 1) v += dt[nb] * dt[m] * Taa[4 * m + 2 * p + q];   // pairs i > m
+              if (nb < m && m < P - 1) v += dt[nb] * Sab[4 * m + 2 * p + q];                 // pair i = m
+              if (m >= 1 && nb < m - 1) v += dt[nb] * Sac[4 * (m - 1) + 2 * p + q];          // pair i = m - 1
+              if (m >= 1 && nb == m - 1) v += Sbc[4 * (m - 1) + 2 * p + q];
+              if (nb == m) {
+                if (m < P - 1) v += Sbb[4 * m + 2 * p + q];
+                if (m >= 1) v += Scc[4 * (m - 1) + 2 * p + q];
+              }
+              add(nb, m, p, q, v);
+            }
+      for (int nb = 0; nb < P; ++nb)
+        for (int p = 0; p < 2; ++p) {
+          double v = 0.0;
+          if (nb < P - 1) v += dt[nb] * Tga[2 * nb + p] + Gb[2 * nb + p];
+          if (nb >= 1) v += Gc[2 * (nb - 1) + p];
+          grad[2 * nb + p] = v;
+        }
+      // the DPC part was built on the upper block triangle: mirror it
+      for (int m = 0; m < P; ++m)
+        for (int nb = 0; nb < m; ++nb)
+          for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) N[(size_t)(2 * m + q) * n + 2 * nb + p] = N[(size_t)(2 * nb + p) * n + 2 * m + q];
+      // Eq. 6: lambda_1 (v[i-1] - 2 v[i] + v[i+1])^2 per component
+      const double cf[3] = {1.0, -2.0, 1.0};
+      for (int i = 1; i + 1 < P; ++i)
+        for (int c = 0; c < 2; ++c) {
+          const double sv = x[2 * (i - 1) + c] - 2.0 * x[2 * i + c] + x[2 * (i + 1) + c];
+          for (int u = 0; u < 3; ++u) {
+            grad[2 * (i - 1 + u) + c] += d->lambda_smooth * cf[u] * sv;
+            for (int w = 0; w < 3; ++w) add(i - 1 + u, i - 1 + w, c, c, d->lambda_smooth * cf[u] * cf[w]);
+          }
+        }
+      // Eq. 7: lambda_2 (z_i - z_DVL[i])^2, dz_i / dv_z[n] = dt_n for n < i
+      {
+        std::vector<double> dres(P), tail(P + 1, 0.0);
+        double z = d->p0[2];
+        for (int i = 0; i < P; ++i) {
+          dres[i] = z - z_dvl[i];
+          if (i + 1 < P) z += x[2 * i + 1] * dt[i];
+        }
+        for (int i = P - 1; i >= 0; --i) tail[i] = tail[i + 1] + dres[i];
+        for (int nb = 0; nb < P - 1; ++nb) {
+          grad[2 * nb + 1] += d->lambda_dvl * dt[nb] * tail[nb + 1];
+          for (int m = 0; m < P - 1; ++m)
+            add(nb, m, 1, 1, d->lambda_dvl * dt[nb] * dt[m] * (double)(P - 1 - std::max(nb, m)));
+        }
+      }
+      bool improved = false;
+      double snorm = 0.0, xnorm = 0.0;
+      for (int tries = 0; tries < 10; ++tries) {
+        std::vector<double> A(N), rhs(n);
+        for (int q = 0; q < n; ++q) {
+          A[(size_t)q * n + q] += lam * (N[(size_t)q * n + q] + 1e-12);
+          rhs[q] = -grad[q];
+        }
+        if (!cholesky_solve(A, rhs, n)) {
+          lam *= 4.0;
+          continue;
+        }
+        std::vector<double> xt(n);
+        snorm = 0.0;
+        xnorm = 0.0;
+        for (int q = 0; q < n; ++q) {
+          xt[q] = x[q] + rhs[q];
+          snorm += rhs[q] * rhs[q];
+          xnorm += x[q] * x[q];
+        }
+        double tl = 0.0;
+        if (!evaluate(xt, true, &tl)) {
+          status = fail(SAS_BP_EDEVICE, "residual pass failed");
+          break;
+        }
+        if (tl < cur_loss) {
+          x = xt;
+          cur_loss = tl;
+          lam = std::max(lam / 3.0, 1e-12);
+          improved = true;
+          break;
+        }
+        lam *= 4.0;
+      }
+      if (status != SAS_BP_OK) break;
+      if (!improved) {
+        (void)evaluate(x, true, &cur_loss);   // rows of the kept point
+        break;
+      }
+      if (std::sqrt(snorm) < 1e-12 * (1.0 + std::sqrt(xnorm))) break;
+    }
+    if (status != SAS_BP_OK) break;
+    for (int q = 0; q < n; ++q) vyz[q] = x[q];
+    if (loss_out) *loss_out = cur_loss;
+  } while (false);
+  (void)hipFree(buf);
+  (void)hipSetDevice(cur);
+  return status;
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -167,4 +167,109 @@ hipError_t launch_dpc_tde(const void* echo, int P, int E, int Ns, const int* pai
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Motion estimate from the measured delays (Eqs. 3-8, Sec. II-D): the Eq. 4
+// residual of every (ping pair i, window k) and its derivatives, FP64 (the
+// path differences are millimetres of paths tens of metres long). With the
+// ping's platform position P_i = p_0 + sum_{n<i} v_n dt_n, TX = P + l_T and
+// RX_e(t) = P + v t + l_e, and u(X) = (X - p_s) / |X - p_s|:
+//   c J g = sum_j |TX_1 - p_s| + |p_s - RX_1j(t)| - |TX_2 - p_s| - |p_s - RX_2j(t)|  (+ c J delta)
+//   dg/dP_i     = a = sum_j u(TX_1) + u(RX_1j) - u(TX_2) - u(RX_2j)      / (c J)
+//   dg/dv_i     = b = sum_j t u(RX_1j) - dt_i (u(TX_2) + u(RX_2j))      / (c J)
+//   dg/dv_{i+1} = d = -sum_j t u(RX_2j)                                 / (c J)
+// (dg/dv_n = dt_n a for n < i). Output per row: g, a_y, a_z, b_y, b_z, d_y, d_z.
+__global__ __launch_bounds__(kThreads) void dpc_residual_kernel(
+    int P, int K, int J, const double* __restrict__ pos, const double* __restrict__ vel,
+    const double* __restrict__ dt, double ltx, double lty, double ltz, const double* __restrict__ lever_rx,
+    const int2* __restrict__ pairs, const double* __restrict__ t_ref, const double* __restrict__ ps,
+    const double* __restrict__ delay, double c, double* __restrict__ rows) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (long long)(P - 1) * K) return;
+  const int i = (int)(r / K), k = (int)(r - (long long)i * K);
+  const double t = t_ref[k];
+  const double* s = ps + (size_t)r * 3;
+  const double* P1 = pos + (size_t)i * 3;
+  const double* P2 = pos + (size_t)(i + 1) * 3;
+  const double* V1 = vel + (size_t)i * 3;
+  const double* V2 = vel + (size_t)(i + 1) * 3;
+  const double dti = dt[i];
+  double tx1[3] = {P1[0] + ltx, P1[1] + lty, P1[2] + ltz};
+  double tx2[3] = {P2[0] + ltx, P2[1] + lty, P2[2] + ltz};
+  double u1[3], u2[3];
+  const double d1 = sqrt((tx1[0] - s[0]) * (tx1[0] - s[0]) + (tx1[1] - s[1]) * (tx1[1] - s[1]) +
+                         (tx1[2] - s[2]) * (tx1[2] - s[2]));
+  const double d2 = sqrt((tx2[0] - s[0]) * (tx2[0] - s[0]) + (tx2[1] - s[1]) * (tx2[1] - s[1]) +
+                         (tx2[2] - s[2]) * (tx2[2] - s[2]));
+  for (int a = 0; a < 3; ++a) {
+    u1[a] = (tx1[a] - s[a]) / d1;
+    u2[a] = (tx2[a] - s[a]) / d2;
+  }
+  double path = 0.0, A[3] = {0.0, 0.0, 0.0}, B[3] = {0.0, 0.0, 0.0}, D[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < J; ++j) {
+    const int2 pr = pairs[j];
+    const double* l1 = lever_rx + (size_t)pr.x * 3;
+    const double* l2 = lever_rx + (size_t)pr.y * 3;
+    double x1[3], x2[3];
+    for (int a = 0; a < 3; ++a) {
+      x1[a] = P1[a] + V1[a] * t + l1[a] - s[a];
+      x2[a] = P2[a] + V2[a] * t + l2[a] - s[a];
+    }
+    const double e1 = sqrt(x1[0] * x1[0] + x1[1] * x1[1] + x1[2] * x1[2]);
+    const double e2 = sqrt(x2[0] * x2[0] + x2[1] * x2[1] + x2[2] * x2[2]);
+    path += (d1 + e1) - (d2 + e2);
+    for (int a = 0; a < 3; ++a) {
+      const double w1 = x1[a] / e1, w2 = x2[a] / e2;
+      A[a] += u1[a] + w1 - u2[a] - w2;
+      B[a] += t * w1 - dti * (u2[a] + w2);
+      D[a] -= t * w2;
+    }
+  }
+  const double f = 1.0 / (c * (double)J);
+  double* o = rows + (size_t)r * 7;
+  o[0] = path * f + delay[r];
+  o[1] = A[1] * f;
+  o[2] = A[2] * f;
+  o[3] = B[1] * f;
+  o[4] = B[2] * f;
+  o[5] = D[1] * f;
+  o[6] = D[2] * f;
+}
+
+hipError_t launch_dpc_residual(int P, int K, int J, const double* pos, const double* vel, const double* dt,
+                               const double* lever_tx, const double* lever_rx, const int* pairs, const double* t_ref,
+                               const double* ps, const double* delay, double c, double* rows, hipStream_t st) {
+  const long long n = (long long)(P - 1) * K;
+  hipLaunchKernelGGL(dpc_residual_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, P,
+                     K, J, pos, vel, dt, lever_tx[0], lever_tx[1], lever_tx[2], lever_rx,
+                     reinterpret_cast<const int2*>(pairs), t_ref, ps, delay, c, rows);
+  return hipGetLastError();
+}
+
+}  // namespace sasbp
+
+namespace sasbp {
+
+// p_i(0) = p_0 + sum_{n<i} v_n dt_n for every ping (one thread, in ping order).
+__global__ void dpc_positions_kernel(int P, const double* __restrict__ vel, const double* __restrict__ dt, double p0x,
+                                     double p0y, double p0z, double* __restrict__ pos) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double x = p0x, y = p0y, z = p0z;
+  for (int i = 0; i < P; ++i) {
+    pos[3 * i] = x;
+    pos[3 * i + 1] = y;
+    pos[3 * i + 2] = z;
+    if (i + 1 < P) {
+      x += vel[3 * i] * dt[i];
+      y += vel[3 * i + 1] * dt[i];
+      z += vel[3 * i + 2] * dt[i];
+    }
+  }
+}
+
+hipError_t launch_dpc_positions(int P, const double* vel, const double* dt, const double* p0, double* pos,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(dpc_positions_kernel, dim3(1), dim3(64), 0, st, P, vel, dt, p0[0], p0[1], p0[2], pos);
+  return hipGetLastError();
+}
+
 }  // namespace sasbp
