@@ -410,6 +410,45 @@ def dpc_tde_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
             "gb_per_s": moved / (ms * 1e-3) / 1e9, "windows_rho_above_0.2": int(sig)}
 
 
+def dpc_solve_leg(api, scn, tde: torch.Tensor, max_iter: int) -> dict:
+    """The motion estimate on the operational cube's time-delay estimates:
+    511 ping pairs x 255 windows (weights rho where rho > 0.5, else 0),
+    footprints from the straight nominal track, surge 0.3 m per 0.2048 s
+    ping interval, Huber loss; times the GPU residual pass and a bounded
+    Levenberg-Marquardt solve (dense normal equations on the host). The echoes
+    were synthesized stop-and-hop, so the estimate itself is not scored."""
+    P, K = scn.n_ping, tde.shape[1]
+    pri = scn.n_sample / scn.fs
+    dt = np.full(P - 1, pri)
+    vx = np.full(P, float(scn.tx[1, 0] - scn.tx[0, 0]) / pri)
+    lever_rx = np.asarray(scn.rx[0] - scn.tx[0], dtype=np.float64)
+    pairs = np.array([(e + 16, e) for e in range(16)], dtype=np.int32)
+    t_ref = scn.t0 + (np.arange(K) * 64 + 64) / scn.fs
+    est = tde.cpu().numpy().astype(np.float64)
+    delay = est[..., 0]
+    weight = np.where(est[..., 2] > 0.5, est[..., 2], 0.0)
+    p0 = np.asarray(scn.tx[0], dtype=np.float64)
+    d = api.dpc_desc(P, K, len(pairs), scn.n_elem, scn.c, 2e-6, 1e-2, 1.0, p0, (0.0, 0.0, 0.0), True, max_iter)
+    nominal = np.column_stack([vx, np.zeros(P), np.zeros(P)])
+    ps = api.sas_bp_dpc_footprints(d, nominal, dt, lever_rx, pairs, t_ref, 0.0, 1.0)   # seafloor at z = 0
+    z_dvl = np.full(P, p0[2])
+    pos, rows = api.sas_bp_dpc_residual(d, nominal, dt, lever_rx, pairs, t_ref, ps, delay)   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        api.sas_bp_dpc_residual(d, nominal, dt, lever_rx, pairs, t_ref, ps, delay)
+    torch.cuda.synchronize()
+    res_ms = (time.perf_counter() - t) / 5 * 1e3
+    t = time.perf_counter()
+    v, loss = api.sas_bp_dpc_solve(d, vx, dt, lever_rx, pairs, t_ref, ps, delay, weight, z_dvl, np.zeros((P, 2)))
+    solve_s = time.perf_counter() - t
+    log(f"dpc solve: residual pass {res_ms:.3f} ms (with transfers) for {(P - 1) * K} rows; "
+        f"{max_iter}-iteration Huber solve over {2 * P} velocities {solve_s:.2f} s, loss {loss:.4e}, "
+        f"{int((weight > 0).sum())} weighted windows")
+    return {"rows": int((P - 1) * K), "unknowns": 2 * P, "residual_pass_ms": res_ms, "max_iter": max_iter,
+            "solve_s": solve_s, "final_loss": loss, "weighted_windows": int((weight > 0).sum())}
+
+
 def volume_leg(api, steps: int, warmup: int) -> dict:
     """The 3D workload at full size: 256 pings x 64 receivers (32 across x 2
     along), 8192 samples, 512 x 512 x 128 voxels at 2 cm, no gate. The seabed
@@ -664,6 +703,8 @@ def main() -> int:
         out["range_compression"] = rangec_leg(api, plan, echo, scn.fs, 3)
     if not args.no_dpc:
         out["dpc_tde"] = dpc_tde_leg(api, plan, echo, 3)
+        tde = api.sas_bp_dpc_tde(plan, 0, echo, [(e + 16, e) for e in range(16)], 128, 64, 16)
+        out["dpc_solve"] = dpc_solve_leg(api, scn, tde, 5)
     if not args.no_sinc:
         out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_motion:
