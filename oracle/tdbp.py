@@ -30,6 +30,17 @@ a = p - R_ie this is the quadratic
 whose larger root is the one with c tau - d_T >= 0 (``motion_delay``). The
 beam gate keeps the ping-time positions.
 
+Sediment refraction (variant of the image; Sec. III-B): the flat seafloor
+z = z_int separates water (c, above; the array is in the water) from sediment
+(c_sed, below). A leg from apex X to a pixel p below the interface crosses it
+where the travel time |X - q| / c + |q - p| / c_sed is least; that point lies in
+the vertical plane through X and p, at horizontal distance r from X where
+Snell's law r / (c |X - q|) = (D - r) / (c_sed |q - p|) holds (D the horizontal
+distance of X and p; the left side grows and the right side falls with r, so
+the root is unique: ``refracted_leg`` brackets it by bisection). Legs to
+pixels at or above the interface are straight. The beam gate keeps straight
+lines.
+
 Gradient (vector-Jacobian product) for a cotangent Gbar = dJ/dRe I + j dJ/dIm I:
 
     dJ/dtheta = sum_p Re( conj(Gbar(p)) * sum_ie g * D_ie(p) * dtau_ie/dtheta )
@@ -113,7 +124,26 @@ def motion_delay(d_T, a, v, c):
     return (Bh + np.sqrt(Bh * Bh - A * (d_T * d_T - aa))) / A
 
 
-def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear", vel=None):
+def refracted_leg(X, pts, c, c_sed, z_int):
+    """One-way travel time from X [3] (in the water) to every point of pts [N, 3]."""
+    X = np.asarray(X, dtype=np.float64)
+    D = np.sqrt((pts[:, 0] - X[0]) ** 2 + (pts[:, 1] - X[1]) ** 2)
+    h1 = z_int - X[2]
+    h2 = pts[:, 2] - z_int
+    below = h2 > 0
+    lo, hi = np.zeros_like(D), D.copy()
+    h2c = np.where(below, h2, 1.0)      # pixels at or above the interface take the straight path below
+    for _ in range(200):
+        r = 0.5 * (lo + hi)
+        f = r / (c * np.sqrt(r * r + h1 * h1)) - (D - r) / (c_sed * np.sqrt((D - r) ** 2 + h2c * h2c))
+        lo = np.where(f < 0, r, lo)
+        hi = np.where(f < 0, hi, r)
+    r = 0.5 * (lo + hi)
+    t = np.sqrt(r * r + h1 * h1) / c + np.sqrt((D - r) ** 2 + h2c * h2c) / c_sed
+    return np.where(below, t, np.sqrt(((pts - X) ** 2).sum(axis=1)) / c)
+
+
+def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear", vel=None, refr=None):
     P, E = rx.shape[0], rx.shape[1]
     acc = np.zeros(pts.shape[0], dtype=np.complex128)
     count = 0
@@ -121,10 +151,14 @@ def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear", vel=None)
     for i in range(P):
         dT = np.sqrt(((pts - tx[i]) ** 2).sum(axis=1))
         gT = _gate(pts[:, 0] - tx[i, 0], dT, sin_g) if sin_g is not None else None
+        tT = None if refr is None else refracted_leg(tx[i], pts, c, refr[0], refr[1])
         for e in range(E):
             R = rx[i, e]
             dR = np.sqrt(((pts - R) ** 2).sum(axis=1))
-            tau = (dT + dR) / c if vel is None else motion_delay(dT, pts - R, vel[i], c)
+            if refr is not None:
+                tau = tT + refracted_leg(R, pts, c, refr[0], refr[1])
+            else:
+                tau = (dT + dR) / c if vel is None else motion_delay(dT, pts - R, vel[i], c)
             u = (tau - t0) * fs
             if interp == "sinc":
                 L = _sinc_interp(echo[i, e], u)
@@ -151,11 +185,11 @@ def _worker(args):
     lo, hi = args
     s = _SHARED
     return _bp_chunk(s["echo"], s["tx"], s["rx"], s["c"], s["fc"], s["fs"], s["t0"],
-                     s["pts"][lo:hi], s["gate"], s["interp"], s["vel"])
+                     s["pts"][lo:hi], s["gate"], s["interp"], s["vel"], s["refr"])
 
 
 def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
-                workers=1, chunk=4096, return_count=False, interp="linear", rx_vel=None):
+                workers=1, chunk=4096, return_count=False, interp="linear", rx_vel=None, refraction=None):
     """Backprojected complex values at arbitrary points [N,3] (float64 in, complex128 out).
 
     echo: complex [P,E,N_s]; tx: [P,3]; rx: [P,E,3]; gate_half_angle in radians
@@ -163,7 +197,8 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
     ``interp`` = "linear" (the definition above) or "sinc": the interpolation
     variant L = sum over the 2 SINC_HALF samples m around u of E~[m] h(u - m),
     h the Hann-windowed sinc of ``sinc_kernel``. ``rx_vel`` ([P, 3], m/s)
-    selects continuous receiver motion (``motion_delay``).
+    selects continuous receiver motion (``motion_delay``); ``refraction``
+    = (c_sed, z_int) the sediment interface (``refracted_leg``).
     """
     echo = np.ascontiguousarray(np.asarray(echo).astype(np.complex128, copy=False))
     tx = np.asarray(tx, dtype=np.float64)
@@ -176,12 +211,13 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
     total = 0
     if workers <= 1 or len(spans) <= 1:
         for lo, hi in spans:
-            v, cnt = _bp_chunk(echo, tx, rx, float(c), fc, fs, t0, pts[lo:hi], gate_half_angle, interp, vel)
+            v, cnt = _bp_chunk(echo, tx, rx, float(c), fc, fs, t0, pts[lo:hi], gate_half_angle, interp, vel,
+                               refraction)
             out[lo:hi] = v
             total += cnt
     else:
         _SHARED.update(echo=echo, tx=tx, rx=rx, c=float(c), fc=fc, fs=fs, t0=t0, pts=pts,
-                       gate=gate_half_angle, interp=interp, vel=vel)
+                       gate=gate_half_angle, interp=interp, vel=vel, refr=refraction)
         ctx = mp.get_context("fork")
         with ctx.Pool(workers) as pool:
             res = pool.map(_worker, spans, chunksize=1)
@@ -193,11 +229,11 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
 
 
 def backproject_image(echo, tx, rx, c, fc, fs, t0, origin, spacing, n, gate_half_angle=0.0,
-                      workers=1, return_count=False, interp="linear", rx_vel=None):
+                      workers=1, return_count=False, interp="linear", rx_vel=None, refraction=None):
     """Full image [nz, ny, nx] complex128 on the grid origin + index * spacing."""
     pts = pixel_points(origin, spacing, n)
     r = backproject(echo, tx, rx, c, fc, fs, t0, pts, gate_half_angle, workers=workers,
-                    return_count=return_count, interp=interp, rx_vel=rx_vel)
+                    return_count=return_count, interp=interp, rx_vel=rx_vel, refraction=refraction)
     nx, ny, nz = (int(v) for v in n)
     if return_count:
         return r[0].reshape(nz, ny, nx), r[1]

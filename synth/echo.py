@@ -15,6 +15,12 @@ reception, R_ie(t) = R_ie + v_i t (t after transmit; the transmitter is
 stationary while it transmits), and tau_s solves
 c tau = |x_s - T_i| + |x_s - R_ie - v_i tau|, found by fixed-point iteration
 (contraction |v| / c). The gate stays that of the ping-time positions.
+With ``refraction = (c_sed, z_int)`` the seafloor z = z_int separates water
+(sound speed c, above) from sediment (c_sed, below): a leg from an apex X
+in the water to a scatterer below the interface crosses it at the point of
+least travel time, found here by golden-section search along the vertical
+plane through both (the travel time is convex there); legs to scatterers at
+or above the interface are straight.
 There is no spherical spreading: time-varying gain is taken as already applied
 (Eq. 10, Sec. II-E). The gate g is the +-theta transmit AND receive cone about
 the broadside plane, the same one the imager applies; g = 1 when no gate.
@@ -42,6 +48,37 @@ def _taper(d: torch.Tensor, half: int) -> torch.Tensor:
     return torch.where(a < half, w, torch.zeros_like(w))
 
 
+def _leg_time(X: torch.Tensor, p: torch.Tensor, c: float, refraction: tuple) -> torch.Tensor:
+    """One-way travel time from X (water) to p across the flat interface
+    z = z_int (golden-section search over the crossing point's horizontal
+    distance r from X along the vertical plane through X and p)."""
+    c_sed, z_int = float(refraction[0]), float(refraction[1])
+    X, p = torch.broadcast_tensors(X, p)
+    D = torch.linalg.norm(p[..., :2] - X[..., :2], dim=-1)
+    h1 = z_int - X[..., 2]
+    h2 = p[..., 2] - z_int
+    below = h2 > 0
+    h2c = torch.clamp(h2, min=0.0)
+    t_of = lambda r: torch.sqrt(r * r + h1 * h1) / c + torch.sqrt((D - r) ** 2 + h2c * h2c) / c_sed
+    lo, hi = torch.zeros_like(D), D.clone()
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    a = hi - g * (hi - lo)
+    b = lo + g * (hi - lo)
+    ta, tb = t_of(a), t_of(b)
+    for _ in range(90):
+        left = ta < tb
+        hi = torch.where(left, b, hi)
+        lo = torch.where(left, lo, a)
+        b_new = torch.where(left, a, lo + g * (hi - lo))
+        a_new = torch.where(left, hi - g * (hi - lo), b)
+        tb_new = torch.where(left, ta, t_of(b_new))
+        ta_new = torch.where(left, t_of(a_new), tb)
+        a, b, ta, tb = a_new, b_new, ta_new, tb_new
+    t_ref = t_of(0.5 * (lo + hi))
+    straight = torch.linalg.norm(p - X, dim=-1) / c
+    return torch.where(below, t_ref, straight)
+
+
 def pulse(d, bandwidth: float, fs: float, half: int):
     """Compressed pulse h(d) at offset d samples from the true delay (numpy or torch)."""
     if isinstance(d, np.ndarray):
@@ -52,7 +89,7 @@ def pulse(d, bandwidth: float, fs: float, half: int):
 def synthesize_echo(scn: Scenario, device="cpu", dtype=torch.complex128,
                     tx: np.ndarray | None = None, rx: np.ndarray | None = None,
                     max_chunk: int = 1 << 22, noise: bool = True, noise_on_device: bool = False,
-                    rx_vel: np.ndarray | None = None) -> torch.Tensor:
+                    rx_vel: np.ndarray | None = None, refraction: tuple | None = None) -> torch.Tensor:
     """Echo cube [P, E, N_s] for the scenario, optionally with its seeded noise.
 
     ``tx``/``rx`` default to the positions the scene was recorded with
@@ -84,6 +121,10 @@ def synthesize_echo(scn: Scenario, device="cpu", dtype=torch.complex128,
         dT = torch.linalg.norm(pos[None, :, :] - T[:, None, :], dim=-1)              # [p,S]
         dR = torch.linalg.norm(pos[None, :, None, :] - R[:, None, :, :], dim=-1)     # [p,S,E]
         tau = (dT[:, :, None] + dR) / scn.c                                           # [p,S,E]
+        if refraction is not None:
+            tT = _leg_time(T[:, None, :], pos[None, :, :], scn.c, refraction)           # [p,S]
+            tR = _leg_time(R[:, None, :, :], pos[None, :, None, :], scn.c, refraction)  # [p,S,E]
+            tau = tT[:, :, None] + tR
         if veld is not None:
             V = veld[i0:i1]                                                           # [p,3]
             rel = pos[None, :, None, :] - R[:, None, :, :]                            # [p,S,E,3]
