@@ -112,6 +112,18 @@ typedef struct {
                                plan share it. A velocity that is not finite, |v| >= c/2,
                                or one that moves a delay by more than one sample across
                                a tile, is reported like bad navigation (SAS_BP_ENAV). */
+    int32_t refract;        /* 1: sediment-water interface refraction in the propagation
+                               time (Sec. III-B): the flat seafloor z = z_interface
+                               separates water (sound speed c, above; the array must be
+                               in the water) from sediment (c_sediment, below); a leg to
+                               a pixel below it crosses at the point of least travel time
+                               (Snell's law), legs to pixels at or above it are straight;
+                               the gate keeps straight lines. Linear interpolation, no
+                               motion, image only; the crossing is found in FP32, the
+                               leg times and the delay are FP64. */
+    int32_t reserved0;      /* 0 */
+    double c_sediment;      /* m/s, > 0 (refract = 1)                             */
+    double z_interface;     /* m, the interface depth (refract = 1)               */
 } sas_bp_swath_desc;
 
 /* Plan options; a NULL options pointer selects every default. */

@@ -32,7 +32,8 @@ class SwathDesc(C.Structure):
         ("n", C.c_int64 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
         ("f_c", C.c_double), ("f_s", C.c_double), ("t0", C.c_double),
         ("gate_half_angle", C.c_double), ("c_min", C.c_double), ("interp", C.c_int32),
-        ("motion", C.c_int32),
+        ("motion", C.c_int32), ("refract", C.c_int32), ("reserved0", C.c_int32), ("c_sediment", C.c_double),
+        ("z_interface", C.c_double),
     ]
 
 

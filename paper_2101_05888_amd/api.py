@@ -25,10 +25,11 @@ INTERPS = {"linear": N.INTERP_LINEAR, "sinc8": N.INTERP_SINC8}
 def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin: Sequence[float],
                spacing: Sequence[float], f_c: float, f_s: float, t0: float = 0.0,
                gate_half_angle: float = 0.0, echo_dtype: str = "c64", c_min: float = 0.0,
-               interp: str = "linear", motion: bool = False) -> N.SwathDesc:
+               interp: str = "linear", motion: bool = False, refraction=None) -> N.SwathDesc:
     """Descriptor of one swath; ``interp`` is "linear" or "sinc8" (the
     Hann-windowed sinc over 8 samples); ``motion`` selects receivers moving
-    during reception (``SwathBuffers.rx_vel``)."""
+    during reception (``SwathBuffers.rx_vel``); ``refraction`` = (c_sediment,
+    z_interface) a sediment-water interface in the propagation time."""
     if interp not in INTERPS:
         raise ValueError(f"interp must be one of {sorted(INTERPS)}")
     d = N.SwathDesc()
@@ -42,6 +43,8 @@ def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin
     d.gate_half_angle, d.c_min = float(gate_half_angle), float(c_min)
     d.interp = INTERPS[interp]
     d.motion = 1 if motion else 0
+    if refraction is not None:
+        d.refract, d.c_sediment, d.z_interface = 1, float(refraction[0]), float(refraction[1])
     return d
 
 

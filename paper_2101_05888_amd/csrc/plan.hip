@@ -45,6 +45,8 @@ hipError_t launch_adjoint(AdjointKernelFn fn, const Workspace& ws, int n_tiles, 
 hipError_t adjoint_occupancy(AdjointKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu);
 hipError_t set_adjoint_lds_limit(AdjointKernelFn fn, int lds_bytes);
 
+typedef void (*RefractKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
+RefractKernelFn refract_kernel_for(int layout, bool gate, int dt);
 typedef void (*ReprojectKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
 ReprojectKernelFn reproject_kernel_for(int layout, bool gate);
 hipError_t launch_reproject(ReprojectKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads,
@@ -149,6 +151,7 @@ struct sas_bp_plan_s {
   int dtype = 0;
   int interp = 0;                  // SAS_BP_INTERP_*, shared by all swaths of the plan
   int motion = 0;                  // continuous receiver motion, shared by all swaths of the plan
+  int refract = 0;                 // sediment refraction, shared by all swaths of the plan
   int bucket_shift = 0;
   int lds_bytes = 0, adj_lds_bytes = 0;
   int grid = 0, adj_grid = 0;
@@ -222,6 +225,11 @@ int validate(const sas_bp_swath_desc* d, int i) {
   if (d->motion != 0 && d->motion != 1) return fail(SAS_BP_EINVAL, "swath %d: motion must be 0 or 1", i);
   if (d->motion && d->interp != SAS_BP_INTERP_LINEAR)
     return fail(SAS_BP_EUNSUPPORTED, "swath %d: continuous motion is built for linear interpolation only", i);
+  if (d->refract != 0 && d->refract != 1) return fail(SAS_BP_EINVAL, "swath %d: refract must be 0 or 1", i);
+  if (d->refract && (d->interp != SAS_BP_INTERP_LINEAR || d->motion))
+    return fail(SAS_BP_EUNSUPPORTED, "swath %d: refraction is built for linear interpolation without motion", i);
+  if (d->refract && (!(d->c_sediment > 0.0) || !finite(d->c_sediment) || !finite(d->z_interface)))
+    return fail(SAS_BP_EINVAL, "swath %d: c_sediment must be > 0 and z_interface finite", i);
   return SAS_BP_OK;
 }
 
@@ -397,6 +405,9 @@ SwathDev make_dev(const SwathPlan& s) {
   v.dtype = s.d.echo_dtype;
   v.interp = s.d.interp;
   v.motion = s.d.motion;
+  v.refract = s.d.refract;
+  v.c_sed = s.d.refract ? s.d.c_sediment : 0.0;
+  v.z_int = s.d.refract ? s.d.z_interface : 0.0;
   v.nx = (int)s.d.n[0];
   v.ny = (int)s.d.n[1];
   v.nz = (int)s.d.n[2];
@@ -1009,6 +1020,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->dtype = sw[0].d.echo_dtype;
   p->interp = sw[0].d.interp;
   p->motion = sw[0].d.motion;
+  p->refract = sw[0].d.refract;
   int max_pe = 1, max_lds = 0, max_adj_lds = 0;
   for (const auto& s : sw) {
     const bool gate = s.d.gate_half_angle > 0.0;
@@ -1025,6 +1037,10 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
       release(p);
       return fail(SAS_BP_EUNSUPPORTED, "all swaths of a plan must share one motion model");
     }
+    if (s.d.refract != p->refract) {
+      release(p);
+      return fail(SAS_BP_EUNSUPPORTED, "all swaths of a plan must share one propagation model");
+    }
     max_pe = std::max(max_pe, s.d.n_ping * s.d.n_elem);
     p->max_p = std::max(p->max_p, s.d.n_ping);
   }
@@ -1038,7 +1054,8 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->bucket_shift = shift;
   p->lds_bytes = max_lds;
   p->adj_lds_bytes = max_adj_lds;
-  p->image_fn = image_kernel_for(t.layout, p->gate_any, p->dtype, p->motion ? 2 : p->interp);
+  p->image_fn = p->refract ? refract_kernel_for(t.layout, p->gate_any, p->dtype)
+                           : image_kernel_for(t.layout, p->gate_any, p->dtype, p->motion ? 2 : p->interp);
   p->adjoint_fn = adjoint_kernel_for(t.layout, p->gate_any, p->dtype);
   p->reproject_fn = reproject_kernel_for(t.layout, p->gate_any);
   if (!p->image_fn || !p->adjoint_fn || !p->reproject_fn) {
@@ -1151,8 +1168,9 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   if (!grad_image || !grad_tx || !grad_rx || !grad_c) return fail(SAS_BP_EINVAL, "gradient array is NULL");
-  if (p->interp != SAS_BP_INTERP_LINEAR || p->motion)
-    return fail(SAS_BP_EUNSUPPORTED, "the adjoint is built for linear interpolation with stop-and-hop positions only");
+  if (p->interp != SAS_BP_INTERP_LINEAR || p->motion || p->refract)
+    return fail(SAS_BP_EUNSUPPORTED, "the adjoint is built for linear interpolation, stop-and-hop positions and "
+                "straight paths only");
   if (!p->adj_ok)
     return fail(SAS_BP_EUNSUPPORTED, "the adjoint stages whole pings and needs %d bytes of LDS with this tiling; "
                 "plan with a smaller tile", p->adj_lds_bytes);
@@ -1219,8 +1237,9 @@ int sas_bp_reproject(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* con
   int rc = check_io(p, io, n_swaths);
   if (rc) return rc;
   if (!image_in || !echo_out) return fail(SAS_BP_EINVAL, "image_in or echo_out is NULL");
-  if (p->interp != SAS_BP_INTERP_LINEAR || p->motion)
-    return fail(SAS_BP_EUNSUPPORTED, "reprojection is built for linear interpolation with stop-and-hop positions only");
+  if (p->interp != SAS_BP_INTERP_LINEAR || p->motion || p->refract)
+    return fail(SAS_BP_EUNSUPPORTED, "reprojection is built for linear interpolation, stop-and-hop positions and "
+                "straight paths only");
   for (int i = 0; i < n_swaths; ++i) {
     if (!image_in[i] || !echo_out[i]) return fail(SAS_BP_EINVAL, "swath %d: NULL image_in or echo_out", i);
     if (((uintptr_t)image_in[i] & 7u) || ((uintptr_t)echo_out[i] & 7u))

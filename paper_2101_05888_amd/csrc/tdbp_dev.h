@@ -51,6 +51,8 @@ struct SwathDev {
   int P, E, Ns, dtype;
   int interp;             // 0 linear, 1 windowed sinc over 2 * kSincHalf samples
   int motion;             // 1: receivers move at vel during reception
+  int refract;            // 1: sediment below z_int refracts the legs (sound speed c_sed)
+  double c_sed, z_int;
   int nx, ny, nz;
   int ntx, nty, ntz;      // tiles per axis
   int tile0;              // index of this swath's first tile in the global tile list

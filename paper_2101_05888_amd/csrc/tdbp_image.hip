@@ -82,7 +82,8 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
         const double uhi = ((dT + dR + 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
         double reach = sw.interp == 1 ? (double)kSincHalf : 0.0;   // taps beyond the delay
         if (sw.motion) reach += vm * (dT + dR + 2.0 * sw.half_diag) / c * sw.fs / c + 1.0;
-        const bool rec_e = (uhi >= -2.0 - reach) && (ulo <= (double)sw.Ns + 1.0 + reach);
+        // refracted legs are not straight: the record test is left to the kernel
+        const bool rec_e = sw.refract || ((uhi >= -2.0 - reach) && (ulo <= (double)sw.Ns + 1.0 + reach));
         const bool gate_e = sw.tan_g > 0.0 ? cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, R) : true;
         in_record |= rec_e && gate_e;
         rx_hit |= gate_e;

@@ -1,0 +1,168 @@
+// Backprojection with sediment-water interface refraction in the propagation
+// time (Sec. III-B: near-field sub-bottom imaging).
+//
+// The flat seafloor z = z_int separates water (sound speed c, above; the array
+// is in the water) from sediment (c_sed, below). A leg from apex X to a pixel p
+// below the interface crosses it at the point of least travel time, in the
+// vertical plane through X and p at horizontal distance r from X, where
+//     f(r) = r / (c a) - (D - r) / (c_sed b) = 0,   a = |(r, h1)|, b = |(D - r, h2)|
+// (Snell's law; D the horizontal distance of X and p, h1 = z_int - X_z,
+// h2 = p_z - z_int). f grows with r, so Newton steps from the straight-line
+// crossing r = D h1 / (h1 + h2), kept inside the bracket [0, D] that the sign
+// of f shrinks, converge; the travel time a / c + b / c_sed is stationary at
+// the root, so a few steps give it to FP32 rounding. Legs to pixels at or above
+// the interface are straight. The beam gate keeps straight lines.
+//
+// Precision: the crossing point by FP32 Newton steps, the leg times, the delay
+// and the carrier phase (reduced to revolutions) in FP64; the interpolation is
+// linear in FP32, the echo read from global memory (L2-resident per tile).
+//
+// Same persistent scheduling as the image kernel: a workgroup takes tiles from
+// the cost-ordered list; lane (lx, ly, lz) owns K pixels of its row, loops over
+// the tile's culled pings and every element, and writes each pixel once.
+#include "tdbp_geom.h"
+
+namespace sasbp {
+
+constexpr int kRefractNewton = 6;   // Newton steps per leg
+
+// One leg's travel time (FP64 result): the crossing distance r by FP32 Newton
+// steps, then the time at r evaluated in FP64 (it is stationary in r, so the
+// FP32 error of r does not reach it).
+__device__ __forceinline__ double refracted_time(double dx, double dy, double dz, double h1, double h2, double inv_c,
+                                                 double inv_cs) {
+  const double D2 = dx * dx + dy * dy;
+  if (!(h2 > 0.0) || !(h1 > 0.0))   // pixel at or above the interface (or apex below it): straight
+    return sqrt(D2 + dz * dz) * inv_c;
+  const double D = sqrt(D2);
+  const float Df = (float)D, h1f = (float)h1, h2f = (float)h2, icf = (float)inv_c, icsf = (float)inv_cs;
+  float lo = 0.0f, hi = Df;
+  float r = Df * h1f / (h1f + h2f);
+#pragma unroll
+  for (int it = 0; it < kRefractNewton; ++it) {
+    const float u = Df - r;
+    const float ia = __builtin_amdgcn_rsqf(fmaf(r, r, h1f * h1f));
+    const float ib = __builtin_amdgcn_rsqf(fmaf(u, u, h2f * h2f));
+    const float f = r * ia * icf - u * ib * icsf;
+    lo = f < 0.0f ? r : lo;
+    hi = f < 0.0f ? hi : r;
+    const float fp = h1f * h1f * ia * ia * ia * icf + h2f * h2f * ib * ib * ib * icsf;
+    float rn = r - f * __builtin_amdgcn_rcpf(fp);
+    rn = (rn >= lo && rn <= hi) ? rn : 0.5f * (lo + hi);   // a converged step may land on the bracket end
+    r = rn;
+  }
+  const double rd = (double)r, ud = D - rd;
+  return sqrt(rd * rd + h1 * h1) * inv_c + sqrt(ud * ud + h2 * h2) * inv_cs;
+}
+
+template <int L, bool GATE, int DT>
+__global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) void refract_kernel(
+    Workspace ws, const SwathDev* __restrict__ swaths, const int* __restrict__ order,
+    const int* __restrict__ tile_swath, const PingRange* __restrict__ prange, int n_tiles) {
+  constexpr int K = kLayouts[L].K, LX = kLayouts[L].LX, LY = kLayouts[L].LY;
+  constexpr int TX = LX * K, TY = LY, TZ = kLayouts[L].LZ;
+  const int tid = threadIdx.x;
+  const int lx = tid % LX, ly = (tid / LX) % LY, lz = tid / (LX * LY);
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_item = (int)atomicAdd(&ws.counters[0], 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    if (item >= n_tiles) break;
+    const int t = __builtin_amdgcn_readfirstlane(order[item]);
+    const int s = __builtin_amdgcn_readfirstlane(tile_swath[t]);
+    const SwathDev& sw = swaths[s];
+    const int lt = t - sw.tile0;
+    const int tix = lt % sw.ntx, tiy = (lt / sw.ntx) % sw.nty, tiz = lt / (sw.ntx * sw.nty);
+    const int iy = tiy * TY + ly, iz = tiz * TZ + lz;
+    const double c = *sw.c;
+    const double inv_c = 1.0 / c, inv_cs = 1.0 / sw.c_sed;
+    const PingRange pr = prange[t];
+    // pixel centres (FP64)
+    double px[K];
+    const double py = sw.o[1] + (double)iy * sw.d[1], pz = sw.o[2] + (double)iz * sw.d[2];
+#pragma unroll
+    for (int k = 0; k < K; ++k) px[k] = sw.o[0] + (double)(tix * TX + lx + LX * k) * sw.d[0];
+    float accr[K], acci[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) { accr[k] = 0.0f; acci[k] = 0.0f; }
+    bool bad = false;
+    for (int p = pr.lo; p <= pr.hi; ++p) {
+      const double* T = sw.tx + (size_t)p * 3;
+      const double Tx = T[0], Ty = T[1], Tz = T[2];
+      bad |= !(finite3(Tx, Ty, Tz));
+      const float scale = sw.dtype == 0 ? 1.0f : sw.scale[p];
+      double tT[K];
+      bool gT[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double dx = px[k] - Tx, dy = py - Ty, dz = pz - Tz;
+        tT[k] = refracted_time(dx, dy, dz, sw.z_int - Tz, pz - sw.z_int, inv_c, inv_cs);
+        gT[k] = true;
+        if (GATE && sw.tan_g > 0.0) gT[k] = fabs(dx) <= sw.sin_g * sqrt(dx * dx + dy * dy + dz * dz);
+      }
+      for (int e = 0; e < sw.E; ++e) {
+        const double* R = sw.rx + ((size_t)p * sw.E + e) * 3;
+        const double Rx = R[0], Ry = R[1], Rz = R[2];
+        bad |= !(finite3(Rx, Ry, Rz));
+        const size_t row = ((size_t)p * sw.E + e) * (size_t)sw.Ns;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double dx = px[k] - Rx, dy = py - Ry, dz = pz - Rz;
+          bool g = gT[k];
+          if (GATE && sw.tan_g > 0.0) g = g && fabs(dx) <= sw.sin_g * sqrt(dx * dx + dy * dy + dz * dz);
+          if (!g) continue;
+          const double tau = tT[k] + refracted_time(dx, dy, dz, sw.z_int - Rz, pz - sw.z_int, inv_c, inv_cs);
+          const double u = (tau - sw.t0) * sw.fs;
+          const double nf = floor(u);
+          const float w = (float)(u - nf);
+          const long long n = (long long)nf;
+          float2 a = make_float2(0.0f, 0.0f), b = make_float2(0.0f, 0.0f);
+          if (n >= 0 && n < sw.Ns) a = load_sample(sw.echo, row + (size_t)n, DT, scale);
+          if (n + 1 >= 0 && n + 1 < sw.Ns) b = load_sample(sw.echo, row + (size_t)(n + 1), DT, scale);
+          const float vr = fmaf(w, b.x - a.x, a.x), vi = fmaf(w, b.y - a.y, a.y);
+          const double cyc_d = sw.fc * tau;
+          const float cyc = (float)(cyc_d - floor(cyc_d));
+          const float sn = __builtin_amdgcn_sinf(cyc), cs = __builtin_amdgcn_cosf(cyc);
+          accr[k] = fmaf(vr, cs, fmaf(-vi, sn, accr[k]));
+          acci[k] = fmaf(vr, sn, fmaf(vi, cs, acci[k]));
+        }
+      }
+    }
+    if (bad) atomicOr(&ws.counters[1], kStatusNav);
+    if (iy < sw.ny && iz < sw.nz) {
+      float2* out = sw.image + ((size_t)iz * sw.ny + iy) * (size_t)sw.nx;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int ix = tix * TX + lx + LX * k;
+        if (ix < sw.nx) out[ix] = bad ? make_float2(0.0f, 0.0f) : make_float2(accr[k], acci[k]);
+      }
+    }
+  }
+}
+
+typedef void (*RefractKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
+
+template <int L>
+static RefractKernelFn refract_for_layout(bool gate, int dt) {
+  if (gate) return dt == 0 ? refract_kernel<L, true, 0> : dt == 1 ? refract_kernel<L, true, 1> : refract_kernel<L, true, 2>;
+  return dt == 0 ? refract_kernel<L, false, 0> : dt == 1 ? refract_kernel<L, false, 1> : refract_kernel<L, false, 2>;
+}
+
+RefractKernelFn refract_kernel_for(int layout, bool gate, int dt) {
+  switch (layout) {
+    case 0: return refract_for_layout<0>(gate, dt);
+    case 1: return refract_for_layout<1>(gate, dt);
+    case 2: return refract_for_layout<2>(gate, dt);
+    case 3: return refract_for_layout<3>(gate, dt);
+    case 4: return refract_for_layout<4>(gate, dt);
+    case 5: return refract_for_layout<5>(gate, dt);
+    case 6: return refract_for_layout<6>(gate, dt);
+    case 7: return refract_for_layout<7>(gate, dt);
+    case 8: return refract_for_layout<8>(gate, dt);
+    default: return nullptr;
+  }
+}
+
+}  // namespace sasbp

@@ -30,10 +30,11 @@ def workers() -> int:
 
 
 def desc_for(api, scn: Scenario, echo_dtype: str = "c64", c_min: float = 0.0, interp: str = "linear",
-             motion: bool = False):
+             motion: bool = False, refraction=None):
     g = scn.grid
     return api.swath_desc(scn.n_ping, scn.n_elem, scn.n_sample, g.n, g.origin, g.spacing,
-                          scn.fc, scn.fs, scn.t0, scn.gate_half_angle, echo_dtype, c_min, interp, motion)
+                          scn.fc, scn.fs, scn.t0, scn.gate_half_angle, echo_dtype, c_min, interp, motion,
+                          refraction)
 
 
 def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scale=None,
@@ -55,8 +56,9 @@ def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scal
 
 
 def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_scale=None, interp="linear",
-              rx_vel=None, **plan_kw):
-    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype, interp=interp, motion=rx_vel is not None)], **plan_kw)
+              rx_vel=None, refraction=None, **plan_kw):
+    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype, interp=interp, motion=rx_vel is not None,
+                                     refraction=refraction)], **plan_kw)
     buf = buffers_for(api, scn, echo, echo_scale=echo_scale, rx_vel=rx_vel)
     api.sas_bp_image(plan, [buf])
     torch.cuda.synchronize()
@@ -64,12 +66,12 @@ def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_sca
     return buf.image.cpu().numpy(), plan, buf
 
 
-def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None, interp="linear", rx_vel=None):
+def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None, interp="linear", rx_vel=None, refraction=None):
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, index)
     return oracle.backproject(echo_np, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
                               scn.gate_half_angle, workers=workers(),
-                              interp="sinc" if interp == "sinc8" else interp, rx_vel=rx_vel)
+                              interp="sinc" if interp == "sinc8" else interp, rx_vel=rx_vel, refraction=refraction)
 
 
 def report(name, img, ref):

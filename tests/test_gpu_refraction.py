@@ -1,0 +1,102 @@
+"""Sediment-water interface refraction (desc.refract = 1) through the C ABI
+against the oracle, on echoes synthesized with the same interface (the
+synthesis finds each crossing by golden-section search, the oracle by
+bisection on Snell's law, the kernel by bracketed Newton steps). Bound: the
+FP32 image bound (1e-4 relative L2, 10 mrad over pixels within 30 dB of the
+peak).
+
+The near-field volume (array at the surface, seabed at 5.5 m, sand at
+1650 m/s): voxels from 5.0 m, buried scatterers to 1 m below the seabed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import make_config, synthesize_echo, subset_indices
+from tests.helpers import FP32_REL_L2, FP32_PHASE_MRAD, desc_for, buffers_for, gpu_image, oracle_image, report
+
+pytestmark = pytest.mark.gpu
+
+REFR = (1650.0, 5.5)
+
+
+@pytest.fixture(scope="module")
+def api():
+    import paper_2101_05888_amd as m
+    return m
+
+
+def _scene(**kw):
+    # voxels from 5.3 m to 5.88 m: across the seabed at 5.5 m
+    base = dict(n_ping=16, n_across=4, nx=40, ny=24, nz=30, z0=5.3, n_seabed=300, n_surface=8, n_buried=12,
+                n_sample=2048)
+    base.update(kw)
+    return make_config("c3", **base)
+
+
+def test_refraction_image_matches_oracle(api):
+    print("case refraction c3 small", flush=True)
+    scn = _scene()
+    echo = synthesize_echo(scn, dtype=torch.complex64, refraction=REFR)
+    img, plan, _ = gpu_image(api, scn, echo, refraction=REFR)
+    ref = oracle_image(scn, echo.numpy(), refraction=REFR).reshape(img.shape)
+    r, ph = report("refraction c3 small", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+    # the case exercises the interface: straight-path imaging of this echo is far off
+    straight = oracle_image(scn, echo.numpy()).reshape(img.shape)
+    assert oracle.rel_l2(straight, ref) > 0.1
+
+
+def test_gated_2d_with_an_interface(api):
+    # the stripmap geometry with a gate, pixels 0.2 m below an interface at z = -0.2
+    print("case refraction gated 2D", flush=True)
+    scn = make_config("c2", n_ping=32, n_elem=8, nx=160, ny=64, n_sample=4096, n_scat=20, n_speckle=100)
+    refr = (1620.0, -0.2)
+    echo = synthesize_echo(scn, dtype=torch.complex64, refraction=refr)
+    img, plan, _ = gpu_image(api, scn, echo, refraction=refr)
+    ref = oracle_image(scn, echo.numpy(), refraction=refr).reshape(img.shape)
+    r, ph = report("refraction gated 2D", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+
+
+def test_equal_speeds_match_the_straight_kernel(api):
+    scn = _scene()
+    echo = synthesize_echo(scn, dtype=torch.complex64)
+    img_r, _, _ = gpu_image(api, scn, echo, refraction=(scn.c, 5.5))
+    img_s, _, _ = gpu_image(api, scn, echo)
+    r, ph = report("refraction c_sed = c vs straight kernel", img_r, img_s)
+    assert r <= 2e-5
+
+
+def test_refraction_plans_refuse_other_paths(api):
+    scn = _scene(n_ping=4, nx=16, ny=8, nz=8)
+    echo = synthesize_echo(scn, dtype=torch.complex64, refraction=REFR)
+    img, plan, buf = gpu_image(api, scn, echo, refraction=REFR)
+    with pytest.raises(RuntimeError):
+        api.sas_bp_reproject(plan, [buf], [buf.image], [torch.zeros_like(buf.echo)])
+    with pytest.raises(RuntimeError):
+        api.sas_bp_plan([desc_for(api, scn, interp="sinc8", refraction=REFR)])
+    with pytest.raises(RuntimeError):
+        api.sas_bp_plan([desc_for(api, scn, refraction=(0.0, 5.5))])
+
+
+def test_full_size_volume_refraction_sampled(api):
+    """The 3D workload at full size (256 pings x 64 receivers, 8192 samples,
+    512 x 512 x 128 voxels) with the sediment interface, in the default launch
+    configuration, on 48 seeded voxels."""
+    print("case refraction c3 full size", flush=True)
+    scn = make_config("c3", n_seabed=5000)
+    echo = synthesize_echo(scn, device="cuda", dtype=torch.complex64, noise_on_device=True, refraction=REFR)
+    plan = api.sas_bp_plan([desc_for(api, scn, refraction=REFR)])
+    buf = buffers_for(api, scn, echo)
+    api.sas_bp_image(plan, [buf])
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    idx = subset_indices(scn, 48)
+    img = buf.image.reshape(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    echo_np = echo.cpu().numpy()
+    del echo, buf
+    ref = oracle_image(scn, echo_np, idx, refraction=REFR)
+    r, ph = report("refraction c3-full-subset", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
