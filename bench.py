@@ -470,13 +470,29 @@ def volume_leg(api, steps: int, warmup: int) -> dict:
     info = plan.info()
     log(f"volume: {ms:.2f} ms/step, image kernel {kms:.2f} ms, {updates / (kms * 1e-3):.4e} updates/s, plan {info}")
     plan.destroy()
+    # the same volume with the sediment-water interface (seabed at 5.5 m, sand at
+    # 1650 m/s; the straight-path echo is reused: the timing does not depend on it)
+    d = _desc(api, scn)
+    d.refract, d.c_sediment, d.z_interface = 1, 1650.0, 5.5
+    rplan = api.sas_bp_plan([d])
+    api.sas_bp_set_kernel_timing(rplan, True)
+    api.sas_bp_image(rplan, [buf])
+    api.sas_bp_kernel_time(rplan)
+    rms = time_steps(lambda: api.sas_bp_image(rplan, [buf]), 1, 0)
+    r_total, r_n = api.sas_bp_kernel_time(rplan)
+    rkms = r_total / r_n
+    log(f"volume with sediment refraction: {rms:.2f} ms/step, kernel {rkms:.2f} ms "
+        f"({rkms / kms:.1f}x straight paths), {updates / (rkms * 1e-3):.4e} updates/s")
+    rplan.destroy()
     del echo, buf
     torch.cuda.empty_cache()
     return {"workload": "3D volume 512x512x128 voxels at 2 cm, 256 pings x 64 receivers, 8192 samples, no gate",
             "updates": int(updates), "ms_per_step": ms, "image_kernel_ms": kms,
             "updates_per_s": updates / (ms * 1e-3), "kernel_updates_per_s": updates / (kms * 1e-3),
             "tile": [info["tile_x"], info["tile_y"], info["tile_z"]], "records_per_chunk": info["records_per_chunk"],
-            "workgroups_per_cu": info["workgroups_per_cu"]}
+            "workgroups_per_cu": info["workgroups_per_cu"],
+            "refraction": {"c_sediment": 1650.0, "z_interface": 5.5, "ms_per_step": rms, "kernel_ms": rkms,
+                           "kernel_updates_per_s": updates / (rkms * 1e-3), "vs_straight": rkms / kms}}
 
 
 def autofocus_leg(api, steps: int, warmup: int) -> dict:
