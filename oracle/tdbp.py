@@ -133,7 +133,7 @@ def refracted_leg(X, pts, c, c_sed, z_int):
     below = h2 > 0
     lo, hi = np.zeros_like(D), D.copy()
     h2c = np.where(below, h2, 1.0)      # pixels at or above the interface take the straight path below
-    for _ in range(200):
+    for _ in range(100):                 # brackets D / 2^100: far below FP64 resolution
         r = 0.5 * (lo + hi)
         f = r / (c * np.sqrt(r * r + h1 * h1)) - (D - r) / (c_sed * np.sqrt((D - r) ** 2 + h2c * h2c))
         lo = np.where(f < 0, r, lo)
