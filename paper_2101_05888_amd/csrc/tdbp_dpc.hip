@@ -7,10 +7,11 @@
 // in groups of G: for each pair j of a group, the window a = echo[i][e1][n0,
 // n0 + W) and the lag-extended window b = echo[i + 1][e2][n0 - L, n0 + W + L)
 // (zero outside the record). One thread owns a (pair, block of kTdeBlock
-// lags) and forms its full sums in registers, sliding a window of b values
-// along n (two LDS reads per sample for kTdeBlock lags):
+// lags, third of the samples) and forms its sums in registers, sliding a
+// window of b values along n (two LDS reads per sample for kTdeBlock lags):
 //     r(l) = sum_n a[n] conj(b[n + l]),  eb(l) = sum_n |b[n + l]|^2   (FP32)
-// then the group's partial sums are added over pairs, per lag, in pair order.
+// then the group's partial sums are added per lag over pairs and sample
+// thirds, in a fixed order.
 // The peak search, the quadratic step mu = (m_- - m_+) / (2 (m_- - 2 m_0 +
 // m_+)) (0 on a flat top), the complex correlation at l* + mu and rho =
 // |r(l*)| / sqrt(ea eb(l*)) are then formed in FP64 by one thread. The peak
@@ -24,10 +25,11 @@ constexpr int kTdeMaxLag = 64;
 constexpr int kTdeMaxLags = 2 * kTdeMaxLag + 1;
 constexpr int kTdeBlock = 4;             // lags per thread
 constexpr int kTdeLdsTarget = 24576;     // bytes of looks per group (several workgroups per CU)
+constexpr int kTdeSplit = 3;             // sample segments per (pair, lag block), summed in LDS
 
 // Pairs per LDS group for windows of W samples and lags to +-L.
 __host__ __device__ inline int tde_group(int W, int L, int J) {
-  const int per = (2 * W + 2 * L + kTdeBlock) * 8 + (2 * L + 1) * 12;
+  const int per = (2 * W + 2 * L + kTdeBlock) * 8 + kTdeSplit * (2 * L + 1) * 12;
   int g = kTdeLdsTarget / per;
   g = g < 1 ? 1 : g;
   return g < J ? g : J;
@@ -49,8 +51,9 @@ __global__ __launch_bounds__(kTdeThreads) void dpc_tde_kernel(const float2* __re
   const int G = tde_group(W, L, J);
   float2* sa = reinterpret_cast<float2*>(tde_lds);            // [G][W]
   float2* sb = sa + (size_t)G * W;                            // [G][WB]
-  float2* pr_r = sb + (size_t)G * WB;                         // [G][NL]
-  float* pr_e = reinterpret_cast<float*>(pr_r + (size_t)G * NL);   // [G][NL]
+  float2* pr_r = sb + (size_t)G * WB;                         // [kTdeSplit][G][NL]
+  float* pr_e = reinterpret_cast<float*>(pr_r + (size_t)kTdeSplit * G * NL);   // [kTdeSplit][G][NL]
+  const int WS = (W + kTdeSplit - 1) / kTdeSplit;             // samples per segment
   for (int li = t; li < NL; li += kTdeThreads) {
     r_acc[li] = make_float2(0.0f, 0.0f);
     eb_acc[li] = 0.0f;
@@ -81,8 +84,10 @@ __global__ __launch_bounds__(kTdeThreads) void dpc_tde_kernel(const float2* __re
       for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o, 64);
       if (t == 0) ea_acc += e;
     }
-    for (int it = t; it < gJ * NB; it += kTdeThreads) {
-      const int j = it / NB, l0 = (it - j * NB) * kTdeBlock;
+    for (int it = t; it < kTdeSplit * gJ * NB; it += kTdeThreads) {
+      const int seg = it / (gJ * NB), jt = it - seg * gJ * NB;
+      const int j = jt / NB, l0 = (jt - j * NB) * kTdeBlock;
+      const int nlo = seg * WS, nhi = min(W, nlo + WS);
       const float2* a = sa + j * W;
       const float2* b = sb + j * WB + l0;
       float re[kTdeBlock], im[kTdeBlock], en[kTdeBlock];
@@ -90,9 +95,9 @@ __global__ __launch_bounds__(kTdeThreads) void dpc_tde_kernel(const float2* __re
 #pragma unroll
       for (int r = 0; r < kTdeBlock; ++r) {
         re[r] = im[r] = en[r] = 0.0f;
-        bw[r] = b[r];
+        bw[r] = b[nlo + r];
       }
-      for (int n = 0; n < W; ++n) {
+      for (int n = nlo; n < nhi; ++n) {
         const float2 av = a[n];
 #pragma unroll
         for (int r = 0; r < kTdeBlock; ++r) {   // a[n] conj(b[n + l])
@@ -107,19 +112,20 @@ __global__ __launch_bounds__(kTdeThreads) void dpc_tde_kernel(const float2* __re
 #pragma unroll
       for (int r = 0; r < kTdeBlock; ++r)
         if (l0 + r < NL) {
-          pr_r[j * NL + l0 + r] = make_float2(re[r], im[r]);
-          pr_e[j * NL + l0 + r] = en[r];
+          pr_r[(seg * G + j) * NL + l0 + r] = make_float2(re[r], im[r]);
+          pr_e[(seg * G + j) * NL + l0 + r] = en[r];
         }
     }
     __syncthreads();
     for (int li = t; li < NL; li += kTdeThreads) {
       float2 racc = r_acc[li];
       float eacc = eb_acc[li];
-      for (int j = 0; j < gJ; ++j) {
-        racc.x += pr_r[j * NL + li].x;
-        racc.y += pr_r[j * NL + li].y;
-        eacc += pr_e[j * NL + li];
-      }
+      for (int j = 0; j < gJ; ++j)
+        for (int sg = 0; sg < kTdeSplit; ++sg) {
+          racc.x += pr_r[(sg * G + j) * NL + li].x;
+          racc.y += pr_r[(sg * G + j) * NL + li].y;
+          eacc += pr_e[(sg * G + j) * NL + li];
+        }
       r_acc[li] = racc;
       eb_acc[li] = eacc;
     }
@@ -155,7 +161,7 @@ int tde_max_lag() { return kTdeMaxLag; }
 
 size_t tde_lds_bytes(int W, int L, int J) {
   const int G = tde_group(W, L, J);
-  return (size_t)G * ((size_t)(2 * W + 2 * L + kTdeBlock) * 8 + (size_t)(2 * L + 1) * 12);
+  return (size_t)G * ((size_t)(2 * W + 2 * L + kTdeBlock) * 8 + (size_t)kTdeSplit * (2 * L + 1) * 12);
 }
 
 hipError_t launch_dpc_tde(const void* echo, int P, int E, int Ns, const int* pairs, int J, int W, int hop, int L,
