@@ -756,12 +756,12 @@ int sas_bp_dpc_solve(const sas_bp_dpc_desc* d, const double* vx, const double* d
   double* g_pos = reinterpret_cast<double*>(buf + at[7]);
   double* g_rows = reinterpret_cast<double*>(buf + at[8]);
   int status = SAS_BP_OK;
-  std::vector<double> vel(3 * P), rows(7 * R), x(n), N((size_t)n * n), grad(n), step(n);
+  std::vector<double> vel(3 * P), rows(7 * R), x(n), N((size_t)n * n), grad(n);
   for (int i = 0; i < P; ++i) {
     x[2 * i] = vyz[2 * i];
     x[2 * i + 1] = vyz[2 * i + 1];
   }
-  auto evaluate = [&](const std::vector<double>& xv, bool want_rows, double* loss) -> bool {
+  auto evaluate = [&](const std::vector<double>& xv, double* loss) -> bool {
     for (int i = 0; i < P; ++i) {
       vel[3 * i] = vx[i];
       vel[3 * i + 1] = xv[2 * i];
@@ -789,7 +789,6 @@ int sas_bp_dpc_solve(const sas_bp_dpc_desc* d, const double* vx, const double* d
       L += d->lambda_dvl * dv * dv;
       if (i + 1 < P) z += xv[2 * i + 1] * dt[i];
     }
-    (void)want_rows;
     *loss = L;
     return true;
   };
@@ -804,7 +803,7 @@ int sas_bp_dpc_solve(const sas_bp_dpc_desc* d, const double* vx, const double* d
       break;
     }
     double cur_loss = 0.0;
-    if (!evaluate(x, true, &cur_loss)) {
+    if (!evaluate(x, &cur_loss)) {
       status = fail(SAS_BP_EDEVICE, "residual pass failed");
       break;
     }
@@ -926,7 +925,7 @@ int sas_bp_dpc_solve(const sas_bp_dpc_desc* d, const double* vx, const double* d
           xnorm += x[q] * x[q];
         }
         double tl = 0.0;
-        if (!evaluate(xt, true, &tl)) {
+        if (!evaluate(xt, &tl)) {
           status = fail(SAS_BP_EDEVICE, "residual pass failed");
           break;
         }
@@ -940,10 +939,7 @@ int sas_bp_dpc_solve(const sas_bp_dpc_desc* d, const double* vx, const double* d
         lam *= 4.0;
       }
       if (status != SAS_BP_OK) break;
-      if (!improved) {
-        (void)evaluate(x, true, &cur_loss);   // rows of the kept point
-        break;
-      }
+      if (!improved) break;
       if (std::sqrt(snorm) < 1e-12 * (1.0 + std::sqrt(xnorm))) break;
     }
     if (status != SAS_BP_OK) break;
