@@ -24,7 +24,7 @@
 
 namespace sasbp {
 
-constexpr int kRefractNewton = 6;   // Newton steps per leg
+constexpr int kRefractNewton = 8;   // most Newton steps per leg (most legs stop after two or three)
 
 // One leg's travel time (FP64 result): the crossing distance r by FP32 Newton
 // steps, then the time at r evaluated in FP64 (it is stationary in r, so the
@@ -38,7 +38,7 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
   const float Df = (float)D, h1f = (float)h1, h2f = (float)h2, icf = (float)inv_c, icsf = (float)inv_cs;
   float lo = 0.0f, hi = Df;
   float r = Df * h1f / (h1f + h2f);
-#pragma unroll
+  const float tol = 1e-6f * (Df + h1f + h2f);   // FP32 resolution of the crossing
   for (int it = 0; it < kRefractNewton; ++it) {
     const float u = Df - r;
     const float ia = __builtin_amdgcn_rsqf(fmaf(r, r, h1f * h1f));
@@ -49,7 +49,9 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
     const float fp = h1f * h1f * ia * ia * ia * icf + h2f * h2f * ib * ib * ib * icsf;
     float rn = r - f * __builtin_amdgcn_rcpf(fp);
     rn = (rn >= lo && rn <= hi) ? rn : 0.5f * (lo + hi);   // a converged step may land on the bracket end
+    const bool done = fabsf(rn - r) <= tol;
     r = rn;
+    if (done) break;
   }
   const double rd = (double)r, ud = D - rd;
   return sqrt(rd * rd + h1 * h1) * inv_c + sqrt(ud * ud + h2 * h2) * inv_cs;
