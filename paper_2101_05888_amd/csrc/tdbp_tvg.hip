@@ -12,7 +12,10 @@
 // row (one 128-byte line per row), and per pass of 11, 11 and 10 bits builds
 // one LDS histogram per sample time of the keys that share the digits found
 // so far; 16 threads per sample time then find the digit holding the rank.
-// The mean over sample times is a fixed-order FP64 sum.
+// With at most 65535 rows two 16-bit counts share each 32-bit LDS word (no
+// count can carry into its neighbour), halving the histograms to 64 KB so
+// that two workgroups fit a CU. The mean over sample times is a fixed-order
+// FP64 sum.
 #include "tdbp_dev.h"
 
 namespace sasbp {
@@ -22,9 +25,14 @@ constexpr int kTvgBins = 2048;
 
 __device__ __forceinline__ unsigned tvg_key(float2 v) { return __float_as_uint(fmaf(v.x, v.x, v.y * v.y)); }
 
+template <bool PACK>
 __global__ __launch_bounds__(kThreads) void tvg_median_kernel(const float2* echo, long long rows, int Ns,
                                                               float* med) {
-  __shared__ unsigned hist[kTvgCols][kTvgBins];
+  constexpr int WORDS = PACK ? kTvgBins / 2 : kTvgBins;
+  __shared__ unsigned hist[kTvgCols][WORDS];
+  auto count = [&](int c, int d) -> unsigned {
+    return PACK ? (hist[c][d >> 1] >> ((d & 1) << 4)) & 0xFFFFu : hist[c][d];
+  };
   __shared__ unsigned part[kTvgCols][kThreads / kTvgCols];
   __shared__ unsigned s_prefix[kTvgCols], s_rank[kTvgCols];
   constexpr int RL = kThreads / kTvgCols;   // threads per sample time (16)
@@ -37,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void tvg_median_kernel(const float2* echo
     s_rank[tid] = (unsigned)((rows - 1) / 2);
   }
   for (int pass = 0; pass < 3; ++pass) {
-    for (int i = tid; i < kTvgCols * kTvgBins; i += kThreads) (&hist[0][0])[i] = 0u;
+    for (int i = tid; i < kTvgCols * WORDS; i += kThreads) (&hist[0][0])[i] = 0u;
     __syncthreads();
     const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
     const unsigned mask = pass == 2 ? 0x3FFu : 0x7FFu;
@@ -46,7 +54,11 @@ __global__ __launch_bounds__(kThreads) void tvg_median_kernel(const float2* echo
       for (long long r = lane; r < rows; r += RL) {
         const unsigned key = tvg_key(echo[r * Ns + t0 + col]);
         const bool match = pass == 0 || (key >> (shift + (pass == 1 ? 11 : 10))) == prefix;
-        if (match) atomicAdd(&hist[col][(key >> shift) & mask], 1u);
+        const unsigned b = (key >> shift) & mask;
+        if (match) {
+          if (PACK) atomicAdd(&hist[col][b >> 1], 1u << ((b & 1u) << 4));
+          else atomicAdd(&hist[col][b], 1u);
+        }
       }
     }
     __syncthreads();
@@ -56,7 +68,7 @@ __global__ __launch_bounds__(kThreads) void tvg_median_kernel(const float2* echo
     unsigned sum = 0u;
     for (int j = 0; j < PER; ++j) {
       const int d = lane * PER + j;
-      sum += d < bins ? hist[col][d] : 0u;
+      sum += d < bins ? count(col, d) : 0u;
     }
     part[col][lane] = sum;
     __syncthreads();
@@ -68,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void tvg_median_kernel(const float2* echo
       unsigned r = k - before;
       int d = lane * PER;
       for (int j = 0; j < PER; ++j) {
-        const unsigned c = hist[col][lane * PER + j];
+        const unsigned c = count(col, lane * PER + j);
         if (r < c) { d = lane * PER + j; break; }
         r -= c;
       }
@@ -114,7 +126,11 @@ hipError_t launch_tvg(void* echo, long long rows, int Ns, double alpha, float* w
   float* med = work;
   float* amp = work + Ns;
   const int groups = (Ns + kTvgCols - 1) / kTvgCols;
-  hipLaunchKernelGGL(tvg_median_kernel, dim3(groups), dim3(kThreads), 0, st, (const float2*)e, rows, Ns, med);
+  if (rows <= 65535)
+    hipLaunchKernelGGL(tvg_median_kernel<true>, dim3(groups), dim3(kThreads), 0, st, (const float2*)e, rows, Ns, med);
+  else
+    hipLaunchKernelGGL(tvg_median_kernel<false>, dim3(groups), dim3(kThreads), 0, st, (const float2*)e, rows, Ns,
+                       med);
   hipLaunchKernelGGL(tvg_gain_kernel, dim3(1), dim3(kThreads), 0, st, (const float*)med, Ns, alpha, amp, gain_out);
   const long long n = rows * (long long)Ns;
   long long blocks = (n + kThreads - 1) / kThreads;

@@ -65,3 +65,26 @@ def test_tvg_ragged_and_zero_columns(api):
     ref, med, G = oracle.tvg(e.astype(np.complex128), 0.0)
     assert np.all(got[:, :, 500] == 0)
     assert oracle.rel_l2(got, ref) <= 2e-6
+
+
+@pytest.mark.parametrize("n_ping", [2047, 2049])
+def test_tvg_packed_and_wide_histograms(api, n_ping):
+    # 32 elements: 65504 rows take 16-bit packed histogram counts, 65568 rows the
+    # 32-bit ones; the medians must be exact either way (ties and a common value
+    # in one column push a count near its limit)
+    E, Ns = 32, 40
+    scn = make_config("c1", n_ping=n_ping, n_elem=E, n_sample=Ns)
+    rng = np.random.default_rng(n_ping)
+    e = (rng.normal(size=(n_ping, E, Ns)) + 1j * rng.normal(size=(n_ping, E, Ns))).astype(np.complex64)
+    e[:, :, 7] = 0.5 + 0.5j                       # every key equal: one bin holds every row
+    e[: n_ping // 2, :, 11] = 1.0                 # half the keys equal
+    plan = api.sas_bp_plan([desc_for(api, scn)])
+    x = torch.as_tensor(e, device="cuda").contiguous()
+    gain = torch.zeros(Ns, dtype=torch.float32, device="cuda")
+    api.sas_bp_tvg(plan, 0, x, 0.2, gain)
+    torch.cuda.synchronize()
+    ref, med, G = oracle.tvg(e.astype(np.complex128), 0.2)
+    r = oracle.rel_l2(x.cpu().numpy(), ref)
+    rg = np.abs(gain.cpu().numpy() - G).max() / np.abs(G).max()
+    print(f"[tvg rows={n_ping * E}] echo rel_l2={r:.2e}, gain max rel={rg:.2e}", flush=True)
+    assert r <= 2e-6 and rg <= 2e-6
