@@ -7,14 +7,18 @@
 // vertical plane through X and p at horizontal distance r from X, where
 //     f(r) = r / (c a) - (D - r) / (c_sed b) = 0,   a = |(r, h1)|, b = |(D - r, h2)|
 // (Snell's law; D the horizontal distance of X and p, h1 = z_int - X_z,
-// h2 = p_z - z_int). f grows with r, so Newton steps from the straight-line
-// crossing r = D h1 / (h1 + h2), kept inside the bracket [0, D] that the sign
-// of f shrinks, converge; the travel time a / c + b / c_sed is stationary at
-// the root, so a few steps give it to FP32 rounding. Legs to pixels at or above
-// the interface are straight. The beam gate keeps straight lines.
+// h2 = p_z - z_int). f grows with r, so Newton steps kept inside the bracket
+// [0, D] that the sign of f shrinks converge; the travel time a / c + b / c_sed
+// is stationary at the root, so a few steps give it to FP32 rounding. A pixel's
+// transmit leg starts from the straight-line crossing r = D h1 / (h1 + h2); its
+// receiver legs start from the crossing ratio r / D of the leg before (the
+// transmit leg, then the previous element), which neighbouring apexes nearly
+// share: two or three steps instead of five to eight. Legs to pixels at or
+// above the interface are straight. The beam gate keeps straight lines.
 //
-// Precision: the crossing point by FP32 Newton steps, the leg times, the delay
-// and the carrier phase (reduced to revolutions) in FP64; the interpolation is
+// Precision: the crossing point by FP32 Newton steps, the leg times (square
+// roots from the FP32 reciprocal square root and one FP64 Newton step), the
+// delay and the carrier phase (reduced to revolutions) in FP64; the interpolation is
 // linear in FP32, the echo read from global memory (L2-resident per tile).
 //
 // Same persistent scheduling as the image kernel: a workgroup takes tiles from
@@ -26,18 +30,29 @@ namespace sasbp {
 
 constexpr int kRefractNewton = 8;   // most Newton steps per leg (most legs stop after two or three)
 
+// Square root of A > 0 in FP64 from the FP32 reciprocal square root y and one
+// Newton step s + (A - s^2) y / 2 with s = A y: the relative error, about the
+// square of the FP32 one, stays near 1e-13 (the seed is kept finite for an A
+// below the FP32 range).
+__device__ __forceinline__ double sqrt_refined(double A) {
+  const double y = (double)__builtin_amdgcn_rsqf(fmaxf((float)A, 1e-30f));
+  const double s = A * y;
+  return fma(fma(-s, s, A), 0.5 * y, s);
+}
+
 // One leg's travel time (FP64 result): the crossing distance r by FP32 Newton
-// steps, then the time at r evaluated in FP64 (it is stationary in r, so the
-// FP32 error of r does not reach it).
+// steps from the ratio q = r / D (in: a nearby leg's, out: this leg's), then
+// the time at r evaluated in FP64 (it is stationary in r, so the FP32 error of
+// r does not reach it).
 __device__ __forceinline__ double refracted_time(double dx, double dy, double dz, double h1, double h2, double inv_c,
-                                                 double inv_cs) {
+                                                 double inv_cs, float& q) {
   const double D2 = dx * dx + dy * dy;
   if (!(h2 > 0.0) || !(h1 > 0.0))   // pixel at or above the interface (or apex below it): straight
     return sqrt(D2 + dz * dz) * inv_c;
   const double D = sqrt(D2);
   const float Df = (float)D, h1f = (float)h1, h2f = (float)h2, icf = (float)inv_c, icsf = (float)inv_cs;
   float lo = 0.0f, hi = Df;
-  float r = Df * h1f / (h1f + h2f);
+  float r = fminf(fmaxf(q, 0.0f), 1.0f) * Df;   // a NaN ratio starts at 0
   const float tol = 1e-6f * (Df + h1f + h2f);   // FP32 resolution of the crossing
   for (int it = 0; it < kRefractNewton; ++it) {
     const float u = Df - r;
@@ -53,8 +68,9 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
     r = rn;
     if (done) break;
   }
+  if (Df > 0.0f) q = r / Df;
   const double rd = (double)r, ud = D - rd;
-  return sqrt(rd * rd + h1 * h1) * inv_c + sqrt(ud * ud + h2 * h2) * inv_cs;
+  return sqrt_refined(rd * rd + h1 * h1) * inv_c + sqrt_refined(ud * ud + h2 * h2) * inv_cs;
 }
 
 template <int L, bool GATE, int DT>
@@ -97,10 +113,13 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
       const float scale = sw.dtype == 0 ? 1.0f : sw.scale[p];
       double tT[K];
       bool gT[K];
+      float q[K];   // crossing ratio of the pixel's last leg
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const double dx = px[k] - Tx, dy = py - Ty, dz = pz - Tz;
-        tT[k] = refracted_time(dx, dy, dz, sw.z_int - Tz, pz - sw.z_int, inv_c, inv_cs);
+        const double h1 = sw.z_int - Tz, h2 = pz - sw.z_int;
+        q[k] = (float)(h1 / (h1 + h2));   // straight-line crossing
+        tT[k] = refracted_time(dx, dy, dz, h1, h2, inv_c, inv_cs, q[k]);
         gT[k] = true;
         if (GATE && sw.tan_g > 0.0) gT[k] = fabs(dx) <= sw.sin_g * sqrt(dx * dx + dy * dy + dz * dz);
       }
@@ -115,7 +134,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
           bool g = gT[k];
           if (GATE && sw.tan_g > 0.0) g = g && fabs(dx) <= sw.sin_g * sqrt(dx * dx + dy * dy + dz * dz);
           if (!g) continue;
-          const double tau = tT[k] + refracted_time(dx, dy, dz, sw.z_int - Rz, pz - sw.z_int, inv_c, inv_cs);
+          const double tau = tT[k] + refracted_time(dx, dy, dz, sw.z_int - Rz, pz - sw.z_int, inv_c, inv_cs, q[k]);
           const double u = (tau - sw.t0) * sw.fs;
           const double nf = floor(u);
           const float w = (float)(u - nf);
