@@ -30,10 +30,10 @@ namespace sasbp {
 
 constexpr int kRefractNewton = 8;   // most Newton steps per leg (most legs stop after two or three)
 
-// Square root of A > 0 in FP64 from the FP32 reciprocal square root y and one
+// Square root of A >= 0 in FP64 from the FP32 reciprocal square root y and one
 // Newton step s + (A - s^2) y / 2 with s = A y: the relative error, about the
 // square of the FP32 one, stays near 1e-13 (the seed is kept finite for an A
-// below the FP32 range).
+// below the FP32 range, so A = 0 gives 0).
 __device__ __forceinline__ double sqrt_refined(double A) {
   const double y = (double)__builtin_amdgcn_rsqf(fmaxf((float)A, 1e-30f));
   const double s = A * y;
@@ -48,8 +48,8 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
                                                  double inv_cs, float& q) {
   const double D2 = dx * dx + dy * dy;
   if (!(h2 > 0.0) || !(h1 > 0.0))   // pixel at or above the interface (or apex below it): straight
-    return sqrt(D2 + dz * dz) * inv_c;
-  const double D = sqrt(D2);
+    return sqrt_refined(D2 + dz * dz) * inv_c;
+  const double D = sqrt_refined(D2);   // enters the leg time at first order: kept to FP64 accuracy
   const float Df = (float)D, h1f = (float)h1, h2f = (float)h2, icf = (float)inv_c, icsf = (float)inv_cs;
   float lo = 0.0f, hi = Df;
   float r = fminf(fmaxf(q, 0.0f), 1.0f) * Df;   // a NaN ratio starts at 0
