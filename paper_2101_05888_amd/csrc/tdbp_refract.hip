@@ -13,8 +13,11 @@
 // transmit leg starts from the straight-line crossing r = D h1 / (h1 + h2); its
 // receiver legs start from the crossing ratio r / D of the leg before (the
 // transmit leg, then the previous element), which neighbouring apexes nearly
-// share: two or three steps instead of five to eight. Legs to pixels at or
-// above the interface are straight. The beam gate keeps straight lines.
+// share. The loop stops at the FP32 resolution of r or once the step s bounds
+// the time error f' s^2 / 2 of the point it came from below 1e-5 of the
+// shorter of the carrier and sampling periods (the point it returns is closer
+// still): about one step per wavefront, from five to eight cold. Legs to
+// pixels at or above the interface are straight. The beam gate keeps straight lines.
 //
 // Precision: the crossing point by FP32 Newton steps, the leg times (square
 // roots from the FP32 reciprocal square root and one FP64 Newton step), the
@@ -41,11 +44,11 @@ __device__ __forceinline__ double sqrt_refined(double A) {
 }
 
 // One leg's travel time (FP64 result): the crossing distance r by FP32 Newton
-// steps from the ratio q = r / D (in: a nearby leg's, out: this leg's), then
-// the time at r evaluated in FP64 (it is stationary in r, so the FP32 error of
-// r does not reach it).
+// steps from the ratio q = r / D (in: a nearby leg's, out: this leg's) until
+// the time error bound falls below tt seconds, then the time at r evaluated in
+// FP64 (it is stationary in r, so the error of r reaches it only squared).
 __device__ __forceinline__ double refracted_time(double dx, double dy, double dz, double h1, double h2, double inv_c,
-                                                 double inv_cs, float& q) {
+                                                 double inv_cs, float tt, float& q) {
   const double D2 = dx * dx + dy * dy;
   if (!(h2 > 0.0) || !(h1 > 0.0))   // pixel at or above the interface (or apex below it): straight
     return sqrt_refined(D2 + dz * dz) * inv_c;
@@ -64,7 +67,8 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
     const float fp = h1f * h1f * ia * ia * ia * icf + h2f * h2f * ib * ib * ib * icsf;
     float rn = r - f * __builtin_amdgcn_rcpf(fp);
     rn = (rn >= lo && rn <= hi) ? rn : 0.5f * (lo + hi);   // a converged step may land on the bracket end
-    const bool done = fabsf(rn - r) <= tol;
+    const float st = fabsf(rn - r);
+    const bool done = st <= tol || 0.5f * fp * st * st <= tt;
     r = rn;
     if (done) break;
   }
@@ -96,6 +100,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
     const int iy = tiy * TY + ly, iz = tiz * TZ + lz;
     const double c = *sw.c;
     const double inv_c = 1.0 / c, inv_cs = 1.0 / sw.c_sed;
+    const float tt = (float)(1e-5 / (sw.fc > sw.fs ? sw.fc : sw.fs));   // time error bound of a stopped solve (s)
     const PingRange pr = prange[t];
     // pixel centres (FP64)
     double px[K];
@@ -119,7 +124,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
         const double dx = px[k] - Tx, dy = py - Ty, dz = pz - Tz;
         const double h1 = sw.z_int - Tz, h2 = pz - sw.z_int;
         q[k] = (float)(h1 / (h1 + h2));   // straight-line crossing
-        tT[k] = refracted_time(dx, dy, dz, h1, h2, inv_c, inv_cs, q[k]);
+        tT[k] = refracted_time(dx, dy, dz, h1, h2, inv_c, inv_cs, tt, q[k]);
         gT[k] = true;
         if (GATE && sw.tan_g > 0.0) gT[k] = fabs(dx) <= sw.sin_g * sqrt(dx * dx + dy * dy + dz * dz);
       }
@@ -134,7 +139,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
           bool g = gT[k];
           if (GATE && sw.tan_g > 0.0) g = g && fabs(dx) <= sw.sin_g * sqrt(dx * dx + dy * dy + dz * dz);
           if (!g) continue;
-          const double tau = tT[k] + refracted_time(dx, dy, dz, sw.z_int - Rz, pz - sw.z_int, inv_c, inv_cs, q[k]);
+          const double tau = tT[k] + refracted_time(dx, dy, dz, sw.z_int - Rz, pz - sw.z_int, inv_c, inv_cs, tt, q[k]);
           const double u = (tau - sw.t0) * sw.fs;
           const double nf = floor(u);
           const float w = (float)(u - nf);
