@@ -72,7 +72,7 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
     r = rn;
     if (done) break;
   }
-  if (Df > 0.0f) q = r / Df;
+  if (Df > 0.0f) q = r * __builtin_amdgcn_rcpf(Df);   // only the next leg's starting point
   const double rd = (double)r, ud = D - rd;
   return sqrt_refined(rd * rd + h1 * h1) * inv_c + sqrt_refined(ud * ud + h2 * h2) * inv_cs;
 }
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
           const double u = (tau - sw.t0) * sw.fs;
           const double nf = floor(u);
           const float w = (float)(u - nf);
-          const long long n = (long long)nf;
+          const int n = (int)fmin(fmax(nf, -2.0), (double)sw.Ns);   // outside the row (or NaN): both taps zero
           float2 a = make_float2(0.0f, 0.0f), b = make_float2(0.0f, 0.0f);
           if (n >= 0 && n < sw.Ns) a = load_sample(sw.echo, row + (size_t)n, DT, scale);
           if (n + 1 >= 0 && n + 1 < sw.Ns) b = load_sample(sw.echo, row + (size_t)(n + 1), DT, scale);
