@@ -41,14 +41,16 @@ METRIC = "pixel·ping·element updates/s; mixed vs FP32 at ≤1e-4 rel-L2 vs FP6
 
 
 def flops_per_update(n_elem: int) -> float:
-    """Algorithmic FLOPs of one (pixel, ping, element) term of the sum.
+    """Algorithmic FLOPs of one (pixel, ping, element) term of the sum, the
+    cost model fixed before any tuning (an FMA counts 2, a transcendental 1):
 
-    d_R = |p - R| (3 sub, 3 mul, 2 add, sqrt: 9), tau = (d_T + d_R) / c (2),
-    u = (tau - t0) f_s (2), floor and fraction (2), complex lerp a + w (b - a)
-    (6), carrier argument and sin/cos (3), complex multiply (6) and accumulate
-    (2): 32, plus the transmitter leg d_T (9) shared by the E elements.
+    receiver displacement p - R (3), its squared norm (1 mul + 2 FMA: 5), the
+    two legs summed (1), sample coordinate (tau - t0) f_s (1 FMA: 2), floor
+    and fraction (2), carrier cycles f_c tau (1), complex lerp a + w (b - a)
+    (2 sub + 2 FMA: 6), complex multiply-accumulate (4 FMA: 8), sqrt, sin and
+    cos (3): 31, plus the transmitter leg (9) shared by the E elements.
     """
-    return 32.0 + 9.0 / n_elem
+    return 31.0 + 9.0 / n_elem
 
 
 IMAGE_KERNEL_SOURCES = ("tdbp_dev.h", "tdbp_geom.h", "tdbp_image.hip")
@@ -136,6 +138,11 @@ def measured_traffic(info: dict):
         return None
 
 
+def oracle_workers() -> int:
+    from oracle import pool
+    return pool.get()[1]
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -154,12 +161,24 @@ def time_steps(fn, steps: int, warmup: int) -> float:
     return start.elapsed_time(stop) / steps
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_leg(scn, echo_cpu: np.ndarray, images: dict, sample: int) -> dict:
     """Time the FP64 oracle on a seeded pixel sample on the host cores and
     compare every GPU form with it on the same pixels."""
     import oracle
+    from oracle import pool
     from synth import subset_indices
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    _, workers = pool.get()
     idx = subset_indices(scn, sample)
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, idx)
@@ -174,6 +193,7 @@ def cpu_baseline_leg(scn, echo_cpu: np.ndarray, images: dict, sample: int) -> di
                      "max_phase_mrad": oracle.phase_error_mrad(got, ref),
                      "p99_phase_mrad": oracle.phase_error_mrad(got, ref, stat="p99")}
     return {"value": useful / dt, "unit": "updates/s", "cores": workers, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{sample} seeded pixels of the same swath, all 512x32 (ping, element) terms "
                       f"evaluated and gated ({useful} useful updates) in {dt:.1f} s",
             "seconds": dt, "useful_updates": int(useful), "accuracy": acc}
@@ -240,9 +260,8 @@ def sinc_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_kerne
     got = buf.image.reshape(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, idx)
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
     ref = oracle.backproject(echo.cpu().numpy(), scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
-                             scn.gate_half_angle, workers=workers, interp="sinc")
+                             scn.gate_half_angle, workers=oracle_workers(), interp="sinc")
     r, ph = oracle.rel_l2(got, ref), oracle.phase_error_mrad(got, ref)
     log(f"sinc8: {ms:.3f} ms/step, image kernel {kms:.3f} ms ({kms / forward_kernel_ms:.2f}x linear), "
         f"rel_l2 {r:.2e}, max phase {ph:.3f} mrad on {sample} pixels")
@@ -277,9 +296,8 @@ def motion_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_ker
     got = buf.image.reshape(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, idx)
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
     ref = oracle.backproject(echo.cpu().numpy(), scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
-                             scn.gate_half_angle, workers=workers, rx_vel=vel)
+                             scn.gate_half_angle, workers=oracle_workers(), rx_vel=vel)
     r, ph = oracle.rel_l2(got, ref), oracle.phase_error_mrad(got, ref)
     log(f"motion: {ms:.3f} ms/step, image kernel {kms:.3f} ms ({kms / forward_kernel_ms:.2f}x stop-and-hop), "
         f"rel_l2 {r:.2e}, max phase {ph:.3f} mrad on {sample} pixels, status {status}")
@@ -608,14 +626,19 @@ def main() -> int:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         return 2
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no HIP device visible"}), flush=True)
-        return 3
     if args.profile:
         args.no_cpu_baseline = args.no_autofocus = args.no_batched = args.no_mixed = True
         args.no_reprojection = args.no_volume = args.no_sinc = args.no_drc = args.no_tvg = args.no_whiten = args.no_rangec = args.no_motion = args.no_dpc = True
         if args.profile_leg:
             setattr(args, "no_" + args.profile_leg, False)
+    if not (args.no_cpu_baseline and args.no_sinc and args.no_motion):
+        # the oracle's worker processes are forked now, before this process
+        # initialises the GPU runtime (it never forks afterwards)
+        from oracle import pool
+        pool.start()
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device visible"}), flush=True)
+        return 3
 
     import paper_2101_05888_amd as api
     from synth import make_config, synthesize_echo, quantize_echo

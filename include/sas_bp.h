@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define SAS_BP_ABI_VERSION 4
+#define SAS_BP_ABI_VERSION 5
 
 typedef struct sas_bp_plan_s* sas_bp_plan_t;
 
@@ -66,7 +66,10 @@ enum sas_bp_status {
     SAS_BP_EUNSUPPORTED = 2,  /* valid but not supported (dtype, tiling, size)    */
     SAS_BP_ENOMEM = 3,        /* device allocation failed or workspace limit hit  */
     SAS_BP_EDEVICE = 4,       /* HIP runtime error                                */
-    SAS_BP_ENAV = 5           /* device found non-finite navigation or bad c      */
+    SAS_BP_ENAV = 5,          /* device found non-finite navigation or bad c      */
+    SAS_BP_ECONVERGE = 6      /* refraction: a leg's crossing point did not converge within
+                                 the Newton step cap (the image is written; the terms of
+                                 such legs may carry a larger delay error)            */
 };
 
 /* Echo storage. Samples are complex, real part first.
@@ -126,6 +129,25 @@ typedef struct {
     double z_interface;     /* m, the interface depth (refract = 1)               */
 } sas_bp_swath_desc;
 
+/* Where the plan's tiling comes from (sas_bp_options.tune_mode).
+ *   DEFAULT : the explicit tile fields, else the automatic choice; sas_bp_autotune
+ *             returns a stored choice for the shape class when there is one
+ *             (process cache, then the tune_cache file) and times otherwise.
+ *   CACHED  : sas_bp_plan takes the tiling stored for the plan's shape class
+ *             (process cache, then the tune_cache file) in place of the tile
+ *             and chunk fields, or the automatic choice when none is stored;
+ *             sas_bp_autotune as for DEFAULT.
+ *   SEARCH  : sas_bp_autotune always times the candidates and replaces the
+ *             stored choice; sas_bp_plan as for CACHED.
+ * A shape class is the GPU architecture, echo dtype, interpolator, motion
+ * and propagation models, 2D/3D, gate on/off, and the largest element count,
+ * window length and total pixels in power-of-two buckets. */
+enum sas_bp_tune_mode {
+    SAS_BP_TUNE_DEFAULT = 0,
+    SAS_BP_TUNE_CACHED = 1,
+    SAS_BP_TUNE_SEARCH = 2
+};
+
 /* Plan options; a NULL options pointer selects every default. */
 typedef struct {
     int32_t device;          /* HIP device ordinal                             */
@@ -138,6 +160,17 @@ typedef struct {
                                 below n_elem (part of a ping; overrides pings_per_chunk
                                 for the image, not the adjoint); 0 = automatic */
     size_t workspace_limit;  /* bytes; 0 = unlimited                           */
+    int32_t tune_mode;       /* enum sas_bp_tune_mode                          */
+    int32_t no_cull;         /* 1: no block culling (Sec. II-C): every ping of every tile
+                                is visited and every (ping, element) is gated pixel row by
+                                pixel row, as in a per-pixel field-of-view test. The image
+                                is the same as with the cull (bitwise); this exists to show
+                                that, and costs the time the cull saves. 0 = cull. */
+    const char* tune_cache;  /* path of the tuning cache (JSON) that sas_bp_autotune
+                                writes and CACHED / SEARCH plans read; NULL = the
+                                process cache only. The file is rewritten whole (through
+                                a temporary file and a rename) when a search stores a
+                                choice; a file that cannot be read counts as empty. */
 } sas_bp_options;
 
 /* Device pointers for one swath. All must be device memory. */
@@ -364,8 +397,9 @@ int sas_bp_tvg(sas_bp_plan_t plan, int swath, void* echo, double alpha, float* g
 int sas_bp_drc(sas_bp_plan_t plan, const void* image, int64_t n_pix, double brightness, float* out,
                double* params, void* stream);
 
-/* Sticky device-detected status of the plan (SAS_BP_OK or SAS_BP_ENAV);
- * synchronises with the device and clears it. */
+/* Sticky device-detected status of the plan (SAS_BP_OK, SAS_BP_ENAV, or
+ * SAS_BP_ECONVERGE when no navigation fault was seen); synchronises with the
+ * device and clears it. */
 int sas_bp_plan_status(sas_bp_plan_t plan);
 
 /* Chosen tiling, for reporting: tile_x, tile_y, tile_z, pings_per_chunk
@@ -382,13 +416,33 @@ int sas_bp_plan_info(sas_bp_plan_t plan, int64_t info[10]);
  * are overwritten) on `stream`: one warm-up and `reps` timed launches each,
  * measured with HIP events. Writes the fastest candidate's options to *best
  * (device and workspace_limit copied from `base`, which may be NULL) and its
- * mean time to *best_ms (host memory). The choice is cached for the process
- * per shape class (2D/3D, echo dtype, gate on/off, largest element count,
- * window length and total pixels, each in power-of-two buckets): a later call
- * for the same class returns it without timing, with *best_ms = 0.
+ * mean time to *best_ms (host memory). The choice is stored per shape class
+ * (see sas_bp_tune_mode) in the process cache and, when base->tune_cache is
+ * set, in that file: unless base->tune_mode is SEARCH, a later call for the
+ * same class, in this process or (through the file) in another, returns it
+ * without timing, with *best_ms = 0. The returned options carry tune_mode
+ * DEFAULT and base's device, workspace_limit, no_cull and tune_cache.
  * Synchronous; creates and destroys one plan per candidate. */
 int sas_bp_autotune(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_swath_io* io,
                     const sas_bp_options* base, int reps, void* stream, sas_bp_options* best, double* best_ms);
+
+/* The block-cull predicates of the image kernels (Sec. II-C: a block of pixels
+ * is kept for a ping when its pixels may lie inside the beam; Sec. III-B: the
+ * transmitter and each receiver are tested as separate apexes), evaluated on
+ * the host for one cone apex and one axis-aligned box of pixel centres
+ * [box_lo, box_hi] (metres). The cone is |x - apex_x| <= tan(half_angle) rho,
+ * rho the (y, z) distance to the apex, which is the gate |dx| <= sin(half_angle)
+ * |p - apex| rearranged. Writes
+ *   *record_class : 0 every point of the box is outside the cone, 1 every point
+ *                   is inside, 2 neither can be shown (decided per pixel row);
+ *                   the class each (tile, ping, element) record gets;
+ *   *may_hit      : 0 only if no point of the box is inside (the per-(tile, ping)
+ *                   test of the cull pass; a conservative superset of class != 0).
+ * Both are exact for the box: a box that the beam crosses without holding any
+ * of the box's corners is class 2 and may_hit 1. half_angle in (0, pi/2).
+ * Host only; needs no device. */
+int sas_bp_gate_class(const double apex[3], const double box_lo[3], const double box_hi[3], double half_angle,
+                      int32_t* record_class, int32_t* may_hit);
 
 /* Per-launch timing of the main kernel, for measuring it against its
  * roofline. With enable != 0, sas_bp_image and sas_bp_adjoint enqueue their

@@ -52,7 +52,6 @@ The gate is held constant and the slope is that of the segment containing u.
 from __future__ import annotations
 
 import math
-import multiprocessing as mp
 import os
 
 import numpy as np
@@ -178,14 +177,12 @@ def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear", vel=None,
     return acc, count
 
 
-_SHARED = {}
-
-
 def _worker(args):
-    lo, hi = args
-    s = _SHARED
-    return _bp_chunk(s["echo"], s["tx"], s["rx"], s["c"], s["fc"], s["fs"], s["t0"],
-                     s["pts"][lo:hi], s["gate"], s["interp"], s["vel"], s["refr"])
+    specs, sc, lo, hi = args
+    from . import pool
+    a = pool.attach(specs)
+    return _bp_chunk(a["echo"], a["tx"], a["rx"], sc["c"], sc["fc"], sc["fs"], sc["t0"],
+                     a["pts"][lo:hi], sc["gate"], sc["interp"], a["vel"], sc["refr"])
 
 
 def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
@@ -193,14 +190,18 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
     """Backprojected complex values at arbitrary points [N,3] (float64 in, complex128 out).
 
     echo: complex [P,E,N_s]; tx: [P,3]; rx: [P,E,3]; gate_half_angle in radians
-    (0 = no gate). ``workers`` > 1 splits the points over forked processes.
+    (0 = no gate). ``workers`` > 1 splits the points over the worker pool of
+    ``oracle.pool`` (arrays passed through shared memory).
     ``interp`` = "linear" (the definition above) or "sinc": the interpolation
     variant L = sum over the 2 SINC_HALF samples m around u of E~[m] h(u - m),
     h the Hann-windowed sinc of ``sinc_kernel``. ``rx_vel`` ([P, 3], m/s)
     selects continuous receiver motion (``motion_delay``); ``refraction``
     = (c_sed, z_int) the sediment interface (``refracted_leg``).
     """
-    echo = np.ascontiguousarray(np.asarray(echo).astype(np.complex128, copy=False))
+    echo = np.asarray(echo)
+    if echo.dtype not in (np.complex64, np.complex128):   # complex64 samples convert exactly per tap
+        echo = echo.astype(np.complex128)
+    echo = np.ascontiguousarray(echo)
     tx = np.asarray(tx, dtype=np.float64)
     rx = np.asarray(rx, dtype=np.float64)
     pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
@@ -216,12 +217,11 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
             out[lo:hi] = v
             total += cnt
     else:
-        _SHARED.update(echo=echo, tx=tx, rx=rx, c=float(c), fc=fc, fs=fs, t0=t0, pts=pts,
-                       gate=gate_half_angle, interp=interp, vel=vel, refr=refraction)
-        ctx = mp.get_context("fork")
-        with ctx.Pool(workers) as pool:
-            res = pool.map(_worker, spans, chunksize=1)
-        _SHARED.clear()
+        from . import pool
+        workers_pool, _ = pool.get()
+        sc = dict(c=float(c), fc=fc, fs=fs, t0=t0, gate=gate_half_angle, interp=interp, refr=refraction)
+        with pool.Shared(echo=echo, tx=tx, rx=rx, pts=pts, vel=vel) as sh:
+            res = workers_pool.map(_worker, [(sh.specs, sc, lo, hi) for lo, hi in spans], chunksize=1)
         for (lo, hi), (v, cnt) in zip(spans, res):
             out[lo:hi] = v
             total += cnt
@@ -429,10 +429,3 @@ def sharpness_cotangent(img) -> np.ndarray:
     A = (m2 ** 2).sum()
     B = m2.sum()
     return 4.0 * I * (m2 / B ** 2 - A / B ** 3)
-
-
-def default_workers() -> int:
-    try:
-        return len(os.sched_getaffinity(0))
-    except AttributeError:  # pragma: no cover
-        return os.cpu_count() or 1

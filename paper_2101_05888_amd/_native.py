@@ -12,16 +12,17 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsas_bp.so")
 
-SAS_BP_OK, SAS_BP_EINVAL, SAS_BP_EUNSUPPORTED, SAS_BP_ENOMEM, SAS_BP_EDEVICE, SAS_BP_ENAV = range(6)
+SAS_BP_OK, SAS_BP_EINVAL, SAS_BP_EUNSUPPORTED, SAS_BP_ENOMEM, SAS_BP_EDEVICE, SAS_BP_ENAV, SAS_BP_ECONVERGE = range(7)
 ECHO_C64, ECHO_F16X2, ECHO_BF16X2 = 0, 1, 2
 INTERP_LINEAR, INTERP_SINC8 = 0, 1
+TUNE_DEFAULT, TUNE_CACHED, TUNE_SEARCH = 0, 1, 2
 
 EXPORTED = (
     "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image", "sas_bp_adjoint", "sas_bp_reproject",
     "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_drc", "sas_bp_tvg", "sas_bp_whiten",
     "sas_bp_range_compress", "sas_bp_dpc_tde", "sas_bp_dpc_footprints", "sas_bp_dpc_residual",
     "sas_bp_dpc_solve", "sas_bp_plan_status", "sas_bp_plan_info",
-    "sas_bp_autotune", "sas_bp_set_kernel_timing", "sas_bp_kernel_time", "sas_bp_destroy", "sas_bp_error_string",
+    "sas_bp_autotune", "sas_bp_gate_class", "sas_bp_set_kernel_timing", "sas_bp_kernel_time", "sas_bp_destroy", "sas_bp_error_string",
     "sas_bp_last_error_detail", "sas_bp_abi_version",
 )
 
@@ -41,7 +42,8 @@ class Options(C.Structure):
     _fields_ = [
         ("device", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
         ("pings_per_chunk", C.c_int32), ("threads", C.c_int32), ("use_graph", C.c_int32),
-        ("elems_per_chunk", C.c_int32), ("workspace_limit", C.c_size_t),
+        ("elems_per_chunk", C.c_int32), ("workspace_limit", C.c_size_t), ("tune_mode", C.c_int32),
+        ("no_cull", C.c_int32), ("tune_cache", C.c_char_p),
     ]
 
 
@@ -88,6 +90,8 @@ def _load():
     lib.sas_bp_plan_info.argtypes = [P, C.POINTER(C.c_int64)]
     lib.sas_bp_autotune.argtypes = [C.POINTER(SwathDesc), C.c_int, C.POINTER(SwathIO), C.POINTER(Options), C.c_int,
                                     P, C.POINTER(Options), C.POINTER(C.c_double)]
+    D3 = C.POINTER(C.c_double)
+    lib.sas_bp_gate_class.argtypes = [D3, D3, D3, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.sas_bp_set_kernel_timing.argtypes = [P, C.c_int]
     lib.sas_bp_kernel_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.sas_bp_destroy.argtypes = [P]

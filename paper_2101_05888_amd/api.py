@@ -20,6 +20,7 @@ from ._native import check
 
 ECHO_DTYPES = {"c64": N.ECHO_C64, "f16": N.ECHO_F16X2, "bf16": N.ECHO_BF16X2}
 INTERPS = {"linear": N.INTERP_LINEAR, "sinc8": N.INTERP_SINC8}
+TUNE_MODES = {"default": N.TUNE_DEFAULT, "cached": N.TUNE_CACHED, "search": N.TUNE_SEARCH}
 
 
 def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin: Sequence[float],
@@ -49,8 +50,13 @@ def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin
 
 
 def _options(device=0, tile=(0, 0, 0), pings_per_chunk=0, use_graph=True, workspace_limit=0,
-             threads=0, elems_per_chunk=0) -> N.Options:
+             threads=0, elems_per_chunk=0, tune_mode="default", no_cull=False, tune_cache=None) -> N.Options:
+    if tune_mode not in TUNE_MODES:
+        raise ValueError(f"tune_mode must be one of {sorted(TUNE_MODES)}")
     o = N.Options()
+    o.tune_mode = TUNE_MODES[tune_mode]
+    o.no_cull = 1 if no_cull else 0
+    o.tune_cache = None if tune_cache is None else str(tune_cache).encode()
     o.device = int(device)
     o.tile_x, o.tile_y, o.tile_z = (int(v) for v in tile)
     o.pings_per_chunk = int(pings_per_chunk)
@@ -93,20 +99,27 @@ class Plan:
 
 def sas_bp_plan(descs: Sequence[N.SwathDesc], device: int = 0, tile=(0, 0, 0), pings_per_chunk: int = 0,
                 use_graph: bool = True, workspace_limit: int = 0, threads: int = 0,
-                elems_per_chunk: int = 0) -> Plan:
+                elems_per_chunk: int = 0, tune_mode: str = "default", no_cull: bool = False,
+                tune_cache=None) -> Plan:
+    """``tune_mode`` "cached" or "search" takes the tiling stored for the shape
+    class (process cache, then the ``tune_cache`` file); ``no_cull`` turns the
+    block cull off (every ping of every tile, every record gated per row)."""
     descs = list(descs)
     arr = (N.SwathDesc * len(descs))(*descs)
-    opt = _options(device, tile, pings_per_chunk, use_graph, workspace_limit, threads, elems_per_chunk)
+    opt = _options(device, tile, pings_per_chunk, use_graph, workspace_limit, threads, elems_per_chunk,
+                   tune_mode, no_cull, tune_cache)
     out = C.c_void_p()
     check(N.lib().sas_bp_plan(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_plan")
     return Plan(out.value, descs, device)
 
 
 def sas_bp_workspace_size(descs: Sequence[N.SwathDesc], tile=(0, 0, 0), pings_per_chunk: int = 0,
-                          threads: int = 0, elems_per_chunk: int = 0) -> int:
+                          threads: int = 0, elems_per_chunk: int = 0, tune_mode: str = "default",
+                          no_cull: bool = False, tune_cache=None) -> int:
     descs = list(descs)
     arr = (N.SwathDesc * len(descs))(*descs)
-    opt = _options(0, tile, pings_per_chunk, threads=threads, elems_per_chunk=elems_per_chunk)
+    opt = _options(0, tile, pings_per_chunk, threads=threads, elems_per_chunk=elems_per_chunk,
+                   tune_mode=tune_mode, no_cull=no_cull, tune_cache=tune_cache)
     out = C.c_size_t()
     check(N.lib().sas_bp_workspace_size(arr, len(descs), C.byref(opt), C.byref(out)), "sas_bp_workspace_size")
     return int(out.value)
@@ -381,15 +394,16 @@ def sas_bp_sharpness(plan: Plan, image: torch.Tensor, out_S: torch.Tensor,
 
 
 def sas_bp_autotune(descs: Sequence[N.SwathDesc], bufs: Sequence[SwathBuffers], reps: int = 3, device: int = 0,
-                    stream=None) -> dict:
+                    stream=None, tune_mode: str = "default", tune_cache=None, no_cull: bool = False) -> dict:
     """Fastest tiling for these swaths, timed on their buffers (images are
     overwritten). Returns ``sas_bp_plan`` keyword arguments (tile, threads,
     pings_per_chunk, elems_per_chunk) plus ``ms``, the mean image time (0 when
-    the choice came from the process cache)."""
+    the choice came from the process cache or the ``tune_cache`` file;
+    ``tune_mode`` "search" always times)."""
     descs = list(descs)
     arr = (N.SwathDesc * len(descs))(*descs)
     io = _io_for(descs, device, bufs)
-    base = _options(device)
+    base = _options(device, tune_mode=tune_mode, no_cull=no_cull, tune_cache=tune_cache)
     best = N.Options()
     ms = C.c_double()
     check(N.lib().sas_bp_autotune(arr, len(descs), io, C.byref(base), int(reps), _stream(device, stream),
@@ -397,6 +411,16 @@ def sas_bp_autotune(descs: Sequence[N.SwathDesc], bufs: Sequence[SwathBuffers], 
     return {"tile": (best.tile_x, best.tile_y, best.tile_z), "threads": best.threads,
             "pings_per_chunk": best.pings_per_chunk, "elems_per_chunk": best.elems_per_chunk,
             "ms": float(ms.value)}
+
+
+def sas_bp_gate_class(apex, box_lo, box_hi, half_angle: float) -> tuple:
+    """(record class, may_hit) of the block cull for one cone apex and one box
+    of pixel centres (host only): class 0 outside, 1 inside, 2 decided per row."""
+    D3 = C.c_double * 3
+    a, lo, hi = (D3(*(float(v) for v in x)) for x in (apex, box_lo, box_hi))
+    cls, hit = C.c_int32(), C.c_int32()
+    check(N.lib().sas_bp_gate_class(a, lo, hi, float(half_angle), C.byref(cls), C.byref(hit)), "sas_bp_gate_class")
+    return int(cls.value), int(hit.value)
 
 
 def sas_bp_set_kernel_timing(plan: Plan, enable: bool) -> None:

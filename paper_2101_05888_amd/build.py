@@ -18,7 +18,6 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsas_bp.so")
 SOURCES = ["plan.hip", "tdbp_image.hip", "tdbp_adjoint.hip", "tdbp_reproject.hip", "tdbp_drc.hip", "tdbp_tvg.hip", "tdbp_whiten.hip", "tdbp_rangec.hip", "tdbp_dpc.hip", "tdbp_refract.hip"]
-PROBE = os.path.join(HERE, "issue_probe")   # VALU issue-rate microbenchmark (standalone program)
 ARCH = os.environ.get("SAS_BP_ARCH", "gfx950")
 
 
@@ -62,13 +61,8 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
-    cmd = [hipcc(), *flags(), os.path.join(CSRC, "issue_probe.hip"), "-o", PROBE + ".tmp"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"probe build failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(PROBE + ".tmp", PROBE)
     if verbose:
-        print(f"built {LIB} and {PROBE}")
+        print(f"built {LIB}")
     return LIB
 
 

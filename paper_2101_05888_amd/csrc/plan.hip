@@ -24,6 +24,7 @@
 
 #include "sas_bp.h"
 #include "tdbp_dev.h"
+#include "tdbp_geom.h"
 
 namespace sasbp {
 typedef void (*ImageKernelFn)(Workspace, const SwathDev*, const int*, const int*, const PingRange*, int);
@@ -126,6 +127,7 @@ struct SwathPlan {
   sas_bp_swath_desc d;
   int ntx, nty, ntz, ntiles, tile0;
   int W, CP, RC, SC;
+  int no_cull;
   double half_diag, c_min;
 };
 
@@ -192,6 +194,7 @@ struct sas_bp_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   bool timing = false;
+  bool tuned_from_cache = false;   // the tiling came from the tuning cache
   std::vector<hipEvent_t> events;  // pairs bracketing the main kernel
   size_t n_timed = 0;              // pairs recorded since the last read
 };
@@ -292,6 +295,7 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
   for (int i = 0; i < n; ++i) {
     SwathPlan s;
     s.d = d[i];
+    s.no_cull = (o && o->no_cull) ? 1 : 0;
     s.ntx = (int)((d[i].n[0] + t.TX - 1) / t.TX);
     s.nty = (int)((d[i].n[1] + t.TY - 1) / t.TY);
     s.ntz = (int)((d[i].n[2] + t.TZ - 1) / t.TZ);
@@ -406,6 +410,7 @@ SwathDev make_dev(const SwathPlan& s) {
   v.interp = s.d.interp;
   v.motion = s.d.motion;
   v.refract = s.d.refract;
+  v.no_cull = s.no_cull;
   v.c_sed = s.d.refract ? s.d.c_sediment : 0.0;
   v.z_int = s.d.refract ? s.d.z_interface : 0.0;
   v.nx = (int)s.d.n[0];
@@ -566,6 +571,9 @@ int plan_sizes(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, Ti
                std::vector<SwathPlan>* sw, int* n_tiles, Layout* lay) {
   if (!desc) return fail(SAS_BP_EINVAL, "desc is NULL");
   if (n < 1 || n > 4096) return fail(SAS_BP_EINVAL, "n_swaths must be in [1, 4096]");
+  if (o && (o->tune_mode < SAS_BP_TUNE_DEFAULT || o->tune_mode > SAS_BP_TUNE_SEARCH))
+    return fail(SAS_BP_EINVAL, "tune_mode must be DEFAULT, CACHED or SEARCH");
+  if (o && o->no_cull != 0 && o->no_cull != 1) return fail(SAS_BP_EINVAL, "no_cull must be 0 or 1");
   for (int i = 0; i < n; ++i) {
     int rc = validate(&desc[i], i);
     if (rc) return rc;
@@ -594,18 +602,196 @@ int plan_sizes(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, Ti
 
 }  // namespace
 
-// Autotuner cache (process-wide), keyed by shape class.
+// Tuning cache, keyed by shape class: a process-wide map, and optionally a
+// JSON file shared between processes.
 namespace {
 
-typedef std::tuple<int, int, int, int, int, int> TuneKey;   // 3D, dtype, gate, E, W, pixels (log2 buckets)
-
 std::mutex g_tune_mutex;
-std::map<TuneKey, sas_bp_options> g_tune_cache;
+std::map<std::string, sas_bp_options> g_tune_cache;
 
 int log2_bucket(long long v) {
   int b = 0;
   while (v > 1) { v >>= 1; ++b; }
   return b;
+}
+
+// The shape class of these swaths on `device` (see sas_bp_tune_mode), from the
+// automatic tiling's window lengths.
+int shape_class(const sas_bp_swath_desc* desc, int n, int device, std::string* key) {
+  Tiling t;
+  std::vector<SwathPlan> sw;
+  int n_tiles = 0;
+  Layout lay;
+  int rc = plan_sizes(desc, n, nullptr, &t, &sw, &n_tiles, &lay);
+  if (rc) return rc;
+  bool any3d = false, gate = false;
+  int E = 0, W = 0;
+  long long pix = 0;
+  for (const auto& s : sw) {
+    any3d |= s.d.n[2] > 1;
+    gate |= s.d.gate_half_angle > 0.0;
+    E = std::max(E, s.d.n_elem);
+    W = std::max(W, s.W);
+    pix += s.d.n[0] * s.d.n[1] * s.d.n[2];
+  }
+  std::string arch = "unknown";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  } else {
+    (void)hipGetLastError();
+  }
+  static const char* kDtype[] = {"c64", "f16", "bf16"};
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s|%s|%s|interp%d|motion%d|refract%d|%s|e%d|w%d|p%d", arch.c_str(),
+           any3d ? "3d" : "2d", kDtype[sw[0].d.echo_dtype], sw[0].d.interp, sw[0].d.motion, sw[0].d.refract,
+           gate ? "gate" : "nogate", log2_bucket(E), log2_bucket(W), log2_bucket(pix));
+  *key = buf;
+  return SAS_BP_OK;
+}
+
+// Fields of a tiling stored in the cache.
+const char* kTuneFields[] = {"tile_x", "tile_y", "tile_z", "threads", "pings_per_chunk", "elems_per_chunk"};
+
+int32_t* tune_field(sas_bp_options* o, int i) {
+  int32_t* f[] = {&o->tile_x, &o->tile_y, &o->tile_z, &o->threads, &o->pings_per_chunk, &o->elems_per_chunk};
+  return f[i];
+}
+
+struct TuneEntry {
+  std::string key;
+  sas_bp_options opt;
+  double ms;
+};
+
+// Entries of a cache file written by write_tune_file: one object per entry,
+// {"class": "...", "tile_x": 64, ..., "ms": 21.9}. Anything unreadable is skipped.
+std::vector<TuneEntry> read_tune_file(const char* path) {
+  std::vector<TuneEntry> out;
+  FILE* f = fopen(path, "rb");
+  if (!f) return out;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 24)) text.append(buf, got);
+  fclose(f);
+  size_t pos = 0;
+  const std::string tag = "\"class\"";
+  while ((pos = text.find(tag, pos)) != std::string::npos) {
+    const size_t end = text.find('}', pos);
+    if (end == std::string::npos) break;
+    const std::string obj = text.substr(pos, end - pos);
+    pos = end;
+    const size_t colon0 = obj.find(':');
+    if (colon0 == std::string::npos) continue;
+    const size_t q0 = obj.find('"', colon0 + 1);
+    if (q0 == std::string::npos) continue;
+    const size_t q1 = obj.find('"', q0 + 1);
+    if (q1 == std::string::npos) continue;
+    TuneEntry e;
+    e.key = obj.substr(q0 + 1, q1 - q0 - 1);
+    std::memset(&e.opt, 0, sizeof e.opt);
+    e.ms = 0.0;
+    bool ok = true;
+    for (int i = 0; i < 6 && ok; ++i) {
+      const std::string k = std::string("\"") + kTuneFields[i] + "\"";
+      const size_t at = obj.find(k);
+      if (at == std::string::npos) { ok = false; break; }
+      const size_t colon = obj.find(':', at + k.size());
+      if (colon == std::string::npos) { ok = false; break; }
+      char* stop = nullptr;
+      const long v = strtol(obj.c_str() + colon + 1, &stop, 10);
+      if (stop == obj.c_str() + colon + 1 || v < 0 || v > 1 << 20) { ok = false; break; }
+      *tune_field(&e.opt, i) = (int32_t)v;
+    }
+    const size_t at = obj.find("\"ms\"");
+    if (at != std::string::npos) {
+      const size_t colon = obj.find(':', at);
+      if (colon != std::string::npos) e.ms = strtod(obj.c_str() + colon + 1, nullptr);
+    }
+    if (ok) out.push_back(e);
+  }
+  return out;
+}
+
+bool write_tune_file(const char* path, const std::vector<TuneEntry>& entries) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return false;
+  fprintf(f, "{\"format\": \"sas_bp tuning cache\", \"version\": 1, \"entries\": [\n");
+  for (size_t i = 0; i < entries.size(); ++i) {
+    const TuneEntry& e = entries[i];
+    fprintf(f, "  {\"class\": \"%s\"", e.key.c_str());
+    for (int j = 0; j < 6; ++j)
+      fprintf(f, ", \"%s\": %d", kTuneFields[j], *tune_field(const_cast<sas_bp_options*>(&e.opt), j));
+    fprintf(f, ", \"ms\": %.6g}%s\n", e.ms, i + 1 < entries.size() ? "," : "");
+  }
+  fprintf(f, "]}\n");
+  const bool ok = fflush(f) == 0;
+  fclose(f);
+  return ok && rename(tmp.c_str(), path) == 0;
+}
+
+// Stored tiling for a class: the process cache, then the file.
+bool tune_lookup(const std::string& key, const char* path, sas_bp_options* out) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  auto it = g_tune_cache.find(key);
+  if (it != g_tune_cache.end()) {
+    *out = it->second;
+    return true;
+  }
+  if (!path) return false;
+  for (const TuneEntry& e : read_tune_file(path)) {
+    if (e.key == key) {
+      g_tune_cache[key] = e.opt;
+      *out = e.opt;
+      return true;
+    }
+  }
+  return false;
+}
+
+void tune_store(const std::string& key, const sas_bp_options& opt, double ms, const char* path) {
+  std::lock_guard<std::mutex> lock(g_tune_mutex);
+  sas_bp_options o;
+  std::memset(&o, 0, sizeof o);
+  for (int i = 0; i < 6; ++i) *tune_field(&o, i) = *tune_field(const_cast<sas_bp_options*>(&opt), i);
+  g_tune_cache[key] = o;
+  if (!path) return;
+  std::vector<TuneEntry> entries = read_tune_file(path);
+  bool found = false;
+  for (TuneEntry& e : entries) {
+    if (e.key == key) {
+      e.opt = o;
+      e.ms = ms;
+      found = true;
+    }
+  }
+  if (!found) entries.push_back(TuneEntry{key, o, ms});
+  (void)write_tune_file(path, entries);
+}
+
+// The options a plan is made with: for CACHED and SEARCH, the stored tiling of
+// the shape class replaces the tile and chunk fields (when one is stored).
+int resolve_options(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, sas_bp_options* out,
+                    bool* used) {
+  *used = false;
+  if (!o) return SAS_BP_OK;
+  *out = *o;
+  if (o->tune_mode != SAS_BP_TUNE_CACHED && o->tune_mode != SAS_BP_TUNE_SEARCH) return SAS_BP_OK;
+  std::string key;
+  int rc = shape_class(desc, n, o->device, &key);
+  if (rc) return rc;
+  sas_bp_options stored;
+  if (tune_lookup(key, o->tune_cache, &stored)) {
+    for (int i = 0; i < 6; ++i) *tune_field(out, i) = *tune_field(&stored, i);
+    *used = true;
+  } else {
+    for (int i = 0; i < 6; ++i) *tune_field(out, i) = 0;   // the automatic choice
+  }
+  return SAS_BP_OK;
 }
 
 }  // namespace
@@ -965,6 +1151,7 @@ const char* sas_bp_error_string(int status) {
     case SAS_BP_ENOMEM: return "out of device memory or over the workspace limit";
     case SAS_BP_EDEVICE: return "HIP runtime error";
     case SAS_BP_ENAV: return "non-finite navigation or sound speed below c_min";
+    case SAS_BP_ECONVERGE: return "a refracted leg's crossing did not converge within the step cap";
     default: return "unknown status";
   }
 }
@@ -974,11 +1161,16 @@ const char* sas_bp_last_error_detail(void) { return g_detail.c_str(); }
 int sas_bp_workspace_size(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_options* options,
                           size_t* bytes) {
   if (!bytes) return fail(SAS_BP_EINVAL, "bytes is NULL");
+  sas_bp_options ro;
+  bool cached = false;
+  int rc = resolve_options(desc, n_swaths, options, &ro, &cached);
+  if (rc) return rc;
+  if (options) options = &ro;
   Tiling t;
   std::vector<SwathPlan> sw;
   int n_tiles = 0;
   Layout lay;
-  int rc = plan_sizes(desc, n_swaths, options, &t, &sw, &n_tiles, &lay);
+  rc = plan_sizes(desc, n_swaths, options, &t, &sw, &n_tiles, &lay);
   if (rc) return rc;
   *bytes = lay.total;
   return SAS_BP_OK;
@@ -987,11 +1179,16 @@ int sas_bp_workspace_size(const sas_bp_swath_desc* desc, int n_swaths, const sas
 int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_options* options, sas_bp_plan_t* out) {
   if (!out) return fail(SAS_BP_EINVAL, "out is NULL");
   *out = nullptr;
+  sas_bp_options ro;
+  bool cached = false;
+  int rc = resolve_options(desc, n_swaths, options, &ro, &cached);
+  if (rc) return rc;
+  if (options) options = &ro;
   Tiling t;
   std::vector<SwathPlan> sw;
   int n_tiles = 0;
   Layout lay;
-  int rc = plan_sizes(desc, n_swaths, options, &t, &sw, &n_tiles, &lay);
+  rc = plan_sizes(desc, n_swaths, options, &t, &sw, &n_tiles, &lay);
   if (rc) return rc;
   if (options && options->workspace_limit && lay.total > options->workspace_limit)
     return fail(SAS_BP_ENOMEM, "workspace needs %zu bytes, limit is %zu", lay.total, options->workspace_limit);
@@ -1011,8 +1208,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->sw = sw;
   p->lay = lay;
   p->use_graph = options ? options->use_graph != 0 : true;
-  if (options && options->use_graph == 0) p->use_graph = false;
-  if (!options) p->use_graph = true;
+  p->tuned_from_cache = cached;
   p->dtype = sw[0].d.echo_dtype;
   p->interp = sw[0].d.interp;
   p->motion = sw[0].d.motion;
@@ -1513,7 +1709,8 @@ int sas_bp_plan_status(sas_bp_plan_t p) {
   HIP_TRY(hipMemcpy(&h, p->ws.counters + 1, sizeof h, hipMemcpyDeviceToHost));
   const unsigned z = 0;
   HIP_TRY(hipMemcpy(p->ws.counters + 1, &z, sizeof z, hipMemcpyHostToDevice));
-  return (h & kStatusNav) ? SAS_BP_ENAV : SAS_BP_OK;
+  if (h & kStatusNav) return SAS_BP_ENAV;
+  return (h & kStatusConverge) ? SAS_BP_ECONVERGE : SAS_BP_OK;
 }
 
 int sas_bp_plan_info(sas_bp_plan_t p, int64_t info[10]) {
@@ -1561,45 +1758,39 @@ int sas_bp_autotune(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_sw
                     const sas_bp_options* base, int reps, void* stream, sas_bp_options* best, double* best_ms) {
   if (!best || !best_ms) return fail(SAS_BP_EINVAL, "best or best_ms is NULL");
   if (reps < 1 || reps > 1000) return fail(SAS_BP_EINVAL, "reps must be in [1, 1000]");
+  if (base && (base->tune_mode < SAS_BP_TUNE_DEFAULT || base->tune_mode > SAS_BP_TUNE_SEARCH))
+    return fail(SAS_BP_EINVAL, "tune_mode must be DEFAULT, CACHED or SEARCH");
   // validate with the default tiling, and get the shape class
-  Tiling t0;
-  std::vector<SwathPlan> sw0;
-  int n_tiles0 = 0;
-  Layout lay0;
-  int rc = plan_sizes(desc, n_swaths, nullptr, &t0, &sw0, &n_tiles0, &lay0);
+  const int device = base ? base->device : 0;
+  std::string key;
+  int rc = shape_class(desc, n_swaths, device, &key);
   if (rc) return rc;
-  bool any3d = false, gate = false;
-  int E = 0, W = 0;
-  long long pix = 0;
-  for (const auto& s : sw0) {
-    any3d |= s.d.n[2] > 1;
-    gate |= s.d.gate_half_angle > 0.0;
-    E = std::max(E, s.d.n_elem);
-    W = std::max(W, s.W);
-    pix += s.d.n[0] * s.d.n[1] * s.d.n[2];
+  bool any3d = false;
+  int E = 0;
+  for (int i = 0; i < n_swaths; ++i) {
+    any3d |= desc[i].n[2] > 1;
+    E = std::max(E, desc[i].n_elem);
   }
-  const TuneKey key(any3d ? 1 : 0, sw0[0].d.echo_dtype, gate ? 1 : 0, log2_bucket(E), log2_bucket(W),
-                    log2_bucket(pix));
-  {
-    std::lock_guard<std::mutex> lock(g_tune_mutex);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      *best = it->second;
-      if (base) {
-        best->device = base->device;
-        best->workspace_limit = base->workspace_limit;
-      }
-      *best_ms = 0.0;
-      return SAS_BP_OK;
-    }
-  }
+  const char* path = base ? base->tune_cache : nullptr;
   sas_bp_options cand;
   std::memset(&cand, 0, sizeof cand);
   if (base) {
     cand.device = base->device;
     cand.workspace_limit = base->workspace_limit;
+    cand.no_cull = base->no_cull;
   }
   cand.use_graph = 1;
+  cand.tune_mode = SAS_BP_TUNE_DEFAULT;   // candidates are timed as given, never looked up
+  if (!base || base->tune_mode != SAS_BP_TUNE_SEARCH) {
+    sas_bp_options stored;
+    if (tune_lookup(key, path, &stored)) {
+      *best = cand;
+      for (int i = 0; i < 6; ++i) *tune_field(best, i) = *tune_field(&stored, i);
+      best->tune_cache = path;
+      *best_ms = 0.0;
+      return SAS_BP_OK;
+    }
+  }
   DeviceGuard guard(cand.device);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipEvent_t ea = nullptr, eb = nullptr;
@@ -1656,12 +1847,27 @@ int sas_bp_autotune(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_sw
     if (last_err != SAS_BP_OK) return last_err;
     return fail(SAS_BP_EUNSUPPORTED, "no tiling candidate fits these swaths");
   }
-  {
-    std::lock_guard<std::mutex> lock(g_tune_mutex);
-    g_tune_cache[key] = best_opt;
-  }
+  tune_store(key, best_opt, best_time, path);
   *best = best_opt;
+  best->tune_cache = path;
   *best_ms = best_time;
+  return SAS_BP_OK;
+}
+
+int sas_bp_gate_class(const double apex[3], const double box_lo[3], const double box_hi[3], double half_angle,
+                      int32_t* record_class, int32_t* may_hit) {
+  if (!apex || !box_lo || !box_hi || !record_class || !may_hit) return fail(SAS_BP_EINVAL, "NULL argument");
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(apex[a]) || !std::isfinite(box_lo[a]) || !std::isfinite(box_hi[a]))
+      return fail(SAS_BP_EINVAL, "apex and box must be finite");
+    if (box_lo[a] > box_hi[a]) return fail(SAS_BP_EINVAL, "box_lo[%d] > box_hi[%d]", a, a);
+  }
+  if (!(half_angle > 0.0) || !(half_angle < 1.5707963267948966))
+    return fail(SAS_BP_EINVAL, "half_angle must be in (0, pi/2)");
+  const double tg = std::tan(half_angle);
+  *record_class = gate_class(tg * tg, apex[0], apex[1], apex[2], box_lo[0], box_hi[0], box_lo[1], box_hi[1],
+                             box_lo[2], box_hi[2]);
+  *may_hit = cone_may_hit(tg, box_lo[0], box_hi[0], box_lo[1], box_hi[1], box_lo[2], box_hi[2], apex) ? 1 : 0;
   return SAS_BP_OK;
 }
 

@@ -52,6 +52,7 @@ struct SwathDev {
   int interp;             // 0 linear, 1 windowed sinc over 2 * kSincHalf samples
   int motion;             // 1: receivers move at vel during reception
   int refract;            // 1: sediment below z_int refracts the legs (sound speed c_sed)
+  int no_cull;            // 1: no block cull (every ping of every tile, every record decided per row)
   double c_sed, z_int;
   int nx, ny, nz;
   int ntx, nty, ntz;      // tiles per axis
@@ -130,6 +131,6 @@ __host__ __device__ inline int chunk_pings(int RC, int E) {
 constexpr int kBuckets = 64;
 constexpr int kPartial = 8;   // gR.xyz, gc, gT.xyz (element 0 only), pad
 
-enum : unsigned { kStatusOk = 0u, kStatusNav = 1u };
+enum : unsigned { kStatusOk = 0u, kStatusNav = 1u, kStatusConverge = 2u };
 
 }  // namespace sasbp

@@ -60,7 +60,7 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
 // closer is "partial" and decided per row.
 enum { kGateOut = 0, kGateIn = 1, kGatePartial = 2 };
 
-__device__ __forceinline__ int gate_class(double tan2, double x, double y, double z, double bx0, double bx1,
+__host__ __device__ inline int gate_class(double tan2, double x, double y, double z, double bx0, double bx1,
                                           double by0, double by1, double bz0, double bz1) {
   // squared form: out iff dxmin^2 > tan^2 rmax^2, in iff dxmax^2 <= tan^2 rmin^2
   const double dxmin = fmax(0.0, fmax(bx0 - x, x - bx1));
@@ -74,6 +74,21 @@ __device__ __forceinline__ int gate_class(double tan2, double x, double y, doubl
   if (dxmin * dxmin > tan2 * r2max * (1.0 + 1e-11) + 1e-18) return kGateOut;
   if (dxmax * dxmax <= tan2 * r2min * (1.0 - 1e-11) - 1e-18) return kGateIn;
   return kGatePartial;
+}
+
+// Coarser per-(tile, ping) form used by the cull pass, with the box given by
+// its pixel-centre extent [xa, xb] x [ya, yb] x [za, zb]: can any point of the
+// box lie inside the cone of apex X? Uses the smallest |dx| and the largest
+// rho over the box (each bounds its own coordinate, so the test is
+// conservative: it may keep a box whose points all lie outside, never the
+// reverse).
+__host__ __device__ inline bool cone_may_hit(double tan_g, double xa, double xb, double ya, double yb, double za,
+                                             double zb, const double* X) {
+  const double dxm = fmax(0.0, fmax(xa - X[0], X[0] - xb));
+  const double dy = fmax(fabs(ya - X[1]), fabs(yb - X[1]));
+  const double dz = fmax(fabs(za - X[2]), fabs(zb - X[2]));
+  const double rho = sqrt(dy * dy + dz * dz);
+  return dxm <= tan_g * rho * (1.0 + 1e-9) + 1e-9;
 }
 
 // Receiver record and window start for (ping p, element e) of the tile centred
@@ -323,6 +338,9 @@ __device__ __forceinline__ void build_geometry(const Geo& g, int* lpart, int* ln
     unsigned f = __float_as_uint(rec.q0.w);
     if (!gate_on) {
       f |= kFlagFull;
+    } else if (sw.no_cull) {
+      // no block classification: every record is decided row by row
+      if (!(f & kFlagSkip)) lpart[atomicAdd(lnpart, 1)] = r;
     } else {
       const double* T = sw.tx + (size_t)p * 3;
       const double* R = sw.rx + ((size_t)p * E + e) * 3;

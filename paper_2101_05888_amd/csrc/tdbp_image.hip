@@ -34,16 +34,8 @@ __global__ void init_kernel(Workspace ws) {
 // Conservative per-(tile, ping) test: can any pixel of the tile box lie inside
 // the transmit cone and the cone of some element, and can its delay fall in
 // the record? Keeps a superset of the exact set; the image kernel applies the
-// exact per-row test, so the cull never changes a pixel.
-__device__ __forceinline__ bool cone_may_hit(double tan_g, double xa, double xb, double ya, double yb,
-                                             double za, double zb, const double* X) {
-  const double dxm = fmax(0.0, fmax(xa - X[0], X[0] - xb));
-  const double dy = fmax(fabs(ya - X[1]), fabs(yb - X[1]));
-  const double dz = fmax(fabs(za - X[2]), fabs(zb - X[2]));
-  const double rho = sqrt(dy * dy + dz * dz);
-  return dxm <= tan_g * rho * (1.0 + 1e-9) + 1e-9;
-}
-
+// exact per-row test, so the cull never changes a pixel. With the cull off
+// (no_cull) every ping is kept.
 __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, int TY, int TZ, int bucket_shift) {
   const int t = blockIdx.x;
   const int s = __builtin_amdgcn_readfirstlane(ws.tile_swath[t]);
@@ -83,12 +75,13 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
         double reach = sw.interp == 1 ? (double)kSincHalf : 0.0;   // taps beyond the delay
         if (sw.motion) reach += vm * (dT + dR + 2.0 * sw.half_diag) / c * sw.fs / c + 1.0;
         // refracted legs are not straight: the record test is left to the kernel
-        const bool rec_e = sw.refract || ((uhi >= -2.0 - reach) && (ulo <= (double)sw.Ns + 1.0 + reach));
-        const bool gate_e = sw.tan_g > 0.0 ? cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, R) : true;
+        const bool rec_e = sw.refract || sw.no_cull ||
+                           ((uhi >= -2.0 - reach) && (ulo <= (double)sw.Ns + 1.0 + reach));
+        const bool gate_e = (sw.tan_g > 0.0 && !sw.no_cull) ? cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, R) : true;
         in_record |= rec_e && gate_e;
         rx_hit |= gate_e;
       }
-      if (sw.tan_g > 0.0) hit = cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, T) && rx_hit;
+      if (sw.tan_g > 0.0 && !sw.no_cull) hit = cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, T) && rx_hit;
       // non-finite navigation makes every comparison false; keep such pings so
       // that the image kernel can flag them
       const bool bad = !(isfinite(dT)) || !isfinite(vm);

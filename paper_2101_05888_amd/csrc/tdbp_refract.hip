@@ -16,7 +16,10 @@
 // share. The loop stops at the FP32 resolution of r or once the step s bounds
 // the time error f' s^2 / 2 of the point it came from below 1e-5 of the
 // shorter of the carrier and sampling periods (the point it returns is closer
-// still): about one step per wavefront, from five to eight cold. Legs to
+// still), in both cases only for a step small against the sediment leg: about
+// one step per wavefront, from five to eight cold. For faster sediment the
+// bracket's upper end is the critical crossing. A leg still unconverged after
+// the step cap sets the plan's SAS_BP_ECONVERGE status. Legs to
 // pixels at or above the interface are straight. The beam gate keeps straight lines.
 //
 // Precision: the crossing point by FP32 Newton steps, the leg times (square
@@ -47,16 +50,29 @@ __device__ __forceinline__ double sqrt_refined(double A) {
 // steps from the ratio q = r / D (in: a nearby leg's, out: this leg's) until
 // the time error bound falls below tt seconds, then the time at r evaluated in
 // FP64 (it is stationary in r, so the error of r reaches it only squared).
+//
+// The root lies in [0, D] and, when the sediment is faster (c_sed > c), also
+// below the critical crossing r_c = h1 c / sqrt(c_sed^2 - c^2): there f >= 0
+// (the water leg is at the critical angle, the sediment leg's sine is at most
+// one). rc_ratio = c / sqrt(c_sed^2 - c^2) (infinite for slower sediment).
+// Without that bound, a pixel just below the interface beyond the critical
+// distance starts near r = D, where the sediment leg is shorter than the step
+// and Newton steps stall at a point far from the root.
+// A step counts as converged only if it is small against the sediment leg b at
+// the point it left (a quarter of it), so that the local model behind both
+// stop tests holds over the step. A leg that has not converged after
+// kRefractNewton steps clears *conv.
 __device__ __forceinline__ double refracted_time(double dx, double dy, double dz, double h1, double h2, double inv_c,
-                                                 double inv_cs, float tt, float& q) {
+                                                 double inv_cs, float rc_ratio, float tt, float& q, bool& conv) {
   const double D2 = dx * dx + dy * dy;
   if (!(h2 > 0.0) || !(h1 > 0.0))   // pixel at or above the interface (or apex below it): straight
     return sqrt_refined(D2 + dz * dz) * inv_c;
   const double D = sqrt_refined(D2);   // enters the leg time at first order: kept to FP64 accuracy
   const float Df = (float)D, h1f = (float)h1, h2f = (float)h2, icf = (float)inv_c, icsf = (float)inv_cs;
-  float lo = 0.0f, hi = Df;
-  float r = fminf(fmaxf(q, 0.0f), 1.0f) * Df;   // a NaN ratio starts at 0
+  float lo = 0.0f, hi = fminf(Df, h1f * rc_ratio * (1.0f + 1e-6f));
+  float r = fminf(fmaxf(q * Df, 0.0f), hi);   // a NaN ratio starts at 0
   const float tol = 1e-6f * (Df + h1f + h2f);   // FP32 resolution of the crossing
+  bool done = false;
   for (int it = 0; it < kRefractNewton; ++it) {
     const float u = Df - r;
     const float ia = __builtin_amdgcn_rsqf(fmaf(r, r, h1f * h1f));
@@ -68,10 +84,11 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
     float rn = r - f * __builtin_amdgcn_rcpf(fp);
     rn = (rn >= lo && rn <= hi) ? rn : 0.5f * (lo + hi);   // a converged step may land on the bracket end
     const float st = fabsf(rn - r);
-    const bool done = st <= tol || 0.5f * fp * st * st <= tt;
+    done = st * ib <= 0.25f && (st <= tol || 0.5f * fp * st * st <= tt);
     r = rn;
     if (done) break;
   }
+  conv = conv && done;
   if (Df > 0.0f) q = r * __builtin_amdgcn_rcpf(Df);   // only the next leg's starting point
   const double rd = (double)r, ud = D - rd;
   return sqrt_refined(rd * rd + h1 * h1) * inv_c + sqrt_refined(ud * ud + h2 * h2) * inv_cs;
@@ -101,6 +118,8 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
     const double c = *sw.c;
     const double inv_c = 1.0 / c, inv_cs = 1.0 / sw.c_sed;
     const float tt = (float)(1e-5 / (sw.fc > sw.fs ? sw.fc : sw.fs));   // time error bound of a stopped solve (s)
+    const float rc_ratio = sw.c_sed > c ? (float)(c / sqrt(sw.c_sed * sw.c_sed - c * c)) : __builtin_inff();
+    bool conv = true;
     const PingRange pr = prange[t];
     // pixel centres (FP64)
     double px[K];
@@ -124,7 +143,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
         const double dx = px[k] - Tx, dy = py - Ty, dz = pz - Tz;
         const double h1 = sw.z_int - Tz, h2 = pz - sw.z_int;
         q[k] = (float)(h1 / (h1 + h2));   // straight-line crossing
-        tT[k] = refracted_time(dx, dy, dz, h1, h2, inv_c, inv_cs, tt, q[k]);
+        tT[k] = refracted_time(dx, dy, dz, h1, h2, inv_c, inv_cs, rc_ratio, tt, q[k], conv);
         gT[k] = true;
         if (GATE && sw.tan_g > 0.0) gT[k] = fabs(dx) <= sw.sin_g * sqrt(dx * dx + dy * dy + dz * dz);
       }
@@ -139,7 +158,8 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
           bool g = gT[k];
           if (GATE && sw.tan_g > 0.0) g = g && fabs(dx) <= sw.sin_g * sqrt(dx * dx + dy * dy + dz * dz);
           if (!g) continue;
-          const double tau = tT[k] + refracted_time(dx, dy, dz, sw.z_int - Rz, pz - sw.z_int, inv_c, inv_cs, tt, q[k]);
+          const double tau = tT[k] + refracted_time(dx, dy, dz, sw.z_int - Rz, pz - sw.z_int, inv_c, inv_cs,
+                                                    rc_ratio, tt, q[k], conv);
           const double u = (tau - sw.t0) * sw.fs;
           const double nf = floor(u);
           const float w = (float)(u - nf);
@@ -157,6 +177,7 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
       }
     }
     if (bad) atomicOr(&ws.counters[1], kStatusNav);
+    if (!conv) atomicOr(&ws.counters[1], kStatusConverge);
     if (iy < sw.ny && iz < sw.nz) {
       float2* out = sw.image + ((size_t)iz * sw.ny + iy) * (size_t)sw.nx;
 #pragma unroll

@@ -4,9 +4,10 @@ Conventions (Sec. II-B, NED frame): x is along-track, y is ground range to
 starboard, z points down. The origin lies on the seafloor below the first ping,
 so a platform at altitude h sits at z = -h. A pixel centre is
 ``origin + index * spacing`` on every axis, evaluated in FP64 as one product
-followed by one sum. Positions are stop-and-hop: the transmitter and every
-receiver are fixed for the duration of a ping (the paper's continuous receive
-motion, Eq. 1, is not modelled).
+followed by one sum. Positions are stop-and-hop by default: the transmitter
+and every receiver are fixed for the duration of a ping. Continuous receiver
+motion during reception (the x_RX(t) of Eq. 1) is available to the echo
+synthesis: ``synthesize_echo(..., rx_vel=receiver_velocity(scn))``.
 
 The five workloads follow the configurations the build is measured on:
 

@@ -11,6 +11,11 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU test")
+    # The oracle's worker processes are forked here, before anything in this
+    # process initialises the GPU runtime (collection below asks torch for a
+    # device); a process that holds GPU state never forks.
+    from oracle import pool
+    pool.start()
 
 
 def pytest_collection_modifyitems(config, items):

@@ -22,11 +22,9 @@ BF16_REL_L2, BF16_PHASE_MRAD = 5e-3, 100.0
 
 
 def workers() -> int:
-    try:
-        n = len(os.sched_getaffinity(0))
-    except AttributeError:  # pragma: no cover
-        n = os.cpu_count() or 1
-    return max(1, min(16, n))
+    """Workers of the oracle's pool (started by the test session before any GPU call)."""
+    from oracle import pool
+    return pool.default_workers()
 
 
 def desc_for(api, scn: Scenario, echo_dtype: str = "c64", c_min: float = 0.0, interp: str = "linear",
@@ -66,12 +64,38 @@ def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_sca
     return buf.image.cpu().numpy(), plan, buf
 
 
-def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None, interp="linear", rx_vel=None, refraction=None):
+def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None, interp="linear", rx_vel=None, refraction=None,
+                 chunk=4096):
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, index)
     return oracle.backproject(echo_np, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
-                              scn.gate_half_angle, workers=workers(),
+                              scn.gate_half_angle, workers=workers(), chunk=chunk,
                               interp="sinc" if interp == "sinc8" else interp, rx_vel=rx_vel, refraction=refraction)
+
+
+def volume_subset(scn: Scenario, count: int, seabed_z: float) -> np.ndarray:
+    """Seeded voxel subset (flat indices, sorted, unique) of a volume: half
+    drawn uniformly, a quarter from the seven voxel planes around the seabed
+    and a quarter from the outer tenth of the footprint on either horizontal
+    axis (large horizontal offsets from the array)."""
+    g = scn.grid
+    nx, ny, nz = (int(v) for v in g.n)
+    rng = scn.streams()["subset"]
+    uni = rng.choice(nx * ny * nz, count // 2, replace=False)
+    q = count // 4
+    kz = int(round((seabed_z - g.origin[2]) / g.spacing[2]))
+    zs = rng.integers(max(0, kz - 3), min(nz, kz + 4), q)
+    sea = (zs * ny + rng.integers(0, ny, q)) * nx + rng.integers(0, nx, q)
+    bx, by = max(1, nx // 10), max(1, ny // 10)
+    ex = rng.integers(0, 2 * bx, q)
+    ex = np.where(ex < bx, ex, nx - 2 * bx + ex)
+    ey = rng.integers(0, 2 * by, q)
+    ey = np.where(ey < by, ey, ny - 2 * by + ey)
+    on_x = rng.random(q) < 0.5
+    ix = np.where(on_x, ex, rng.integers(0, nx, q))
+    iy = np.where(on_x, rng.integers(0, ny, q), ey)
+    edge = (rng.integers(0, nz, q) * ny + iy) * nx + ix
+    return np.unique(np.concatenate([uni, sea, edge]).astype(np.int64))
 
 
 def report(name, img, ref):

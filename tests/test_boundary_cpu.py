@@ -27,9 +27,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_strings():
     from paper_2101_05888_amd import _native as N
-    assert N.lib().sas_bp_abi_version() == 4
-    for s in range(6):
-        assert N.lib().sas_bp_error_string(s)
+    assert N.lib().sas_bp_abi_version() == 5
+    for s in range(7):
+        assert N.lib().sas_bp_error_string(s) != b"unknown status"
     assert N.lib().sas_bp_error_string(99) == b"unknown status"
 
 
@@ -110,3 +110,47 @@ def test_product_path_has_no_oracle_or_cpu_fallback():
             src = open(os.path.join(pkg, fn)).read()
             assert "import oracle" not in src and "from oracle" not in src, fn
             assert "import synth" not in src and "from synth" not in src, fn
+
+
+def test_option_fields_are_checked_on_the_host():
+    import paper_2101_05888_amd as api
+    from paper_2101_05888_amd import _native as N
+    arr = (N.SwathDesc * 1)(_desc(api))
+    out = C.c_size_t()
+    for field, value in (("tune_mode", 3), ("tune_mode", -1), ("no_cull", 2)):
+        o = api.api._options()
+        setattr(o, field, value)
+        assert N.lib().sas_bp_workspace_size(arr, 1, C.byref(o), C.byref(out)) == N.SAS_BP_EINVAL, field
+    # no_cull changes nothing in the sizing
+    assert api.sas_bp_workspace_size([_desc(api)], no_cull=True) == api.sas_bp_workspace_size([_desc(api)])
+
+
+def test_cached_tiling_is_read_from_the_tune_file(tmp_path):
+    # On a host without a device the architecture in the shape class reads
+    # "unknown". A stored 32 x 32 tiling for this class replaces the automatic
+    # choice (16 x 32 for a 256 x 256 image) in a CACHED plan's sizing; a
+    # DEFAULT plan ignores it, and an unreadable or missing file counts as empty.
+    import paper_2101_05888_amd as api
+    d = _desc(api)
+    path = tmp_path / "tune.json"
+    # class: arch, 2D, FP32 echo, linear, stop-and-hop, straight paths, no
+    # gate, 8 elements (bucket 3), 65536 pixels (bucket 16); the window-length
+    # bucket depends on the automatic tile, so every bucket is stored
+    rows = ['  {"class": "unknown|2d|c64|interp0|motion0|refract0|nogate|e3|w%d|p16", "tile_x": 32, '
+            '"tile_y": 32, "tile_z": 1, "threads": 256, "pings_per_chunk": 2, "elems_per_chunk": 0, "ms": 1.5}' % w
+            for w in range(14)]
+    path.write_text('{"format": "sas_bp tuning cache", "version": 1, "entries": [\n' + ",\n".join(rows) + "\n]}\n")
+    auto = api.sas_bp_workspace_size([d])
+    tiled = api.sas_bp_workspace_size([d], tile=(32, 32, 1), threads=256, pings_per_chunk=2)
+    assert auto != tiled
+    # (first: a stored choice, once read, stays in the process cache)
+    bad = tmp_path / "bad.json"
+    bad.write_text("{not json")
+    assert api.sas_bp_workspace_size([d], tune_mode="cached", tune_cache=str(bad)) == auto
+    assert api.sas_bp_workspace_size([d], tune_mode="cached", tune_cache=str(tmp_path / "none.json")) == auto
+    assert api.sas_bp_workspace_size([d], tune_mode="cached", tune_cache=str(path)) == tiled
+    assert api.sas_bp_workspace_size([d], tune_mode="search", tune_cache=str(path)) == tiled
+    assert api.sas_bp_workspace_size([d], tune_mode="default", tune_cache=str(path)) == auto
+    # another class (a gated swath) finds nothing and keeps the automatic tiling
+    g = _desc(api, gate_half_angle=0.17)
+    assert api.sas_bp_workspace_size([g], tune_mode="cached", tune_cache=str(path)) == api.sas_bp_workspace_size([g])

@@ -1,20 +1,20 @@
 """The motion estimate (Eqs. 3-8) through the C ABI against the oracle: the
 Eq. 4 residuals and their derivatives on the GPU (against the oracle's
-residuals and its central differences), and the Levenberg-Marquardt solve
-(against the oracle's solve on the same problem, squared and Huber loss).
+residuals and its central differences), and the Levenberg-Marquardt solve,
+checked as a minimiser of the oracle's loss (Eq. 8), not as a copy of the
+oracle's iteration.
 
 Bounds: residuals within 1e-14 s (FP64 path differences); derivatives within
 1e-6 relative to their largest entry (central differences with a 1e-6 m/s
-step carry about that); solutions within 1e-8 m/s of the oracle's (2 nm
-over a ping interval) with losses equal to 1e-9: the oracle differentiates
-numerically and both stop at slightly different points of a nearly flat
-valley (the last ping's heave is held only by its own reception).
+step carry about that). The solve: its loss, evaluated by the oracle, at most
+1e-9 above the oracle solve's, and the oracle loss's gradient at the GPU
+solution below 1e-3 of the data term's (the two cancel at a minimiser).
 """
 import numpy as np
 import pytest
 
 from oracle import dpc
-from tests.test_oracle_dpc_motion import _problem
+from tests.test_oracle_dpc_motion import STATIONARY, _noisy_problem, _problem, loss_gradients
 
 pytestmark = pytest.mark.gpu
 
@@ -65,18 +65,22 @@ def test_residuals_and_derivatives_match_oracle(api, P, K):
     assert err < 1e-6
 
 
-@pytest.mark.parametrize("robust,outlier", [(False, False), (True, True), (False, True)])
-def test_solve_matches_oracle(api, robust, outlier):
-    kw, true = _problem(outlier=outlier)
+@pytest.mark.parametrize("robust", [False, True])
+def test_solve_reaches_the_minimum(api, robust):
+    kw, true = _noisy_problem(robust)
     P, K = true.shape[0], kw["t_ref"].size
     d = _desc(api, kw, P, K, robust)
     v, loss = api.sas_bp_dpc_solve(d, kw["vx"], kw["dt"], kw["lever_rx"], kw["pairs"], kw["t_ref"], kw["ps"],
                                    kw["delay"], kw["weights"], kw["z_dvl"], np.zeros_like(true))
+    lg = dpc.loss(v, robust=robust, **kw)
     vo, lo = dpc.solve(np.zeros_like(true), robust=robust, iters=60, **kw)
-    print(f"[dpc solve robust={robust} outlier={outlier}] |v - oracle| {np.abs(v - vo).max():.2e} m/s, "
-          f"|v - true| {np.abs(v - true).max():.2e} m/s, loss {loss:.6e} vs {lo:.6e}", flush=True)
-    assert np.abs(v - vo).max() < 1e-8
-    assert abs(loss - lo) <= 1e-9 * max(1.0, abs(lo))
+    g, gd = loss_gradients(kw, v, robust)
+    ratio = np.abs(g).max() / np.abs(gd).max()
+    print(f"[dpc solve robust={robust}] loss {lg:.9e} (native {loss:.9e}) vs oracle solve {lo:.9e}, "
+          f"|grad L| / |grad data| {ratio:.2e}, |v - oracle| {np.abs(v - vo).max():.2e} m/s", flush=True)
+    assert abs(loss - lg) <= 1e-9 * abs(lg)
+    assert lg <= lo * (1.0 + 1e-9)
+    assert ratio <= STATIONARY
 
 
 def test_solve_recovers_a_longer_track(api):

@@ -14,7 +14,8 @@ import torch
 
 import oracle
 from synth import make_config, synthesize_echo, subset_indices
-from tests.helpers import FP32_REL_L2, FP32_PHASE_MRAD, desc_for, buffers_for, gpu_image, oracle_image, report
+from tests.helpers import (FP32_REL_L2, FP32_PHASE_MRAD, desc_for, buffers_for, gpu_image, oracle_image, report,
+                           volume_subset)
 
 pytestmark = pytest.mark.gpu
 
@@ -46,6 +47,26 @@ def test_refraction_image_matches_oracle(api):
     # the case exercises the interface: straight-path imaging of this echo is far off
     straight = oracle_image(scn, echo.numpy()).reshape(img.shape)
     assert oracle.rel_l2(straight, ref) > 0.1
+
+
+@pytest.mark.parametrize("offset", [1e-5, 1e-4])
+def test_voxels_just_below_the_interface_beyond_the_critical_distance(api, offset):
+    # a voxel plane 1e-5 or 1e-4 m below a shallow interface (0.96 m under the
+    # array, sand at 1650 m/s: the critical crossing is 2.09 m out), pings up
+    # to 4 m away along the track: the sediment legs of that plane are almost
+    # horizontal and their crossing lies just inside the critical distance
+    print(f"case refraction near interface offset {offset}", flush=True)
+    scn = _scene(n_ping=80, nz=6, z0=0.9, seabed_z=0.96, n_seabed=200, n_surface=10, n_buried=6, bury_max=0.05)
+    refr = (1650.0, 0.96 - offset)
+    echo = synthesize_echo(scn, dtype=torch.complex64, refraction=refr)
+    img, plan, _ = gpu_image(api, scn, echo, refraction=refr)   # also asserts a clean status (every leg converged)
+    ref = oracle_image(scn, echo.numpy(), refraction=refr).reshape(img.shape)
+    r, ph = report(f"refraction near interface {offset}", img, ref)
+    plane = ref[3]
+    r3 = oracle.rel_l2(img[3], plane)
+    print(f"  the plane below the interface: rel_l2 {r3:.3e}", flush=True)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+    assert r3 <= FP32_REL_L2
 
 
 def test_gated_2d_with_an_interface(api):
@@ -81,10 +102,12 @@ def test_refraction_plans_refuse_other_paths(api):
         api.sas_bp_plan([desc_for(api, scn, refraction=(0.0, 5.5))])
 
 
-def test_full_size_volume_refraction_sampled(api):
+@pytest.fixture(scope="module")
+def full_volume(api):
     """The 3D workload at full size (256 pings x 64 receivers, 8192 samples,
-    512 x 512 x 128 voxels) with the sediment interface, in the default launch
-    configuration, on 48 seeded voxels."""
+    512 x 512 x 128 voxels) with the sediment interface, imaged once in the
+    default launch configuration; 4096 seeded voxels weighted towards the
+    seabed and large horizontal offsets are kept for the oracle."""
     print("case refraction c3 full size", flush=True)
     scn = make_config("c3", n_seabed=5000)
     echo = synthesize_echo(scn, device="cuda", dtype=torch.complex64, noise_on_device=True, refraction=REFR)
@@ -92,11 +115,23 @@ def test_full_size_volume_refraction_sampled(api):
     buf = buffers_for(api, scn, echo)
     api.sas_bp_image(plan, [buf])
     torch.cuda.synchronize()
-    assert plan.status() == 0
-    idx = subset_indices(scn, 48)
+    status = plan.status()
+    idx = volume_subset(scn, 4096, REFR[1])
     img = buf.image.reshape(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
     echo_np = echo.cpu().numpy()
     del echo, buf
-    ref = oracle_image(scn, echo_np, idx, refraction=REFR)
-    r, ph = report("refraction c3-full-subset", img, ref)
+    plan.destroy()
+    torch.cuda.empty_cache()
+    return scn, echo_np, idx, img, status
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_full_size_volume_refraction_sampled(full_volume, part):
+    # the oracle's voxels in four parts of about 1024 (its bisection per leg
+    # makes each part some 15 s of host time)
+    scn, echo_np, idx, img, status = full_volume
+    assert status == 0
+    sel = slice(part * idx.size // 4, (part + 1) * idx.size // 4)
+    ref = oracle_image(scn, echo_np, idx[sel], refraction=REFR, chunk=64)
+    r, ph = report(f"refraction c3-full-subset part {part} ({ref.size} voxels)", img[sel], ref)
     assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
