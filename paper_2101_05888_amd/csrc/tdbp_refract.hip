@@ -13,13 +13,14 @@
 // transmit leg starts from the straight-line crossing r = D h1 / (h1 + h2); its
 // receiver legs start from the crossing ratio r / D of the leg before (the
 // transmit leg, then the previous element), which neighbouring apexes nearly
-// share. The loop stops at the FP32 resolution of r or once the step s bounds
-// the time error f' s^2 / 2 of the point it came from below 1e-5 of the
-// shorter of the carrier and sampling periods (the point it returns is closer
-// still), in both cases only for a step small against the sediment leg: about
-// one step per wavefront, from five to eight cold. For faster sediment the
-// bracket's upper end is the critical crossing. A leg still unconverged after
-// the step cap sets the plan's SAS_BP_ECONVERGE status. Legs to
+// share. The loop stops once the travel-time error is below 1e-5 of the
+// shorter of the carrier and sampling periods, by a certified bound from the
+// convexity of the travel time or by the local model of a small Newton step
+// (details at refracted_time): about 1.3 steps per leg on the near-interface
+// scenes, up to about fifteen for pixels just below the interface at the
+// critical distance. For faster sediment the bracket's upper end is the
+// critical crossing. A leg still unconverged after the step cap sets the
+// plan's SAS_BP_ECONVERGE status. Legs to
 // pixels at or above the interface are straight. The beam gate keeps straight lines.
 //
 // Precision: the crossing point by FP32 Newton steps, the leg times (square
@@ -34,7 +35,7 @@
 
 namespace sasbp {
 
-constexpr int kRefractNewton = 8;   // most Newton steps per leg (most legs stop after two or three)
+constexpr int kRefractNewton = 24;  // most Newton steps per leg (most stop after one or two)
 
 // Square root of A >= 0 in FP64 from the FP32 reciprocal square root y and one
 // Newton step s + (A - s^2) y / 2 with s = A y: the relative error, about the
@@ -48,8 +49,18 @@ __device__ __forceinline__ double sqrt_refined(double A) {
 
 // One leg's travel time (FP64 result): the crossing distance r by FP32 Newton
 // steps from the ratio q = r / D (in: a nearby leg's, out: this leg's) until
-// the time error bound falls below tt seconds, then the time at r evaluated in
-// FP64 (it is stationary in r, so the error of r reaches it only squared).
+// the time error is below tt seconds, then the time at r evaluated in FP64
+// (it is stationary in r, so the error of r reaches it only squared).
+//
+// Stop tests. The travel time t(r) is convex (t' = f, f' > 0), so at any r
+//     t(r) - t(r*) <= |f(r)| |r - r*| <= f(r)^2 / m,
+// m a lower bound of f' between r and the root r*; the water leg's curvature
+// h1^2 / (c a^3) is one, smallest where a is largest: at r when the root lies
+// below r (f > 0), at r = D otherwise. A leg stops when f^2 <= tt m there
+// (certified), or when a Newton step s is small against the sediment leg b
+// at the point it left (s <= b / 4, so that the local model holds over the
+// step) and either bounds the time error f' s^2 / 2 below tt or reaches the
+// FP32 resolution of r.
 //
 // The root lies in [0, D] and, when the sediment is faster (c_sed > c), also
 // below the critical crossing r_c = h1 c / sqrt(c_sed^2 - c^2): there f >= 0
@@ -57,11 +68,8 @@ __device__ __forceinline__ double sqrt_refined(double A) {
 // one). rc_ratio = c / sqrt(c_sed^2 - c^2) (infinite for slower sediment).
 // Without that bound, a pixel just below the interface beyond the critical
 // distance starts near r = D, where the sediment leg is shorter than the step
-// and Newton steps stall at a point far from the root.
-// A step counts as converged only if it is small against the sediment leg b at
-// the point it left (a quarter of it), so that the local model behind both
-// stop tests holds over the step. A leg that has not converged after
-// kRefractNewton steps clears *conv.
+// and Newton steps stall at a point far from the root. A leg that meets no
+// stop test within kRefractNewton steps clears *conv.
 __device__ __forceinline__ double refracted_time(double dx, double dy, double dz, double h1, double h2, double inv_c,
                                                  double inv_cs, float rc_ratio, float tt, float& q, bool& conv) {
   const double D2 = dx * dx + dy * dy;
@@ -69,28 +77,33 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
     return sqrt_refined(D2 + dz * dz) * inv_c;
   const double D = sqrt_refined(D2);   // enters the leg time at first order: kept to FP64 accuracy
   const float Df = (float)D, h1f = (float)h1, h2f = (float)h2, icf = (float)inv_c, icsf = (float)inv_cs;
+  const float h1s = h1f * h1f;
+  const float iaD = __builtin_amdgcn_rsqf(fmaf(Df, Df, h1s));
+  const float mD = h1s * iaD * iaD * iaD * icf;    // water-leg curvature at r = D (its smallest)
   float lo = 0.0f, hi = fminf(Df, h1f * rc_ratio * (1.0f + 1e-6f));
   float r = fminf(fmaxf(q * Df, 0.0f), hi);   // a NaN ratio starts at 0
   const float tol = 1e-6f * (Df + h1f + h2f);   // FP32 resolution of the crossing
   bool done = false;
   for (int it = 0; it < kRefractNewton; ++it) {
     const float u = Df - r;
-    const float ia = __builtin_amdgcn_rsqf(fmaf(r, r, h1f * h1f));
+    const float ia = __builtin_amdgcn_rsqf(fmaf(r, r, h1s));
     const float ib = __builtin_amdgcn_rsqf(fmaf(u, u, h2f * h2f));
     const float f = r * ia * icf - u * ib * icsf;
+    const float fw = h1s * ia * ia * ia * icf;
+    const bool cert = f * f <= tt * (f >= 0.0f ? fw : mD);   // certified: r stays
     lo = f < 0.0f ? r : lo;
     hi = f < 0.0f ? hi : r;
-    const float fp = h1f * h1f * ia * ia * ia * icf + h2f * h2f * ib * ib * ib * icsf;
+    const float fp = fw + h2f * h2f * ib * ib * ib * icsf;
     float rn = r - f * __builtin_amdgcn_rcpf(fp);
     rn = (rn >= lo && rn <= hi) ? rn : 0.5f * (lo + hi);   // a converged step may land on the bracket end
     const float st = fabsf(rn - r);
-    done = st * ib <= 0.25f && (st <= tol || 0.5f * fp * st * st <= tt);
-    r = rn;
+    done = cert || (st * ib <= 0.25f && (st <= tol || 0.5f * fp * st * st <= tt));
+    r = cert ? r : rn;
     if (done) break;
   }
   conv = conv && done;
   if (Df > 0.0f) q = r * __builtin_amdgcn_rcpf(Df);   // only the next leg's starting point
-  const double rd = (double)r, ud = D - rd;
+  const double rd = fmin((double)r, D), ud = D - rd;   // FP32 rounding may put r past D
   return sqrt_refined(rd * rd + h1 * h1) * inv_c + sqrt_refined(ud * ud + h2 * h2) * inv_cs;
 }
 
