@@ -253,6 +253,22 @@ int sas_bp_useful_updates(sas_bp_plan_t plan, const sas_bp_swath_io* io, int n_s
 int sas_bp_sharpness(sas_bp_plan_t plan, const void* image, int64_t n_pix, double* out_S,
                      void* grad_image, void* stream);
 
+/* Allocation-free variant of sas_bp_sharpness, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same S and cotangent, computed by the
+ * same kernels in the same fixed order (bitwise equal to sas_bp_sharpness), with
+ * the partial sums in a fixed array of 2 x 1024 + 2 doubles (16.4 KB) that the
+ * library keeps on every device it runs on until the process ends. Needs no
+ * plan; runs on the calling thread's current device (stream must belong to it);
+ * calls no allocating routine. The array's address is looked up on the first
+ * call on each device. n_pix in [1, SAS_BP_SHARPNESS_STATIC_MAX_PIX]; larger
+ * sizes return SAS_BP_EINVAL. Every call on one device shares the array (each
+ * call overwrites all of it before reading it): calls that overlap on one
+ * device, on different streams or threads, race. Pointers as for
+ * sas_bp_sharpness (device memory, 8-byte aligned). Asynchronous on `stream`. */
+#define SAS_BP_SHARPNESS_STATIC_MAX_PIX (1ll << 34)
+int sas_bp_sharpness_static(const void* image, int64_t n_pix, double* out_S, void* grad_image, void* stream);
+
 /* Range compression and basebanding of swath `swath`'s echo cube, in place:
  * the matched filter with the transmitted waveform q of Eq. 1 (Sec. II-A),
  * which yields the compressed complex baseband echo the image reads. For each

@@ -393,6 +393,23 @@ def sas_bp_sharpness(plan: Plan, image: torch.Tensor, out_S: torch.Tensor,
                                  _stream(plan.device, stream)), "sas_bp_sharpness")
 
 
+def sas_bp_sharpness_static(image: torch.Tensor, out_S: torch.Tensor, grad_image: Optional[torch.Tensor] = None,
+                            stream=None) -> None:
+    """``sas_bp_sharpness`` without a plan and without any allocation: the
+    partial sums use the library's fixed per-device array (calls that overlap
+    on one device race). Runs on the image's device."""
+    if image.dtype != torch.complex64 or not image.is_contiguous() or image.device.type != "cuda":
+        raise ValueError("image must be a contiguous complex64 device tensor")
+    dev = image.device.index
+    _need(out_S, "out_S", torch.float64, (1,), dev)
+    if grad_image is not None:
+        _need(grad_image, "grad_image", torch.complex64, tuple(image.shape), dev)
+    with torch.cuda.device(dev):
+        check(N.lib().sas_bp_sharpness_static(image.data_ptr(), image.numel(), out_S.data_ptr(),
+                                              grad_image.data_ptr() if grad_image is not None else None,
+                                              _stream(dev, stream)), "sas_bp_sharpness_static")
+
+
 def sas_bp_autotune(descs: Sequence[N.SwathDesc], bufs: Sequence[SwathBuffers], reps: int = 3, device: int = 0,
                     stream=None, tune_mode: str = "default", tune_cache=None, no_cull: bool = False) -> dict:
     """Fastest tiling for these swaths, timed on their buffers (images are

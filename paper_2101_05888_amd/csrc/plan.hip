@@ -112,7 +112,6 @@ int fail(int status, const char* fmt, ...) {
   } while (0)
 
 constexpr double kDefaultCmin = 1400.0;
-constexpr int kSharpPartials = 1024;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -383,7 +382,7 @@ Layout make_layout(int n_swaths, int n_tiles, size_t n_partials, size_t geo_stri
   L.counters = o;   o = align_up(o + sizeof(unsigned) * 16);
   L.bucket = o;     o = align_up(o + sizeof(unsigned) * kBuckets);
   L.tile_swath = o; o = align_up(o + sizeof(int) * n_tiles);
-  L.scratch = o;    o = align_up(o + sizeof(double) * (2 * kSharpPartials + 64));
+  L.scratch = o;    o = align_up(o + sizeof(double) * (kSharpScratch + 16));
   L.drc = o;        o = align_up(o + drc_work_bytes());
   L.geo = o;        o = align_up(o + geo_stride * (size_t)geo_slots);
   L.geo_stride = geo_stride;
@@ -1698,6 +1697,59 @@ int sas_bp_sharpness(sas_bp_plan_t p, const void* image, int64_t n_pix, double* 
   DeviceGuard guard(p->device);
   HIP_TRY(launch_sharpness(image, (long long)n_pix, p->ws.scratch64 + 16, out_S, grad_image,
                            reinterpret_cast<hipStream_t>(stream)));
+  return SAS_BP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------- allocation-free sharpness ---
+// The partial sums of sas_bp_sharpness_static live in this fixed device array
+// instead of a plan's workspace. In host code its name is only a stand-in for
+// the device variable: the address each device holds it at is looked up once
+// per device (hipGetSymbolAddress, with that device current) and only that
+// address is passed to kernels.
+static __device__ __align__(256) double scratch[kSharpScratch];
+
+namespace {
+
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kStaticMaxDevices] = {};   // scratch's address on each device, once looked up
+
+// scratch's device address on the current device (looked up on first use).
+int static_scratch(int* device, double** out) {
+  HIP_TRY(hipGetDevice(device));
+  if (*device < 0 || *device >= kStaticMaxDevices)
+    return fail(SAS_BP_EUNSUPPORTED, "device %d: at most %d devices", *device, kStaticMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[*device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SAS_BP_EDEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", *device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[*device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[*device];
+  return SAS_BP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sas_bp_sharpness_static(const void* image, int64_t n_pix, double* out_S, void* grad_image, void* stream) {
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  if (!image || !out_S) return fail(SAS_BP_EINVAL, "NULL pointer");
+  if (n_pix < 1 || n_pix > SAS_BP_SHARPNESS_STATIC_MAX_PIX)
+    return fail(SAS_BP_EINVAL, "n_pix must be in [1, %lld]", (long long)SAS_BP_SHARPNESS_STATIC_MAX_PIX);
+  if (((uintptr_t)image & 7u) || ((uintptr_t)out_S & 7u) || ((uintptr_t)grad_image & 7u))
+    return fail(SAS_BP_EINVAL, "pointer not 8-byte aligned");
+  int device = 0;
+  double* ptr = nullptr;
+  int rc = static_scratch(&device, &ptr);
+  if (rc) return rc;
+  HIP_TRY(launch_sharpness(image, (long long)n_pix, ptr, out_S, grad_image, reinterpret_cast<hipStream_t>(stream)));
   return SAS_BP_OK;
 }
 

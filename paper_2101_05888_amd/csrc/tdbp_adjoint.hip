@@ -324,7 +324,7 @@ __global__ void zero_u64(unsigned long long* p) { *p = 0ull; }
 
 // Sharpness S = A / B^2 with A = sum |I|^4, B = sum |I|^2 (FP64, fixed order),
 // and optionally the cotangent Gbar = 4 I (|I|^2 / B^2 - A / B^3).
-constexpr int kSharpBlocks = 1024;
+// kSharpBlocks (tdbp_dev.h) partial pairs, then the two sums in a fixed order.
 
 __global__ __launch_bounds__(kThreads) void sharp_partial_kernel(const float2* img, long long n, double* partials) {
   double a = 0.0, b = 0.0;

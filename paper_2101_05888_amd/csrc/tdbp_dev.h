@@ -129,6 +129,10 @@ __host__ __device__ inline int chunk_pings(int RC, int E) {
 }
 
 constexpr int kBuckets = 64;
+// Sharpness: one partial (sum |I|^4, sum |I|^2) pair per block of a fixed grid,
+// then the two sums; scratch of 2 kSharpBlocks + 2 doubles.
+constexpr int kSharpBlocks = 1024;
+constexpr int kSharpScratch = 2 * kSharpBlocks + 2;
 constexpr int kPartial = 8;   // gR.xyz, gc, gT.xyz (element 0 only), pad
 
 enum : unsigned { kStatusOk = 0u, kStatusNav = 1u, kStatusConverge = 2u };
