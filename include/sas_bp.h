@@ -361,6 +361,19 @@ int sas_bp_dpc_residual(const sas_bp_dpc_desc* desc, const double* vel, const do
                         const int32_t* pairs, const double* t_ref, const double* footprint, const double* delay,
                         double* pos_out, double* rows, void* stream);
 
+/* Fine delays (Sec. II-D, the second step of the estimate): the correlation
+ * phase of every (ping pair, window) unwrapped around the delay a first motion
+ * solution predicts. tde: device float [n][4] as written by sas_bp_dpc_tde
+ * (its phase, element 1, is used); rows: device double [n][7], the
+ * sas_bp_dpc_residual rows of the first solution evaluated with a zero
+ * measured delay, so that -rows[r][0] is the delay the solution predicts;
+ * writes out[r] = (phi + 2 pi m) / (2 pi f_c) (device double [n], seconds),
+ * m the integer nearest f_c (-rows[r][0]) - phi / (2 pi). The fine delays then
+ * replace the coarse ones in a second sas_bp_dpc_solve. FP64; n in [1, 2^31];
+ * f_c > 0 (the swath's carrier); tde 16-byte aligned. Asynchronous on
+ * `stream`. */
+int sas_bp_dpc_fine_delay(const float* tde, const double* rows, int64_t n, double f_c, double* out, void* stream);
+
 /* Levenberg-Marquardt solve of the motion estimate (host arrays: vx [P], dt
  * [P-1], lever_rx [E][3], pairs [J][2], t_ref [K], footprint [P-1][K][3],
  * delay and weight [P-1][K], z_dvl [P]; vyz [P][2] holds the start and

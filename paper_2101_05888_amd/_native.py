@@ -20,7 +20,7 @@ TUNE_DEFAULT, TUNE_CACHED, TUNE_SEARCH = 0, 1, 2
 EXPORTED = (
     "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image", "sas_bp_adjoint", "sas_bp_reproject",
     "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_sharpness_static", "sas_bp_drc", "sas_bp_tvg", "sas_bp_whiten",
-    "sas_bp_range_compress", "sas_bp_dpc_tde", "sas_bp_dpc_footprints", "sas_bp_dpc_residual",
+    "sas_bp_range_compress", "sas_bp_dpc_tde", "sas_bp_dpc_footprints", "sas_bp_dpc_residual", "sas_bp_dpc_fine_delay",
     "sas_bp_dpc_solve", "sas_bp_plan_status", "sas_bp_plan_info",
     "sas_bp_autotune", "sas_bp_gate_class", "sas_bp_set_kernel_timing", "sas_bp_kernel_time", "sas_bp_destroy", "sas_bp_error_string",
     "sas_bp_last_error_detail", "sas_bp_abi_version",
@@ -84,6 +84,7 @@ def _load():
     lib.sas_bp_dpc_footprints.argtypes = [DP, P, P, P, P, P, C.c_double, C.c_double, P]
     lib.sas_bp_dpc_residual.argtypes = [DP, P, P, P, P, P, P, P, P, P, P]
     lib.sas_bp_dpc_solve.argtypes = [DP, P, P, P, P, P, P, P, P, P, P, P, C.c_int]
+    lib.sas_bp_dpc_fine_delay.argtypes = [P, P, C.c_int64, C.c_double, P, P]
     lib.sas_bp_useful_updates.argtypes = [P, C.POINTER(SwathIO), C.c_int, P, C.POINTER(C.c_int64)]
     lib.sas_bp_sharpness.argtypes = [P, P, C.c_int64, P, P, P]
     lib.sas_bp_sharpness_static.argtypes = [P, C.c_int64, P, P, P]

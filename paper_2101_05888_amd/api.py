@@ -329,6 +329,28 @@ def sas_bp_dpc_residual(desc: N.DpcDesc, vel, dt, lever_rx, pairs, t_ref, footpr
     return pos, rows
 
 
+def sas_bp_dpc_fine_delay(tde: torch.Tensor, rows: torch.Tensor, f_c: float, out: Optional[torch.Tensor] = None,
+                          stream=None) -> torch.Tensor:
+    """Fine delays (Sec. II-D): the TDE phase (float32 [..., 4] from
+    sas_bp_dpc_tde) unwrapped around the delay that a first solution predicts,
+    -rows[..., 0] with rows (float64 [..., 7]) from sas_bp_dpc_residual at a
+    zero measured delay. Returns a float64 device tensor of the leading shape."""
+    if tde.dtype != torch.float32 or tde.shape[-1] != 4 or not tde.is_contiguous() or not tde.is_cuda:
+        raise ValueError("tde must be a contiguous float32 CUDA tensor [..., 4]")
+    if rows.dtype != torch.float64 or rows.shape[-1] != 7 or not rows.is_contiguous() or rows.device != tde.device:
+        raise ValueError("rows must be a contiguous float64 tensor [..., 7] on the device of tde")
+    if tuple(rows.shape[:-1]) != tuple(tde.shape[:-1]):
+        raise ValueError(f"rows {tuple(rows.shape)} and tde {tuple(tde.shape)} must share their leading shape")
+    if out is None:
+        out = torch.empty(tde.shape[:-1], dtype=torch.float64, device=tde.device)
+    elif out.dtype != torch.float64 or tuple(out.shape) != tuple(tde.shape[:-1]) or not out.is_contiguous() \
+            or out.device != tde.device:
+        raise ValueError("out must be a contiguous float64 tensor of the leading shape of tde, on its device")
+    check(N.lib().sas_bp_dpc_fine_delay(tde.data_ptr(), rows.data_ptr(), int(out.numel()), float(f_c), out.data_ptr(),
+                                        _stream(tde.device.index, stream)), "sas_bp_dpc_fine_delay")
+    return out
+
+
 def sas_bp_dpc_solve(desc: N.DpcDesc, vx, dt, lever_rx, pairs, t_ref, footprint, delay, weight, z_dvl, vyz0,
                      device: int = 0):
     """Levenberg-Marquardt motion estimate: returns (vyz [P, 2], final loss)."""

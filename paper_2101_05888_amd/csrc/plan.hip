@@ -69,6 +69,8 @@ int tde_max_lag();
 hipError_t launch_dpc_residual(int P, int K, int J, const double* pos, const double* vel, const double* dt,
                                const double* lever_tx, const double* lever_rx, const int* pairs, const double* t_ref,
                                const double* ps, const double* delay, double c, double* rows, hipStream_t st);
+hipError_t launch_dpc_fine_delay(long long n, const float* tde, const double* rows, double fc, double* out,
+                                 hipStream_t st);
 hipError_t launch_dpc_positions(int P, const double* vel, const double* dt, const double* p0, double* pos,
                                 hipStream_t st);
 size_t tde_lds_bytes(int W, int L, int J);
@@ -155,6 +157,7 @@ struct sas_bp_plan_s {
   int refract = 0;                 // sediment refraction, shared by all swaths of the plan
   int bucket_shift = 0;
   int lds_bytes = 0, adj_lds_bytes = 0;
+  int image_launch_lds = 0;        // dynamic LDS of the image kernel's launch (0 for refraction)
   int grid = 0, adj_grid = 0;
   int occ = 0;                     // image workgroups resident per CU
   bool adj_ok = false;             // the adjoint's whole-ping chunks fit the device
@@ -493,7 +496,7 @@ int enqueue_image(sas_bp_plan_s* p, hipStream_t st) {
     if (rc) return rc;
     HIP_TRY(hipEventRecord(a, st));
   }
-  HIP_TRY(launch_image(p->image_fn, p->ws, p->n_tiles, p->grid, p->tiling.NT, p->lds_bytes, st));
+  HIP_TRY(launch_image(p->image_fn, p->ws, p->n_tiles, p->grid, p->tiling.NT, p->image_launch_lds, st));
   if (p->timing) {
     HIP_TRY(hipEventRecord(b, st));
     ++p->n_timed;
@@ -896,6 +899,17 @@ int sas_bp_dpc_residual(const sas_bp_dpc_desc* d, const double* vel, const doubl
   return SAS_BP_OK;
 }
 
+int sas_bp_dpc_fine_delay(const float* tde, const double* rows, int64_t n, double f_c, double* out, void* stream) {
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  if (!tde || !rows || !out) return fail(SAS_BP_EINVAL, "NULL pointer");
+  if (n < 1 || n > (1ll << 31)) return fail(SAS_BP_EINVAL, "n must be in [1, 2^31]");
+  if (!(f_c > 0.0) || !std::isfinite(f_c)) return fail(SAS_BP_EINVAL, "f_c must be > 0");
+  if (((uintptr_t)tde & 15u) || ((uintptr_t)rows & 7u) || ((uintptr_t)out & 7u))
+    return fail(SAS_BP_EINVAL, "tde must be 16-byte aligned, rows and out 8-byte aligned");
+  HIP_TRY(launch_dpc_fine_delay((long long)n, tde, rows, f_c, out, reinterpret_cast<hipStream_t>(stream)));
+  return SAS_BP_OK;
+}
+
 int sas_bp_dpc_solve(const sas_bp_dpc_desc* d, const double* vx, const double* dt, const double* lever_rx,
                      const int32_t* pairs, const double* t_ref, const double* footprint, const double* delay,
                      const double* weight, const double* z_dvl, double* vyz, double* loss_out, int device) {
@@ -1261,11 +1275,15 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
                 (size_t)prop.sharedMemPerBlock);
   }
   p->adj_ok = e == hipSuccess && (size_t)max_adj_lds + 1024 <= prop.sharedMemPerBlock;
-  if (e == hipSuccess) e = set_image_lds_limit(p->image_fn, max_lds);
+  // the refraction kernel reads the echo from global memory: no dynamic LDS,
+  // so that its occupancy is set by its registers alone
+  const int image_lds = p->refract ? 0 : max_lds;
+  p->image_launch_lds = image_lds;
+  if (e == hipSuccess) e = set_image_lds_limit(p->image_fn, image_lds);
   if (e == hipSuccess && p->adj_ok) e = set_adjoint_lds_limit(p->adjoint_fn, max_adj_lds);
   if (e == hipSuccess) e = set_reproject_lds_limit(p->reproject_fn, max_lds);   // same layout as the image
   int occ = 0, adj_occ = 1, rep_occ = 0;
-  if (e == hipSuccess) e = image_occupancy(p->image_fn, t.NT, max_lds, &occ);
+  if (e == hipSuccess) e = image_occupancy(p->image_fn, t.NT, image_lds, &occ);
   if (e == hipSuccess && p->adj_ok) e = adjoint_occupancy(p->adjoint_fn, t.NT, max_adj_lds, &adj_occ);
   if (e == hipSuccess) e = reproject_occupancy(p->reproject_fn, t.NT, max_lds, &rep_occ);
   if (e != hipSuccess) {

@@ -255,6 +255,32 @@ hipError_t launch_dpc_residual(int P, int K, int J, const double* pos, const dou
 
 namespace sasbp {
 
+// Fine delay of every (ping pair, window) (Sec. II-D, the second step): the
+// phase of the correlation at the coarse peak, phi = 2 pi f_c delta (mod 2 pi),
+// unwrapped to the whole number of carrier cycles that brings it nearest the
+// delay predicted by a first motion solution. rows are the Eq. 4 residual rows
+// of that solution evaluated with a zero measured delay, so that rows[7 r] =
+// c^-1 mean_j (path_1 - path_2) and the predicted delay is its negative:
+//     m = round(f_c ref - phi / 2 pi),  delta = (phi + 2 pi m) / (2 pi f_c).
+__global__ __launch_bounds__(kThreads) void dpc_fine_delay_kernel(long long n, const float4* __restrict__ tde,
+                                                                 const double* __restrict__ rows, double fc,
+                                                                 double* __restrict__ out) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double two_pi = 6.283185307179586;
+  const double phi = (double)tde[r].y;
+  const double ref = -rows[(size_t)r * 7];
+  const double m = rint(fc * ref - phi / two_pi);
+  out[r] = (phi + two_pi * m) / (two_pi * fc);
+}
+
+hipError_t launch_dpc_fine_delay(long long n, const float* tde, const double* rows, double fc, double* out,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(dpc_fine_delay_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st, n,
+                     reinterpret_cast<const float4*>(tde), rows, fc, out);
+  return hipGetLastError();
+}
+
 // p_i(0) = p_0 + sum_{n<i} v_n dt_n for every ping (one thread, in ping order).
 __global__ void dpc_positions_kernel(int P, const double* __restrict__ vel, const double* __restrict__ dt, double p0x,
                                      double p0y, double p0z, double* __restrict__ pos) {

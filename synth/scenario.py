@@ -319,6 +319,59 @@ def _c5(**kw):
     return scn
 
 
+@dataclasses.dataclass
+class DpcTrack:
+    """A swath for the DPC motion estimate: the scenario (``tx``/``rx`` the
+    straight nominal track, ``true_tx``/``true_rx`` the track the echoes are
+    synthesized on), the true per-ping velocities [P, 3] (surge, sway, heave;
+    the receivers also move with them during reception), the ping intervals
+    dt [P - 1] and the platform position of the first ping."""
+    scn: Scenario
+    vel: np.ndarray
+    dt: np.ndarray
+    p0: np.ndarray
+
+
+def dpc_track(n_ping: int = 16, n_sample: int = 2048, pri: float = 0.2, sway_amp: float = 0.02,
+              heave_amp: float = 0.012, seed: int = 1006, n_speckle: int = 40000) -> DpcTrack:
+    """Stripmap geometry of the operational workload (32 receivers at
+    3.75 cm, transmitter at the array centre, 0.3 m advance per ping, so
+    element e + 16 of ping i and element e of ping i + 1 share a phase centre;
+    10 m altitude) over a fully developed speckle seafloor covering every
+    beam, on a track whose sway and heave velocities are smooth sinusoids of
+    seeded phase (amplitudes in m/s) plus a seeded constant: the platform
+    drifts a few centimetres over the swath. Positions integrate the
+    velocities over the ping intervals."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    ph = rng.uniform(0.0, 2.0 * math.pi, 2)
+    bias = rng.uniform(-0.2, 0.2, 2)
+    i = np.arange(n_ping, dtype=np.float64)
+    vx = 0.3 / pri
+    vel = np.column_stack([np.full(n_ping, vx),
+                           sway_amp * (np.sin(2.0 * math.pi * 0.8 * i / n_ping + ph[0]) + bias[0]),
+                           heave_amp * (np.cos(2.0 * math.pi * 0.6 * i / n_ping + ph[1]) + bias[1])])
+    dt = np.full(n_ping - 1, float(pri))
+    p0 = np.array([0.0, 0.0, -10.0])
+    true_tx = p0[None, :] + np.concatenate([np.zeros((1, 3)), np.cumsum(vel[:-1] * dt[:, None], axis=0)])
+    slant = 1500.0 * n_sample / 80e3 / 2.0
+    half_x = math.tan(math.radians(10.0)) * slant + 0.6
+    x_lo, x_hi = -half_x, true_tx[-1, 0] + half_x
+    ground = math.sqrt(max(slant ** 2 - 9.0 ** 2, 1.0)) + 0.5
+    px = 0.015
+    nx, ny = int(math.ceil((x_hi - x_lo) / px)) + 1, int(math.ceil(ground / px)) + 1
+    scn = _stripmap("dpc", seed, n_ping=n_ping, ping_dx=0.3, n_elem=32, pitch=0.0375, altitude=10.0,
+                    sway_sigma=0.0, nx=nx, ny=ny, px=px, y0=0.0, n_sample=n_sample, gate_deg=10.0,
+                    n_scat=0, n_speckle=n_speckle, speckle_sigma=1.0, snr_db=20.0, taper_half=16, straight=True)
+    scn.grid = Grid(n=(nx, ny, 1), origin=(x_lo, 0.0, 0.0), spacing=(px, px, px))
+    pos = scn.streams()["positions"]
+    scn.scat_pos = np.stack([pos.uniform(x_lo, x_hi, n_speckle), pos.uniform(0.0, ground, n_speckle),
+                             np.zeros(n_speckle)], axis=1)
+    scn.true_tx = true_tx
+    scn.true_rx = linear_array_rx(true_tx, 32, 0.0375)
+    scn.notes = "DPC track: echoes on true_tx/true_rx with the receivers moving at vel during reception"
+    return DpcTrack(scn=scn, vel=vel, dt=dt, p0=p0)
+
+
 def make_config(name: str, **overrides) -> Scenario:
     """Build a workload by name: 'c1', 'c2', 'c3', 'c4a' (= c1), 'c4b:k', 'c5'.
 

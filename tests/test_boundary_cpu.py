@@ -96,6 +96,7 @@ def test_null_arguments_rejected():
     assert N.lib().sas_bp_dpc_tde(None, 0, None, None, 1, 2, 1, 1, None, None) == 1
     assert N.lib().sas_bp_dpc_footprints(None, None, None, None, None, None, 0.0, 1.0, None) == 1
     assert N.lib().sas_bp_dpc_residual(None, None, None, None, None, None, None, None, None, None, None) == 1
+    assert N.lib().sas_bp_dpc_fine_delay(None, None, 1, 1e5, None, None) == 1
     assert N.lib().sas_bp_dpc_solve(None, None, None, None, None, None, None, None, None, None, None, None, 0) == 1
     assert N.lib().sas_bp_adjoint(None, None, None, None, None, None, 1, None) == 1
     out = C.c_size_t()
