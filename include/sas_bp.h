@@ -413,6 +413,17 @@ int sas_bp_whiten(sas_bp_plan_t plan, int swath, void* echo, double gamma, void*
  * the first call. Asynchronous on `stream`. */
 int sas_bp_tvg(sas_bp_plan_t plan, int swath, void* echo, double alpha, float* gain_out, void* stream);
 
+/* Echo envelope of swath `swath` for the incoherent stage of the sharpness
+ * autofocus (Sec. II-A's delay-and-sum with the carrier phase removed: its
+ * sharpness varies on the scale of the range resolution, not the
+ * wavelength): every sample e of the cube [P][E][N_s] becomes (|e|, 0), in
+ * the swath's echo storage format (complex64, or FP16/BF16 pairs; per-ping
+ * scales unchanged). |e| = sqrt(re^2 + im^2) in FP32, correctly rounded, then
+ * rounded to nearest-even for 16-bit storage (a magnitude beyond the format's
+ * range becomes infinite). echo and out are device memory, 8-byte (complex64)
+ * or 4-byte aligned, equal (in place) or disjoint. Asynchronous on `stream`. */
+int sas_bp_envelope(sas_bp_plan_t plan, int swath, const void* echo, void* out, void* stream);
+
 /* Dynamic range compression of an image for display (Eqs. 11-12, Sec.
  * II-E). x = |I| / max |I| over the n_pix complex64 pixels of image; each
  * pixel maps to out[i] = q x / ((q - 1) x + 1) (FP32, n_pix floats), with

@@ -19,7 +19,7 @@ TUNE_DEFAULT, TUNE_CACHED, TUNE_SEARCH = 0, 1, 2
 
 EXPORTED = (
     "sas_bp_plan", "sas_bp_workspace_size", "sas_bp_image", "sas_bp_adjoint", "sas_bp_reproject",
-    "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_sharpness_static", "sas_bp_drc", "sas_bp_tvg", "sas_bp_whiten",
+    "sas_bp_useful_updates", "sas_bp_sharpness", "sas_bp_sharpness_static", "sas_bp_drc", "sas_bp_tvg", "sas_bp_envelope", "sas_bp_whiten",
     "sas_bp_range_compress", "sas_bp_dpc_tde", "sas_bp_dpc_footprints", "sas_bp_dpc_residual", "sas_bp_dpc_fine_delay",
     "sas_bp_dpc_solve", "sas_bp_plan_status", "sas_bp_plan_info",
     "sas_bp_autotune", "sas_bp_gate_class", "sas_bp_set_kernel_timing", "sas_bp_kernel_time", "sas_bp_destroy", "sas_bp_error_string",
@@ -77,6 +77,7 @@ def _load():
     lib.sas_bp_reproject.argtypes = [P, C.POINTER(SwathIO), C.POINTER(P), C.POINTER(P), C.c_int, P]
     lib.sas_bp_drc.argtypes = [P, P, C.c_int64, C.c_double, P, P, P]
     lib.sas_bp_tvg.argtypes = [P, C.c_int, P, C.c_double, P, P]
+    lib.sas_bp_envelope.argtypes = [P, C.c_int, P, P, P]
     lib.sas_bp_whiten.argtypes = [P, C.c_int, P, C.c_double, P]
     lib.sas_bp_range_compress.argtypes = [P, C.c_int, P, P, C.c_int32, C.c_int, P]
     lib.sas_bp_dpc_tde.argtypes = [P, C.c_int, P, P, C.c_int, C.c_int32, C.c_int32, C.c_int32, P, P]

@@ -380,6 +380,27 @@ def sas_bp_tvg(plan: Plan, swath: int, echo: torch.Tensor, alpha: float,
           "sas_bp_tvg")
 
 
+def sas_bp_envelope(plan: Plan, swath: int, echo: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+    """Echo envelope (|e|, 0) of swath `swath`'s cube in its storage format
+    (complex64 [P, E, N_s], or float16/bfloat16 [P, E, N_s, 2]); out may be
+    echo itself (in place) or a new tensor of the same kind."""
+    d = plan.descs[swath]
+    P, E, Ns = d.n_ping, d.n_elem, d.n_sample
+    if d.echo_dtype == N.ECHO_C64:
+        dt, shape = torch.complex64, (P, E, Ns)
+    else:
+        dt, shape = (torch.float16 if d.echo_dtype == N.ECHO_F16X2 else torch.bfloat16), (P, E, Ns, 2)
+    _need(echo, "echo", dt, shape, plan.device)
+    if out is None:
+        out = torch.empty_like(echo)
+    else:
+        _need(out, "out", dt, shape, plan.device)
+    check(N.lib().sas_bp_envelope(plan.handle, int(swath), echo.data_ptr(), out.data_ptr(),
+                                  _stream(plan.device, stream)), "sas_bp_envelope")
+    return out
+
+
 def sas_bp_drc(plan: Plan, image: torch.Tensor, brightness: float, out: torch.Tensor,
                params: Optional[torch.Tensor] = None, stream=None) -> None:
     """Dynamic range compression for display: out (float32, image's shape) from

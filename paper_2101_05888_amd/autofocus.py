@@ -77,19 +77,13 @@ def envelope_stage(plan, buf: SwathBuffers, **kw) -> Stage:
     resolution instead of the wavelength, so it has no wrapped maxima within
     centimetres of motion error and brings the track close enough for the
     coherent stages. Allocates its own plan and buffers."""
-    from .api import sas_bp_plan, swath_desc
+    from .api import sas_bp_envelope, sas_bp_plan, swath_desc
     d = plan.descs[0]
     dt = {0: "c64", 1: "f16", 2: "bf16"}[d.echo_dtype]
     env = swath_desc(d.n_ping, d.n_elem, d.n_sample, tuple(d.n), tuple(d.origin), tuple(d.spacing), 0.0, d.f_s,
                      d.t0, d.gate_half_angle, dt, d.c_min)
     p2 = sas_bp_plan([env], device=plan.device)
-    if dt == "c64":
-        mag = torch.zeros_like(buf.echo)
-        mag.real.copy_(buf.echo.abs())
-    else:
-        e = buf.echo.float()
-        mag = torch.zeros_like(buf.echo)
-        mag[..., 0].copy_(torch.sqrt(e[..., 0] ** 2 + e[..., 1] ** 2).to(buf.echo.dtype))
+    mag = sas_bp_envelope(p2, 0, buf.echo)
     b2 = SwathBuffers(echo=mag, tx=buf.tx.clone(), rx=buf.rx.clone(), c=buf.c, image=torch.empty_like(buf.image),
                       echo_scale=buf.echo_scale)
     return Stage(plan=p2, buf=b2, **kw)

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsas_bp.so")
-SOURCES = ["plan.hip", "tdbp_image.hip", "tdbp_adjoint.hip", "tdbp_reproject.hip", "tdbp_drc.hip", "tdbp_tvg.hip", "tdbp_whiten.hip", "tdbp_rangec.hip", "tdbp_dpc.hip", "tdbp_refract.hip"]
+SOURCES = ["plan.hip", "tdbp_image.hip", "tdbp_adjoint.hip", "tdbp_reproject.hip", "tdbp_drc.hip", "tdbp_tvg.hip", "tdbp_envelope.hip", "tdbp_whiten.hip", "tdbp_rangec.hip", "tdbp_dpc.hip", "tdbp_refract.hip"]
 ARCH = os.environ.get("SAS_BP_ARCH", "gfx950")
 
 

@@ -58,6 +58,7 @@ hipError_t set_reproject_lds_limit(ReprojectKernelFn fn, int lds_bytes);
 hipError_t launch_drc(const void* image, long long n, double brightness, float* out, double* params, void* work,
                       hipStream_t st);
 size_t drc_work_bytes();
+hipError_t launch_envelope(const void* in, void* out, long long n, int dt, hipStream_t st);
 hipError_t launch_tvg(void* echo, long long rows, int Ns, double alpha, float* work, float* gain_out,
                       hipStream_t st);
 size_t whiten_work_bytes(int Ns);
@@ -1664,6 +1665,23 @@ int sas_bp_tvg(sas_bp_plan_t p, int swath, void* echo, double alpha, float* gain
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HIP_TRY(launch_tvg(echo, (long long)d.n_ping * d.n_elem, d.n_sample, alpha, reinterpret_cast<float*>(p->tvg_buf),
                      gain_out, st));
+  return SAS_BP_OK;
+}
+
+int sas_bp_envelope(sas_bp_plan_t p, int swath, const void* echo, void* out, void* stream) {
+  if (!p) return fail(SAS_BP_EINVAL, "plan is NULL");
+  (void)hipGetLastError();   // an earlier failed runtime call must not be reported as ours
+  if (swath < 0 || swath >= p->n_swaths) return fail(SAS_BP_EINVAL, "swath %d out of range", swath);
+  if (!echo || !out) return fail(SAS_BP_EINVAL, "echo or out is NULL");
+  const auto& d = p->sw[swath].d;
+  const unsigned align = d.echo_dtype == SAS_BP_ECHO_C64 ? 7u : 3u;
+  if (((uintptr_t)echo & align) || ((uintptr_t)out & align)) return fail(SAS_BP_EINVAL, "echo or out misaligned");
+  const long long n = (long long)d.n_ping * d.n_elem * d.n_sample;
+  const size_t bytes = (size_t)n * (d.echo_dtype == SAS_BP_ECHO_C64 ? 8 : 4);
+  const uintptr_t a = (uintptr_t)echo, b = (uintptr_t)out;
+  if (a != b && a < b + bytes && b < a + bytes) return fail(SAS_BP_EINVAL, "echo and out overlap without being equal");
+  DeviceGuard guard(p->device);
+  HIP_TRY(launch_envelope(echo, out, n, d.echo_dtype, reinterpret_cast<hipStream_t>(stream)));
   return SAS_BP_OK;
 }
 

@@ -95,9 +95,10 @@ __device__ __forceinline__ double refracted_time(double dx, double dy, double dz
     hi = f < 0.0f ? hi : r;
     const float fp = fw + h2f * h2f * ib * ib * ib * icsf;
     float rn = r - f * __builtin_amdgcn_rcpf(fp);
-    rn = (rn >= lo && rn <= hi) ? rn : 0.5f * (lo + hi);   // a converged step may land on the bracket end
+    rn = ((rn >= lo) & (rn <= hi)) ? rn : 0.5f * (lo + hi);   // a converged step may land on the bracket end
     const float st = fabsf(rn - r);
-    done = cert || (st * ib <= 0.25f && (st <= tol || 0.5f * fp * st * st <= tt));
+    // every test evaluated, combined without short-circuit branches
+    done = cert | ((st * ib <= 0.25f) & ((st <= tol) | (0.5f * fp * st * st <= tt)));
     r = cert ? r : rn;
     if (done) break;
   }

@@ -91,6 +91,7 @@ def test_null_arguments_rejected():
     assert N.lib().sas_bp_reproject(None, None, None, None, 1, None) == 1
     assert N.lib().sas_bp_drc(None, None, 1, 0.5, None, None, None) == 1
     assert N.lib().sas_bp_tvg(None, 0, None, 0.0, None, None) == 1
+    assert N.lib().sas_bp_envelope(None, 0, None, None, None) == 1
     assert N.lib().sas_bp_whiten(None, 0, None, 0.0, None) == 1
     assert N.lib().sas_bp_range_compress(None, 0, None, None, 1, 1, None) == 1
     assert N.lib().sas_bp_dpc_tde(None, 0, None, None, 1, 2, 1, 1, None, None) == 1
