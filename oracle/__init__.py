@@ -18,7 +18,8 @@ estimate (Sec. II-D). It shares no code with the HIP path.
 """
 from .tdbp import (pixel_points, backproject, backproject_image, gated_term_count,
                    gated_term_count_rows, vjp, vjp_segment_bound, reproject, sharpness,
-                   sharpness_cotangent, sinc_kernel, SINC_HALF, motion_delay, refracted_leg)
+                   sharpness_cotangent, sinc_kernel, SINC_HALF, motion_delay, track_delay, track_position,
+                   refracted_leg)
 from .metrics import rel_l2, phase_error_mrad
 from .drc import drc
 from .tvg import tvg
@@ -28,5 +29,6 @@ from . import dpc
 
 __all__ = ["pixel_points", "backproject", "backproject_image", "gated_term_count",
            "gated_term_count_rows", "vjp", "vjp_segment_bound", "reproject", "sharpness",
-           "sharpness_cotangent", "sinc_kernel", "SINC_HALF", "motion_delay", "refracted_leg",
+           "sharpness_cotangent", "sinc_kernel", "SINC_HALF", "motion_delay", "track_delay", "track_position",
+           "refracted_leg",
            "rel_l2", "phase_error_mrad", "drc", "tvg", "whiten", "range_compress", "dpc"]

@@ -30,6 +30,15 @@ a = p - R_ie this is the quadratic
 whose larger root is the one with c tau - d_T >= 0 (``motion_delay``). The
 beam gate keeps the ping-time positions.
 
+Position table (the same variant with the sensor track up-sampled into a
+table that is interpolated linearly at the query time, Sec. II-C): ping i's
+receivers are displaced by Delta_i(t) from their ping-time positions,
+R_ie(t) = R_ie + Delta_i(t), with Delta_i sampled at t_j = j h (j = 0..N - 1)
+and linear between samples; before t_0 and after t_{N-1} the first and last
+segments extend linearly. tau solves c tau = d_T + |p - R_ie - Delta_i(tau)|;
+the right side changes more slowly than the left when the track's speed is
+below c, so the root is unique, and ``track_delay`` brackets it by bisection.
+
 Sediment refraction (variant of the image; Sec. III-B): the flat seafloor
 z = z_int separates water (c, above; the array is in the water) from sediment
 (c_sed, below). A leg from apex X to a pixel p below the interface crosses it
@@ -123,6 +132,39 @@ def motion_delay(d_T, a, v, c):
     return (Bh + np.sqrt(Bh * Bh - A * (d_T * d_T - aa))) / A
 
 
+def track_position(table, h, t):
+    """Delta(t) of one ping's table [N, 3] (samples every h seconds from t = 0),
+    linear between samples and extended linearly past both ends; t [M]."""
+    table = np.asarray(table, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    n = table.shape[0]
+    j = np.clip(np.floor(t / h), 0, n - 2).astype(np.int64)
+    frac = t / h - j                        # outside [0, 1] on the extended end segments
+    return table[j] + frac[:, None] * (table[j + 1] - table[j])
+
+
+def track_delay(d_T, a, table, h, c):
+    """Two-way delay with the receivers displaced by the table: the root of
+    c tau = d_T + |a - Delta(tau)| (a = p - R at transmit, [M, 3]), by
+    bisection on tau (100 halvings of a bracket that starts at 0)."""
+    d_T = np.asarray(d_T, dtype=np.float64)
+    a = np.asarray(a, dtype=np.float64)
+    f = lambda tau: c * tau - d_T - np.linalg.norm(a - track_position(table, h, tau), axis=1)
+    lo = np.zeros_like(d_T)
+    hi = 2.0 * (d_T + np.linalg.norm(a, axis=1)) / c + h
+    for _ in range(64):                      # widen until the bracket holds the root
+        grow = f(hi) <= 0.0
+        if not grow.any():
+            break
+        hi = np.where(grow, 2.0 * hi, hi)
+    for _ in range(100):
+        mid = 0.5 * (lo + hi)
+        neg = f(mid) < 0.0
+        lo = np.where(neg, mid, lo)
+        hi = np.where(neg, hi, mid)
+    return 0.5 * (lo + hi)
+
+
 def refracted_leg(X, pts, c, c_sed, z_int):
     """One-way travel time from X [3] (in the water) to every point of pts [N, 3]."""
     X = np.asarray(X, dtype=np.float64)
@@ -142,7 +184,8 @@ def refracted_leg(X, pts, c, c_sed, z_int):
     return np.where(below, t, np.sqrt(((pts - X) ** 2).sum(axis=1)) / c)
 
 
-def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear", vel=None, refr=None):
+def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear", vel=None, refr=None, track=None,
+              track_h=None):
     P, E = rx.shape[0], rx.shape[1]
     acc = np.zeros(pts.shape[0], dtype=np.complex128)
     count = 0
@@ -156,6 +199,8 @@ def _bp_chunk(echo, tx, rx, c, fc, fs, t0, pts, gate, interp="linear", vel=None,
             dR = np.sqrt(((pts - R) ** 2).sum(axis=1))
             if refr is not None:
                 tau = tT + refracted_leg(R, pts, c, refr[0], refr[1])
+            elif track is not None:
+                tau = track_delay(dT, pts - R, track[i], track_h, c)
             else:
                 tau = (dT + dR) / c if vel is None else motion_delay(dT, pts - R, vel[i], c)
             u = (tau - t0) * fs
@@ -182,11 +227,12 @@ def _worker(args):
     from . import pool
     a = pool.attach(specs)
     return _bp_chunk(a["echo"], a["tx"], a["rx"], sc["c"], sc["fc"], sc["fs"], sc["t0"],
-                     a["pts"][lo:hi], sc["gate"], sc["interp"], a["vel"], sc["refr"])
+                     a["pts"][lo:hi], sc["gate"], sc["interp"], a["vel"], sc["refr"], a["track"], sc["track_h"])
 
 
 def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
-                workers=1, chunk=4096, return_count=False, interp="linear", rx_vel=None, refraction=None):
+                workers=1, chunk=4096, return_count=False, interp="linear", rx_vel=None, refraction=None,
+                rx_track=None):
     """Backprojected complex values at arbitrary points [N,3] (float64 in, complex128 out).
 
     echo: complex [P,E,N_s]; tx: [P,3]; rx: [P,E,3]; gate_half_angle in radians
@@ -195,8 +241,9 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
     ``interp`` = "linear" (the definition above) or "sinc": the interpolation
     variant L = sum over the 2 SINC_HALF samples m around u of E~[m] h(u - m),
     h the Hann-windowed sinc of ``sinc_kernel``. ``rx_vel`` ([P, 3], m/s)
-    selects continuous receiver motion (``motion_delay``); ``refraction``
-    = (c_sed, z_int) the sediment interface (``refracted_leg``).
+    selects continuous receiver motion (``motion_delay``); ``rx_track`` =
+    (table [P, N, 3], h) the same with a position table (``track_delay``);
+    ``refraction`` = (c_sed, z_int) the sediment interface (``refracted_leg``).
     """
     echo = np.asarray(echo)
     if echo.dtype not in (np.complex64, np.complex128):   # complex64 samples convert exactly per tap
@@ -206,6 +253,8 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
     rx = np.asarray(rx, dtype=np.float64)
     pts = np.asarray(points, dtype=np.float64).reshape(-1, 3)
     vel = None if rx_vel is None else np.asarray(rx_vel, dtype=np.float64).reshape(-1, 3)
+    track, track_h = (None, None) if rx_track is None else (np.ascontiguousarray(rx_track[0], dtype=np.float64),
+                                                           float(rx_track[1]))
     N = pts.shape[0]
     spans = [(lo, min(N, lo + chunk)) for lo in range(0, N, chunk)]
     out = np.zeros(N, dtype=np.complex128)
@@ -213,14 +262,15 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
     if workers <= 1 or len(spans) <= 1:
         for lo, hi in spans:
             v, cnt = _bp_chunk(echo, tx, rx, float(c), fc, fs, t0, pts[lo:hi], gate_half_angle, interp, vel,
-                               refraction)
+                               refraction, track, track_h)
             out[lo:hi] = v
             total += cnt
     else:
         from . import pool
         workers_pool, _ = pool.get()
-        sc = dict(c=float(c), fc=fc, fs=fs, t0=t0, gate=gate_half_angle, interp=interp, refr=refraction)
-        with pool.Shared(echo=echo, tx=tx, rx=rx, pts=pts, vel=vel) as sh:
+        sc = dict(c=float(c), fc=fc, fs=fs, t0=t0, gate=gate_half_angle, interp=interp, refr=refraction,
+                  track_h=track_h)
+        with pool.Shared(echo=echo, tx=tx, rx=rx, pts=pts, vel=vel, track=track) as sh:
             res = workers_pool.map(_worker, [(sh.specs, sc, lo, hi) for lo, hi in spans], chunksize=1)
         for (lo, hi), (v, cnt) in zip(spans, res):
             out[lo:hi] = v
@@ -229,11 +279,12 @@ def backproject(echo, tx, rx, c, fc, fs, t0, points, gate_half_angle=0.0,
 
 
 def backproject_image(echo, tx, rx, c, fc, fs, t0, origin, spacing, n, gate_half_angle=0.0,
-                      workers=1, return_count=False, interp="linear", rx_vel=None, refraction=None):
+                      workers=1, return_count=False, interp="linear", rx_vel=None, refraction=None, rx_track=None):
     """Full image [nz, ny, nx] complex128 on the grid origin + index * spacing."""
     pts = pixel_points(origin, spacing, n)
     r = backproject(echo, tx, rx, c, fc, fs, t0, pts, gate_half_angle, workers=workers,
-                    return_count=return_count, interp=interp, rx_vel=rx_vel, refraction=refraction)
+                    return_count=return_count, interp=interp, rx_vel=rx_vel, refraction=refraction,
+                    rx_track=rx_track)
     nx, ny, nz = (int(v) for v in n)
     if return_count:
         return r[0].reshape(nz, ny, nx), r[1]

@@ -15,6 +15,10 @@ reception, R_ie(t) = R_ie + v_i t (t after transmit; the transmitter is
 stationary while it transmits), and tau_s solves
 c tau = |x_s - T_i| + |x_s - R_ie - v_i tau|, found by fixed-point iteration
 (contraction |v| / c). The gate stays that of the ping-time positions.
+With ``rx_track = (table [P, N, 3], h)`` the receivers are displaced by the
+table, R_ie(t) = R_ie + Delta_i(t), sampled every h seconds from transmit and
+joined by straight lines (also beyond both ends); tau_s again by fixed-point
+iteration.
 With ``refraction = (c_sed, z_int)`` the seafloor z = z_int separates water
 (sound speed c, above) from sediment (c_sed, below): a leg from an apex X
 in the water to a scatterer below the interface crosses it at the point of
@@ -79,6 +83,21 @@ def _leg_time(X: torch.Tensor, p: torch.Tensor, c: float, refraction: tuple) -> 
     return torch.where(below, t_ref, straight)
 
 
+def _track_at(table: torch.Tensor, h: float, t: torch.Tensor) -> torch.Tensor:
+    """Displacement of each ping's table [p, N, 3] at times t [p, ...] (sample
+    j at j h, straight lines between samples and beyond both ends)."""
+    n = table.shape[1]
+    u = t / h
+    j = torch.clamp(torch.floor(u), 0, n - 2).to(torch.int64)
+    f = (u - j.to(u.dtype))[..., None]
+    flat = j.reshape(j.shape[0], -1)                                           # [p, M]
+    a = torch.gather(table, 1, flat[..., None].expand(-1, -1, 3))
+    b = torch.gather(table, 1, (flat + 1)[..., None].expand(-1, -1, 3))
+    a = a.reshape(*j.shape, 3)
+    b = b.reshape(*j.shape, 3)
+    return a + f * (b - a)
+
+
 def pulse(d, bandwidth: float, fs: float, half: int):
     """Compressed pulse h(d) at offset d samples from the true delay (numpy or torch)."""
     if isinstance(d, np.ndarray):
@@ -89,7 +108,8 @@ def pulse(d, bandwidth: float, fs: float, half: int):
 def synthesize_echo(scn: Scenario, device="cpu", dtype=torch.complex128,
                     tx: np.ndarray | None = None, rx: np.ndarray | None = None,
                     max_chunk: int = 1 << 22, noise: bool = True, noise_on_device: bool = False,
-                    rx_vel: np.ndarray | None = None, refraction: tuple | None = None) -> torch.Tensor:
+                    rx_vel: np.ndarray | None = None, refraction: tuple | None = None,
+                    rx_track: tuple | None = None) -> torch.Tensor:
     """Echo cube [P, E, N_s] for the scenario, optionally with its seeded noise.
 
     ``tx``/``rx`` default to the positions the scene was recorded with
@@ -108,6 +128,8 @@ def synthesize_echo(scn: Scenario, device="cpu", dtype=torch.complex128,
     txd = torch.as_tensor(tx, dtype=f64, device=dev)
     rxd = torch.as_tensor(rx, dtype=f64, device=dev)
     veld = None if rx_vel is None else torch.as_tensor(rx_vel, dtype=f64, device=dev)
+    trk = None if rx_track is None else torch.as_tensor(np.asarray(rx_track[0]), dtype=f64, device=dev)
+    trk_h = None if rx_track is None else float(rx_track[1])
     H = int(scn.taper_half)
     taps = torch.arange(-H + 1, H + 1, device=dev, dtype=f64)
     sin_g = math.sin(scn.gate_half_angle) if scn.gate_half_angle > 0 else None
@@ -125,6 +147,12 @@ def synthesize_echo(scn: Scenario, device="cpu", dtype=torch.complex128,
             tT = _leg_time(T[:, None, :], pos[None, :, :], scn.c, refraction)           # [p,S]
             tR = _leg_time(R[:, None, :, :], pos[None, :, None, :], scn.c, refraction)  # [p,S,E]
             tau = tT[:, :, None] + tR
+        if trk is not None:
+            Tk = trk[i0:i1]                                                           # [p,N,3]
+            rel = pos[None, :, None, :] - R[:, None, :, :]                            # [p,S,E,3]
+            for _ in range(8):
+                moved = rel - _track_at(Tk, trk_h, tau)
+                tau = (dT[:, :, None] + torch.linalg.norm(moved, dim=-1)) / scn.c
         if veld is not None:
             V = veld[i0:i1]                                                           # [p,3]
             rel = pos[None, :, None, :] - R[:, None, :, :]                            # [p,S,E,3]

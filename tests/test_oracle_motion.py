@@ -118,3 +118,127 @@ def test_p12_pins_reject_mutation(name):
     got = mod.backproject(echo, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, p[None, :], rx_vel=vel)[0]
     ok = ok and abs(np.angle(got / amp)) < 1e-10
     assert not ok, f"mutation {name} survived"
+
+
+# ------------------------------------------------------------ position table
+#
+# P12d: with a table that samples a straight line, Delta(t) = v t, the table
+#   delay (bisection) equals the closed-form root of the constant-velocity
+#   quadratic (``motion_delay``, pinned by P12b).
+# P12e: a lone scatterer whose echo is synthesized with a curved table (the
+#   synthesis finds each delay by fixed-point iteration with its own
+#   interpolation) images to the P2 closed form with zero residual phase; the
+#   same echo imaged with the table shifted by one sample does not.
+# P12f: the defining equation holds at the root, and the interpolation is
+#   exact at the samples and linear between and past them.
+
+def curved_track(scn, n_samp=40, h=2e-3, seed=5):
+    """A table per ping: surge 1.5 m/s plus sinusoidal sway and heave
+    accelerations (up to about 0.5 m/s^2), displacement zero at transmit."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(n_samp) * h
+    P = scn.n_ping
+    tab = np.zeros((P, n_samp, 3))
+    for i in range(P):
+        w = rng.uniform(5.0, 15.0, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        amp = np.array([0.003, 0.004, 0.002])
+        tab[i] = amp * (np.sin(w * t[:, None] + ph) - np.sin(ph))
+        tab[i, :, 0] += 1.5 * t
+    return tab, h
+
+
+def test_p12d_straight_table_equals_constant_velocity_root():
+    rng = np.random.default_rng(4)
+    c = 1500.0
+    for speed in (0.3, 2.9, 20.0):
+        a = rng.normal(size=(400, 3)) * rng.uniform(0.5, 80.0, size=(400, 1))
+        d_T = np.linalg.norm(a + rng.normal(size=(400, 3)) * 0.2, axis=1)
+        v = rng.normal(size=3)
+        v *= speed / np.linalg.norm(v)
+        h = 1e-3
+        table = np.arange(7)[:, None] * h * v[None, :]      # covers 6 ms; later delays use the extension
+        got = oracle.track_delay(d_T, a, table, h, c)
+        want = oracle.motion_delay(d_T, a, v, c)
+        assert np.max(np.abs(got - want) / want) < 1e-13, speed
+
+
+def test_p12f_interpolation_and_defining_equation():
+    table = np.array([[0.0, 0.0, 0.0], [1.0, -2.0, 0.5], [1.5, -1.0, 0.5]])
+    h = 0.5
+    t = np.array([0.0, 0.5, 1.0, 0.25, 0.75, -0.5, 1.5])
+    want = np.array([[0, 0, 0], [1, -2, 0.5], [1.5, -1, 0.5], [0.5, -1, 0.25], [1.25, -1.5, 0.5],
+                     [-1, 2, -0.5], [2.0, 0.0, 0.5]])
+    assert np.allclose(oracle.track_position(table, h, t), want, atol=1e-15)
+    scn = make_config("c1", n_ping=2, n_elem=2)
+    tab, hh = curved_track(scn)
+    rng = np.random.default_rng(2)
+    a = rng.normal(size=(200, 3)) * 30.0
+    d_T = np.linalg.norm(a, axis=1) + rng.uniform(-0.5, 0.5, 200)
+    tau = oracle.track_delay(d_T, a, tab[0], hh, 1500.0)
+    resid = 1500.0 * tau - d_T - np.linalg.norm(a - oracle.track_position(tab[0], hh, tau), axis=1)
+    assert np.max(np.abs(resid)) < 1e-10
+
+
+def test_p12e_lone_scatterer_closed_form_with_a_table():
+    amp = 0.6 + 0.5j
+    scn = make_config("c1", n_scat=1, snr_db=None, n_ping=12, n_elem=4, nx=32, ny=32)
+    p = scn.grid.points(np.array([11 * 32 + 20]))[0]
+    scn.scat_pos = p[None, :].copy()
+    scn.scat_amp = np.array([amp])
+    tab, h = curved_track(scn)
+    echo = synthesize_echo(scn, noise=False, rx_track=(tab, h)).numpy()
+    got = oracle.backproject(echo, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, p[None, :],
+                             rx_track=(tab, h))[0]
+    hfun = lambda d: pulse(np.asarray(d, dtype=np.float64), scn.bandwidth, scn.fs, scn.taper_half)
+    want = 0.0
+    for i in range(scn.n_ping):
+        d_T = np.sqrt(((scn.tx[i] - p) ** 2).sum())
+        for e in range(scn.n_elem):
+            tau = oracle.track_delay(np.array([d_T]), (p - scn.rx[i, e])[None, :], tab[i], h, scn.c)[0]
+            u = (tau - scn.t0) * scn.fs
+            w = u - np.floor(u)
+            want += (1 - w) * hfun(-w) + w * hfun(1 - w)
+    want = amp * want
+    assert abs(got - want) <= 1e-9 * abs(want)
+    # the table shifted by one sample (a slip of the time origin) misses it
+    shifted = np.concatenate([tab[:, 1:], 2 * tab[:, -1:] - tab[:, -2:-1]], axis=1)
+    bad = oracle.backproject(echo, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, p[None, :],
+                             rx_track=(shifted, h))[0]
+    assert abs(bad - want) > 1e-3 * abs(want)
+
+
+TABLE_MUTATIONS = {
+    "segment_off_by_one": ("j = np.clip(np.floor(t / h), 0, n - 2)", "j = np.clip(np.floor(t / h) + 1, 0, n - 2)"),
+    "ends_clamped": ("frac = t / h - j ", "frac = np.clip(t / h - j, 0.0, 1.0) "),
+    "slope_sign": ("return table[j] + frac[:, None] * (table[j + 1] - table[j])",
+                   "return table[j] - frac[:, None] * (table[j + 1] - table[j])"),
+    "bracket_direction": ("neg = f(mid) < 0.0", "neg = f(mid) > 0.0"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TABLE_MUTATIONS))
+def test_p12_table_pins_reject_mutation(name):
+    mod0 = importlib.import_module("oracle.tdbp")
+    old, new = TABLE_MUTATIONS[name]
+    src = inspect.getsource(mod0)
+    assert src.count(old) == 1
+    mod = types.ModuleType("tdbp_mutant")
+    exec(compile(src.replace(old, new), "tdbp_mutant", "exec"), mod.__dict__)
+    rng = np.random.default_rng(4)
+    a = rng.normal(size=(200, 3)) * 30.0
+    d_T = np.linalg.norm(a + 0.1, axis=1)
+    v = np.array([2.9, 0.2, -0.1])
+    h = 1e-3
+    table = np.arange(7)[:, None] * h * v[None, :]
+    ok = np.max(np.abs(mod.track_delay(d_T, a, table, h, 1500.0) - oracle.motion_delay(d_T, a, v, 1500.0))) < 1e-15
+    amp = 0.6 + 0.5j
+    scn = make_config("c1", n_scat=1, snr_db=None, n_ping=12, n_elem=4, nx=32, ny=32)
+    p = scn.grid.points(np.array([11 * 32 + 20]))[0]
+    scn.scat_pos = p[None, :].copy()
+    scn.scat_amp = np.array([amp])
+    tab, hh = curved_track(scn)
+    echo = synthesize_echo(scn, noise=False, rx_track=(tab, hh)).numpy()
+    got = mod.backproject(echo, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, p[None, :], rx_track=(tab, hh))[0]
+    ok = ok and abs(np.angle(got / amp)) < 1e-9
+    assert not ok, f"mutation {name} survived"
