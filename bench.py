@@ -271,19 +271,33 @@ def sinc_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_kerne
             "rel_l2": r, "max_phase_mrad": ph, "sample_pixels": sample}
 
 
-def motion_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_kernel_ms: float, sample: int) -> dict:
-    """Continuous receiver motion during reception on the same swath (the
-    receivers moving at the track's 1.46 m/s during each ping's reception):
-    image kernel time, and its error against the oracle's exact delay root on
-    a seeded pixel sample (same echo cube; the timing does not depend on it)."""
+def motion_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_kernel_ms: float, sample: int,
+               model: str = "velocity") -> dict:
+    """Continuous receiver motion during reception on the same swath: the
+    receivers moving at the track's 1.46 m/s (``velocity``), or displaced
+    along an up-sampled position table (``table``: 2 ms samples, 1.5 m/s
+    surge with millimetre sway and heave oscillations) during each ping's
+    reception. Image kernel time, and its error against the oracle's exact
+    delay root on a seeded pixel sample (same echo cube; the timing does not
+    depend on it)."""
     import oracle
-    from synth import subset_indices, receiver_velocity
-    vel = receiver_velocity(scn)
+    from synth import subset_indices, receiver_velocity, receiver_track
     d = _desc(api, scn)
-    d.motion = 1
-    plan = api.sas_bp_plan([d])
     buf = _buffers(api, scn, echo)
-    buf.rx_vel = torch.as_tensor(vel, dtype=torch.float64, device="cuda")
+    if model == "table":
+        tab, h = receiver_track(scn)
+        d.motion, d.track_n, d.track_dt = 2, tab.shape[1], h
+        buf.rx_track = torch.as_tensor(tab, dtype=torch.float64, device="cuda")
+        kw = dict(rx_track=(tab, h))
+        what = "receivers displaced along a position table (per ping and tile the line of the segment at the " \
+               "centre's delay, certified within 2e-6 m; FP64 centre root, per-pixel Newton step)"
+    else:
+        vel = receiver_velocity(scn)
+        d.motion = 1
+        buf.rx_vel = torch.as_tensor(vel, dtype=torch.float64, device="cuda")
+        kw = dict(rx_vel=vel)
+        what = "receivers moving during reception (exact FP64 centre root, per-pixel Newton step)"
+    plan = api.sas_bp_plan([d])
     api.sas_bp_set_kernel_timing(plan, True)
     for _ in range(warmup):
         api.sas_bp_image(plan, [buf])
@@ -297,13 +311,12 @@ def motion_leg(api, scn, echo, useful: int, steps: int, warmup: int, forward_ker
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, idx)
     ref = oracle.backproject(echo.cpu().numpy(), scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
-                             scn.gate_half_angle, workers=oracle_workers(), rx_vel=vel)
+                             scn.gate_half_angle, workers=oracle_workers(), chunk=32, **kw)
     r, ph = oracle.rel_l2(got, ref), oracle.phase_error_mrad(got, ref)
-    log(f"motion: {ms:.3f} ms/step, image kernel {kms:.3f} ms ({kms / forward_kernel_ms:.2f}x stop-and-hop), "
+    log(f"motion ({model}): {ms:.3f} ms/step, image kernel {kms:.3f} ms ({kms / forward_kernel_ms:.2f}x stop-and-hop), "
         f"rel_l2 {r:.2e}, max phase {ph:.3f} mrad on {sample} pixels, status {status}")
     plan.destroy()
-    return {"model": "receivers moving during reception (exact FP64 centre root, per-pixel Newton step)",
-            "ms_per_step": ms, "image_kernel_ms": kms, "useful_updates_per_s": useful / (kms * 1e-3),
+    return {"model": what, "ms_per_step": ms, "image_kernel_ms": kms, "useful_updates_per_s": useful / (kms * 1e-3),
             "vs_stop_and_hop_kernel": kms / forward_kernel_ms, "rel_l2": r, "max_phase_mrad": ph,
             "sample_pixels": sample, "status": status}
 
@@ -748,6 +761,8 @@ def main() -> int:
         out["sinc8"] = sinc_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
     if not args.no_motion:
         out["motion"] = motion_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512)
+        out["motion_table"] = motion_leg(api, scn, echo, useful, max(3, args.steps // 4), 1, kernel_ms, 512,
+                                         model="table")
     if not args.no_reprojection:
         out["reprojection"] = reprojection_leg(api, plan, buf, useful, max(3, args.steps // 4), 1, kernel_ms)
     if not args.no_volume:

@@ -16,12 +16,13 @@
  *   I(p) = sum_i sum_e g * L * exp(+j 2 pi f_c tau)
  *
  * Positions are fixed during a ping (stop-and-hop) unless a swath selects
- * continuous motion (desc.motion = 1, the receiver location x_RX(t) of Eq. 1
+ * continuous motion (desc.motion, the receiver location x_RX(t) of Eq. 1
  * with the transmitter stationary while it transmits): the receivers then move
- * at the ping's velocity v_i during reception, R_ie(t) = R_ie + v_i t, and tau
- * is the root of c tau = d_T + |p - R_ie - v_i tau| (the gate keeps the
- * ping-time positions). Echoes are range compressed and at complex baseband,
- * so the carrier phase is re-applied.
+ * during reception, at the ping's velocity, R_ie(t) = R_ie + v_i t, or along
+ * the ping's up-sampled position table, R_ie(t) = R_ie + Delta_i(t), and tau
+ * is the root of c tau = d_T + |p - R_ie(tau)| (the gate keeps the ping-time
+ * positions). Echoes are range compressed and at complex baseband, so the
+ * carrier phase is re-applied.
  * Axes are north-east-down (Sec. II-B): x along-track, y across, z down.
  * A pixel centre is origin + index * spacing on each axis.
  *
@@ -56,7 +57,7 @@
 extern "C" {
 #endif
 
-#define SAS_BP_ABI_VERSION 5
+#define SAS_BP_ABI_VERSION 6
 
 typedef struct sas_bp_plan_s* sas_bp_plan_t;
 
@@ -94,6 +95,28 @@ enum sas_bp_interp {
     SAS_BP_INTERP_SINC8 = 1
 };
 
+/* Receiver motion during reception (sas_bp_swath_desc.motion; the receiver
+ * location x_RX(t) of Eq. 1, the transmitter stationary while it transmits):
+ *   STOP_AND_HOP : receivers fixed at rx_pos for the whole ping (the default)
+ *   VELOCITY     : R(t) = rx_pos + v t with v = io.rx_vel of the ping
+ *   TABLE        : R(t) = rx_pos + Delta(t), Delta linear between the ping's
+ *                  up-sampled track samples io.rx_track[j] at t = j track_dt
+ *                  (and along the first and last segments beyond the ends),
+ *                  the paper's interpolated position table (Sec. II-C).
+ * t is time after transmit; tau solves c tau = |p - T| + |p - R(tau)|. The
+ * beam gate keeps the ping-time positions. Linear interpolation only; image
+ * only (the adjoint and reprojection refuse motion). For TABLE the kernel
+ * takes, per tile and ping, the straight line of the table segment that holds
+ * the tile centre's delay and certifies, per (tile, ping, element), that the
+ * table departs from that line by at most 2e-6 m over the tile's delays
+ * (from the largest velocity change between segments); a record that fails
+ * that bound is reported like bad navigation (SAS_BP_ENAV). */
+enum sas_bp_motion {
+    SAS_BP_MOTION_STOP_AND_HOP = 0,
+    SAS_BP_MOTION_VELOCITY = 1,
+    SAS_BP_MOTION_TABLE = 2
+};
+
 /* One swath: acquisition constants and image grid. */
 typedef struct {
     int32_t n_ping;         /* P >= 1                                          */
@@ -109,12 +132,11 @@ typedef struct {
     double gate_half_angle; /* radians in [0, pi/2); 0 disables the beam gate */
     double c_min;           /* smallest sound speed the plan must accept, m/s; 0 selects 1400 */
     int32_t interp;         /* enum sas_bp_interp; all swaths of a plan share it */
-    int32_t motion;         /* 0: stop-and-hop; 1: receivers move at io.rx_vel during
-                               reception (linear interpolation only; image only: the
-                               adjoint and reprojection refuse it). All swaths of a
-                               plan share it. A velocity that is not finite, |v| >= c/2,
-                               or one that moves a delay by more than one sample across
-                               a tile, is reported like bad navigation (SAS_BP_ENAV). */
+    int32_t motion;         /* enum sas_bp_motion. All swaths of a plan share it. A
+                               velocity (or table segment) that is not finite, of speed
+                               >= c/2, or one that moves a delay by more than one sample
+                               across a tile, is reported like bad navigation
+                               (SAS_BP_ENAV). */
     int32_t refract;        /* 1: sediment-water interface refraction in the propagation
                                time (Sec. III-B): the flat seafloor z = z_interface
                                separates water (sound speed c, above; the array must be
@@ -124,9 +146,10 @@ typedef struct {
                                the gate keeps straight lines. Linear interpolation, no
                                motion, image only; the crossing is found in FP32, the
                                leg times and the delay are FP64. */
-    int32_t reserved0;      /* 0 */
+    int32_t track_n;        /* samples per ping of io.rx_track, 2..2^24 (motion = TABLE) */
     double c_sediment;      /* m/s, > 0 (refract = 1)                             */
     double z_interface;     /* m, the interface depth (refract = 1)               */
+    double track_dt;        /* s between samples of io.rx_track, > 0 (motion = TABLE) */
 } sas_bp_swath_desc;
 
 /* Where the plan's tiling comes from (sas_bp_options.tune_mode).
@@ -182,7 +205,10 @@ typedef struct {
     const double* c;         /* f64[1] sound speed, read on the device at every call        */
     void* image;             /* complex64 [nz][ny][nx] output (x fastest), overwritten      */
     const double* rx_vel;    /* f64[P][3] receiver velocity during reception of each ping,
-                                m/s; required when desc.motion = 1, ignored otherwise       */
+                                m/s; required when desc.motion = VELOCITY, else ignored     */
+    const double* rx_track;  /* f64[P][track_n][3] displacement of each ping's receivers
+                                from rx_pos at t = j track_dt after transmit, m (normally 0
+                                at j = 0); required when desc.motion = TABLE, else ignored  */
 } sas_bp_swath_io;
 
 /* Make a plan for n_swaths swaths (1..4096). Validates every descriptor,

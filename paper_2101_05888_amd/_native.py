@@ -33,8 +33,8 @@ class SwathDesc(C.Structure):
         ("n", C.c_int64 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
         ("f_c", C.c_double), ("f_s", C.c_double), ("t0", C.c_double),
         ("gate_half_angle", C.c_double), ("c_min", C.c_double), ("interp", C.c_int32),
-        ("motion", C.c_int32), ("refract", C.c_int32), ("reserved0", C.c_int32), ("c_sediment", C.c_double),
-        ("z_interface", C.c_double),
+        ("motion", C.c_int32), ("refract", C.c_int32), ("track_n", C.c_int32), ("c_sediment", C.c_double),
+        ("z_interface", C.c_double), ("track_dt", C.c_double),
     ]
 
 
@@ -60,6 +60,7 @@ class SwathIO(C.Structure):
     _fields_ = [
         ("echo", C.c_void_p), ("echo_scale", C.c_void_p), ("tx_pos", C.c_void_p),
         ("rx_pos", C.c_void_p), ("c", C.c_void_p), ("image", C.c_void_p), ("rx_vel", C.c_void_p),
+        ("rx_track", C.c_void_p),
     ]
 
 

@@ -26,11 +26,14 @@ TUNE_MODES = {"default": N.TUNE_DEFAULT, "cached": N.TUNE_CACHED, "search": N.TU
 def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin: Sequence[float],
                spacing: Sequence[float], f_c: float, f_s: float, t0: float = 0.0,
                gate_half_angle: float = 0.0, echo_dtype: str = "c64", c_min: float = 0.0,
-               interp: str = "linear", motion: bool = False, refraction=None) -> N.SwathDesc:
+               interp: str = "linear", motion=False, refraction=None, track=None) -> N.SwathDesc:
     """Descriptor of one swath; ``interp`` is "linear" or "sinc8" (the
     Hann-windowed sinc over 8 samples); ``motion`` selects receivers moving
-    during reception (``SwathBuffers.rx_vel``); ``refraction`` = (c_sediment,
-    z_interface) a sediment-water interface in the propagation time."""
+    during reception: True or "velocity" (``SwathBuffers.rx_vel``), or
+    "table" with ``track`` = (samples per ping, seconds between samples) for
+    an up-sampled position table (``SwathBuffers.rx_track``); ``refraction``
+    = (c_sediment, z_interface) a sediment-water interface in the
+    propagation time."""
     if interp not in INTERPS:
         raise ValueError(f"interp must be one of {sorted(INTERPS)}")
     d = N.SwathDesc()
@@ -43,7 +46,16 @@ def swath_desc(n_ping: int, n_elem: int, n_sample: int, n: Sequence[int], origin
     d.f_c, d.f_s, d.t0 = float(f_c), float(f_s), float(t0)
     d.gate_half_angle, d.c_min = float(gate_half_angle), float(c_min)
     d.interp = INTERPS[interp]
-    d.motion = 1 if motion else 0
+    if motion == "table":
+        if track is None:
+            raise ValueError("motion='table' needs track=(samples per ping, seconds between samples)")
+        d.motion, d.track_n, d.track_dt = 2, int(track[0]), float(track[1])
+    elif motion in (True, 1, "velocity"):
+        d.motion = 1
+    elif motion in (False, 0, None, "stop_and_hop"):
+        d.motion = 0
+    else:
+        raise ValueError(f"unknown motion model {motion!r}")
     if refraction is not None:
         d.refract, d.c_sediment, d.z_interface = 1, float(refraction[0]), float(refraction[1])
     return d
@@ -135,6 +147,7 @@ class SwathBuffers:
     image: torch.Tensor                 # complex64 [nz,ny,nx]
     echo_scale: Optional[torch.Tensor] = None   # float32 [P] for 16-bit echoes
     rx_vel: Optional[torch.Tensor] = None       # float64 [P,3], receiver velocity (continuous motion)
+    rx_track: Optional[torch.Tensor] = None     # float64 [P,N,3], receiver displacement table (motion "table")
 
 
 def _need(t: torch.Tensor, name: str, dtype, shape, device) -> None:
@@ -172,8 +185,10 @@ def _io_for(descs, device, bufs: Sequence[SwathBuffers]):
         _need(b.rx, f"rx[{i}]", torch.float64, (P, E, 3), device)
         _need(b.c, f"c[{i}]", torch.float64, (1,), device)
         _need(b.image, f"image[{i}]", torch.complex64, (d.n[2], d.n[1], d.n[0]), device)
-        if d.motion:
+        if d.motion == 1:
             _need(b.rx_vel, f"rx_vel[{i}]", torch.float64, (P, 3), device)
+        if d.motion == 2:
+            _need(b.rx_track, f"rx_track[{i}]", torch.float64, (P, d.track_n, 3), device)
         arr[i].echo = b.echo.data_ptr()
         arr[i].echo_scale = b.echo_scale.data_ptr() if b.echo_scale is not None else None
         arr[i].tx_pos = b.tx.data_ptr()
@@ -181,6 +196,7 @@ def _io_for(descs, device, bufs: Sequence[SwathBuffers]):
         arr[i].c = b.c.data_ptr()
         arr[i].image = b.image.data_ptr()
         arr[i].rx_vel = b.rx_vel.data_ptr() if b.rx_vel is not None else None
+        arr[i].rx_track = b.rx_track.data_ptr() if b.rx_track is not None else None
     return arr
 
 

@@ -33,6 +33,7 @@ int image_lds_bytes(int RC, int E, int W, int ROWS, bool gate, bool motion);
 hipError_t launch_init(const Workspace& ws, hipStream_t st);
 hipError_t launch_cull(const Workspace& ws, int n_tiles, int TX, int TY, int TZ, int bucket_shift, hipStream_t st);
 hipError_t launch_order(const Workspace& ws, int n_tiles, int bucket_shift, hipStream_t st);
+hipError_t launch_track_stats(const Workspace& ws, int swath, int n_ping, hipStream_t st);
 hipError_t launch_image(ImageKernelFn fn, const Workspace& ws, int n_tiles, int grid, int threads, int lds_bytes,
                         hipStream_t st);
 hipError_t image_occupancy(ImageKernelFn fn, int threads, int lds_bytes, int* blocks_per_cu);
@@ -131,10 +132,11 @@ struct SwathPlan {
   int W, CP, RC, SC;
   int no_cull;
   double half_diag, c_min;
+  size_t tstats_off = 0;   // first ping of this swath's position-table statistics (motion = TABLE)
 };
 
 struct Layout {
-  size_t swaths, prange, order, counters, bucket, tile_swath, scratch, drc, geo, total;
+  size_t swaths, prange, order, counters, bucket, tile_swath, scratch, drc, tstats, geo, total;
   size_t geo_stride;   // bytes of geometry scratch per resident workgroup
   int geo_slots;       // resident workgroups the geometry scratch serves
   size_t n_partials;   // adjoint records, allocated on the first adjoint call
@@ -184,6 +186,7 @@ struct sas_bp_plan_s {
   std::vector<SwathPlan> sw;
   Layout lay{};
   unsigned char* slab = nullptr;
+  float4* tstats = nullptr;        // per-ping position-table statistics (motion = TABLE), in the slab
   Workspace ws{};
   ImageKernelFn image_fn = nullptr;
   AdjointKernelFn adjoint_fn = nullptr;
@@ -228,7 +231,10 @@ int validate(const sas_bp_swath_desc* d, int i) {
   if (!(d->c_min >= 0.0) || !finite(d->c_min)) return fail(SAS_BP_EINVAL, "swath %d: c_min must be >= 0", i);
   if (d->interp != SAS_BP_INTERP_LINEAR && d->interp != SAS_BP_INTERP_SINC8)
     return fail(SAS_BP_EINVAL, "swath %d: unknown interpolator %d", i, d->interp);
-  if (d->motion != 0 && d->motion != 1) return fail(SAS_BP_EINVAL, "swath %d: motion must be 0 or 1", i);
+  if (d->motion < 0 || d->motion > 2) return fail(SAS_BP_EINVAL, "swath %d: motion must be 0, 1 or 2", i);
+  if (d->motion == SAS_BP_MOTION_TABLE &&
+      (d->track_n < 2 || d->track_n > (1 << 24) || !(d->track_dt > 0.0) || !finite(d->track_dt)))
+    return fail(SAS_BP_EINVAL, "swath %d: a position table needs track_n in [2, 2^24] and track_dt > 0", i);
   if (d->motion && d->interp != SAS_BP_INTERP_LINEAR)
     return fail(SAS_BP_EUNSUPPORTED, "swath %d: continuous motion is built for linear interpolation only", i);
   if (d->refract != 0 && d->refract != 1) return fail(SAS_BP_EINVAL, "swath %d: refract must be 0 or 1", i);
@@ -377,7 +383,8 @@ int build_swaths(const sas_bp_swath_desc* d, int n, const sas_bp_options* o, con
   return SAS_BP_OK;
 }
 
-Layout make_layout(int n_swaths, int n_tiles, size_t n_partials, size_t geo_stride, int geo_slots) {
+Layout make_layout(int n_swaths, int n_tiles, size_t n_partials, size_t geo_stride, int geo_slots,
+                   size_t n_track_pings) {
   Layout L{};
   size_t o = 0;
   L.swaths = o;     o = align_up(o + sizeof(SwathDev) * n_swaths);
@@ -388,6 +395,7 @@ Layout make_layout(int n_swaths, int n_tiles, size_t n_partials, size_t geo_stri
   L.tile_swath = o; o = align_up(o + sizeof(int) * n_tiles);
   L.scratch = o;    o = align_up(o + sizeof(double) * (kSharpScratch + 16));
   L.drc = o;        o = align_up(o + drc_work_bytes());
+  L.tstats = o;     o = align_up(o + sizeof(float4) * n_track_pings);
   L.geo = o;        o = align_up(o + geo_stride * (size_t)geo_slots);
   L.geo_stride = geo_stride;
   L.geo_slots = geo_slots;
@@ -412,6 +420,8 @@ SwathDev make_dev(const SwathPlan& s) {
   v.dtype = s.d.echo_dtype;
   v.interp = s.d.interp;
   v.motion = s.d.motion;
+  v.track_n = s.d.motion == SAS_BP_MOTION_TABLE ? s.d.track_n : 0;
+  v.track_h = s.d.motion == SAS_BP_MOTION_TABLE ? s.d.track_dt : 0.0;
   v.refract = s.d.refract;
   v.no_cull = s.no_cull;
   v.c_sed = s.d.refract ? s.d.c_sediment : 0.0;
@@ -454,8 +464,10 @@ int check_io(const sas_bp_plan_s* p, const sas_bp_swath_io* io, int n) {
       return fail(SAS_BP_EINVAL, "swath %d: navigation not 8-byte aligned", i);
     if (s.d.echo_dtype != SAS_BP_ECHO_C64 && !io[i].echo_scale)
       return fail(SAS_BP_EINVAL, "swath %d: echo_scale required for 16-bit echoes", i);
-    if (s.d.motion && (!io[i].rx_vel || ((uintptr_t)io[i].rx_vel & 7u)))
+    if (s.d.motion == SAS_BP_MOTION_VELOCITY && (!io[i].rx_vel || ((uintptr_t)io[i].rx_vel & 7u)))
       return fail(SAS_BP_EINVAL, "swath %d: continuous motion needs an 8-byte aligned rx_vel", i);
+    if (s.d.motion == SAS_BP_MOTION_TABLE && (!io[i].rx_track || ((uintptr_t)io[i].rx_track & 7u)))
+      return fail(SAS_BP_EINVAL, "swath %d: a position table needs an 8-byte aligned rx_track", i);
   }
   return SAS_BP_OK;
 }
@@ -489,6 +501,8 @@ int timing_pair(sas_bp_plan_s* p, hipEvent_t* a, hipEvent_t* b) {
 
 int enqueue_image(sas_bp_plan_s* p, hipStream_t st) {
   HIP_TRY(launch_init(p->ws, st));
+  if (p->motion == SAS_BP_MOTION_TABLE)
+    for (int i = 0; i < p->n_swaths; ++i) HIP_TRY(launch_track_stats(p->ws, i, p->sw[i].d.n_ping, st));
   HIP_TRY(launch_cull(p->ws, p->n_tiles, p->tiling.TX, p->tiling.TY, p->tiling.TZ, p->bucket_shift, st));
   HIP_TRY(launch_order(p->ws, p->n_tiles, p->bucket_shift, st));
   hipEvent_t a = nullptr, b = nullptr;
@@ -599,7 +613,12 @@ int plan_sizes(const sas_bp_swath_desc* desc, int n, const sas_bp_options* o, Ti
   }
   const int per_cu = std::max(1, std::min(8, kLdsMax / std::max(1, lds)));
   const int slots = (int)std::min<long long>(*n_tiles, (long long)kMaxCUs * per_cu);
-  *lay = make_layout(n, *n_tiles, adjoint_partials(*sw), stride, slots);
+  size_t track_pings = 0;
+  for (auto& s : *sw) {
+    s.tstats_off = track_pings;
+    if (s.d.motion == SAS_BP_MOTION_TABLE) track_pings += (size_t)s.d.n_ping;
+  }
+  *lay = make_layout(n, *n_tiles, adjoint_partials(*sw), stride, slots, track_pings);
   return SAS_BP_OK;
 }
 
@@ -1261,7 +1280,8 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->lds_bytes = max_lds;
   p->adj_lds_bytes = max_adj_lds;
   p->image_fn = p->refract ? refract_kernel_for(t.layout, p->gate_any, p->dtype)
-                           : image_kernel_for(t.layout, p->gate_any, p->dtype, p->motion ? 2 : p->interp);
+                           : image_kernel_for(t.layout, p->gate_any, p->dtype,
+                                              p->motion == SAS_BP_MOTION_TABLE ? 3 : p->motion ? 2 : p->interp);
   p->adjoint_fn = adjoint_kernel_for(t.layout, p->gate_any, p->dtype);
   p->reproject_fn = reproject_kernel_for(t.layout, p->gate_any);
   if (!p->image_fn || !p->adjoint_fn || !p->reproject_fn) {
@@ -1317,6 +1337,7 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   p->ws.cpart = nullptr;
   p->ws.scratch64 = reinterpret_cast<double*>(p->slab + lay.scratch);
   p->ws.geo = p->slab + lay.geo;
+  p->tstats = reinterpret_cast<float4*>(p->slab + lay.tstats);
   p->ws.geo_stride = (long long)lay.geo_stride;
 
   std::vector<int> tile_swath(n_tiles);
@@ -1358,6 +1379,8 @@ int sas_bp_image(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swaths, void*
     v[i].tx = io[i].tx_pos;
     v[i].rx = io[i].rx_pos;
     v[i].vel = io[i].rx_vel;
+    v[i].track = io[i].rx_track;
+    v[i].tstats = p->tstats + p->sw[i].tstats_off;
     v[i].c = io[i].c;
     v[i].image = reinterpret_cast<float2*>(io[i].image);
   }
@@ -1402,6 +1425,8 @@ int sas_bp_adjoint(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* const
     v[i].tx = io[i].tx_pos;
     v[i].rx = io[i].rx_pos;
     v[i].vel = io[i].rx_vel;
+    v[i].track = io[i].rx_track;
+    v[i].tstats = p->tstats + p->sw[i].tstats_off;
     v[i].c = io[i].c;
     v[i].image = reinterpret_cast<float2*>(io[i].image);
     v[i].gimage = reinterpret_cast<const float2*>(grad_image[i]);
@@ -1465,6 +1490,8 @@ int sas_bp_reproject(sas_bp_plan_t p, const sas_bp_swath_io* io, const void* con
     v[i].tx = io[i].tx_pos;
     v[i].rx = io[i].rx_pos;
     v[i].vel = io[i].rx_vel;
+    v[i].track = io[i].rx_track;
+    v[i].tstats = p->tstats + p->sw[i].tstats_off;
     v[i].c = io[i].c;
     v[i].image = reinterpret_cast<float2*>(io[i].image);
     v[i].gimage = reinterpret_cast<const float2*>(image_in[i]);
@@ -1701,6 +1728,8 @@ int sas_bp_useful_updates(sas_bp_plan_t p, const sas_bp_swath_io* io, int n_swat
     v[i].tx = io[i].tx_pos;
     v[i].rx = io[i].rx_pos;
     v[i].vel = io[i].rx_vel;
+    v[i].track = io[i].rx_track;
+    v[i].tstats = p->tstats + p->sw[i].tstats_off;
     v[i].c = io[i].c;
     v[i].image = reinterpret_cast<float2*>(io[i].image);
   }

@@ -47,10 +47,16 @@ struct SwathDev {
   double* grad_rx;
   double* grad_c;
   float2* gecho;          // reprojection output (complex64, echo layout)
-  const double* vel;      // receiver velocity during reception [P][3] (continuous motion)
+  const double* vel;      // receiver velocity during reception [P][3] (motion 1)
+  const double* track;    // receiver displacement table [P][track_n][3] (motion 2)
+  float4* tstats;         // per ping of the table: (largest displacement over the record,
+                          // largest velocity change between segments, largest segment
+                          // speed, 1 if not finite) (motion 2)
+  double track_h;         // s between table samples (motion 2)
+  int track_n;            // table samples per ping (motion 2)
   int P, E, Ns, dtype;
   int interp;             // 0 linear, 1 windowed sinc over 2 * kSincHalf samples
-  int motion;             // 1: receivers move at vel during reception
+  int motion;             // 1: receivers move at vel during reception; 2: along the table
   int refract;            // 1: sediment below z_int refracts the legs (sound speed c_sed)
   int no_cull;            // 1: no block cull (every ping of every tile, every record decided per row)
   double c_sed, z_int;
@@ -96,8 +102,12 @@ struct Workspace {
 //   receiver records [SC][E] (48 B)   window starts [SC][E] (int)
 //   transmitter records [SC] (32 B)   gate rows [SC][E][ROWS] (int, gate only)
 //   continuous motion only: motion offsets at the tile centre [SC][E] (float),
-//   ping velocities [SC] (float4: vx, vy, vz, |v|^2)
+//   per ping the straight line the receivers follow, R(t) = R + c + v t
+//   (3 float4: (v, |v|^2), (c, |c|^2), (c.v, segment index as int bits, 0, 0);
+//   c = 0 for a constant velocity; for a table, the segment that holds the
+//   tile centre's delay)
 constexpr int kRxRecBytes = 48;
+constexpr int kMotionLineBytes = 48;
 constexpr int kTxRecBytes = 32;
 
 struct GeoLayout {
@@ -115,7 +125,7 @@ __host__ __device__ inline GeoLayout geo_layout(int SC, int E, int ROWS, bool ga
   o = (o + 15) & ~15ll;
   g.dc = o;   o += motion ? (long long)SC * E * 4 : 0;
   o = (o + 15) & ~15ll;
-  g.vel = o;  o += motion ? (long long)SC * 16 : 0;
+  g.vel = o;  o += motion ? (long long)SC * kMotionLineBytes : 0;
   g.bytes = (o + 255) & ~255ll;
   return g;
 }

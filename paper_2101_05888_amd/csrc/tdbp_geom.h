@@ -42,6 +42,8 @@ constexpr unsigned kFlagPoly = 4u;   // receiver offset by the series (degree 5,
 constexpr unsigned kFlagDeg4 = 8u;   // the degree-4 series already meets the bound
 constexpr int kEmptyRow = 30000;     // encodes an empty gate interval (never matches a local x)
 constexpr double kPolyTol = 1e-8;    // metres, bound on the series truncation error
+constexpr double kTrackTol = 2e-6;   // metres, bound on the departure of a position table from
+                                     // the straight line a record uses for it
 
 __device__ __forceinline__ double tile_centre(const SwathDev& sw, int a, int first, int extent) {
   return sw.o[a] + ((double)first + 0.5 * (double)(extent - 1)) * sw.d[a];
@@ -91,21 +93,86 @@ __host__ __device__ inline bool cone_may_hit(double tan_g, double xa, double xb,
   return dxm <= tan_g * rho * (1.0 + 1e-9) + 1e-9;
 }
 
+// Position table (motion 2): ping p's displacement Delta(t) is linear between
+// samples j h and (j + 1) h. The straight line through segment j, written
+// Delta(t) = q + v t, and the segment that holds a delay tau (the first and
+// last segments continue past the table's ends).
+__device__ __forceinline__ void track_line(const SwathDev& sw, int p, int j, double q[3], double v[3]) {
+  const double* a = sw.track + ((size_t)p * sw.track_n + j) * 3;
+  const double t = (double)j * sw.track_h;
+  for (int k = 0; k < 3; ++k) {
+    v[k] = (a[3 + k] - a[k]) / sw.track_h;
+    q[k] = a[k] - v[k] * t;
+  }
+}
+
+__device__ __forceinline__ int track_segment_of(const SwathDev& sw, double tau) {
+  const double u = floor(tau / sw.track_h);
+  if (!(u >= 0.0)) return 0;                       // also a delay that is not finite
+  return u >= (double)(sw.track_n - 2) ? sw.track_n - 2 : (int)u;
+}
+
+// The segment whose line ping p's records of the tile use: the one holding
+// the tile centre's delay with the transmitter's own position standing for
+// the receivers (they lie within the array's length of it), by fixed-point
+// iteration on c tau = d_T + |C - T - Delta(tau)| (contraction |v| / c).
+__device__ __forceinline__ int track_segment(const SwathDev& sw, int p, const double C[3], double c) {
+  const double* T = sw.tx + (size_t)p * 3;
+  const double u0 = C[0] - T[0], u1 = C[1] - T[1], u2 = C[2] - T[2];
+  const double d = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+  double tau = 2.0 * d / c;
+  for (int it = 0; it < 12; ++it) {
+    const int j = track_segment_of(sw, tau);
+    double q[3], v[3];
+    track_line(sw, p, j, q, v);
+    const double w0 = u0 - q[0] - v[0] * tau, w1 = u1 - q[1] - v[1] * tau, w2 = u2 - q[2] - v[2] * tau;
+    tau = (d + sqrt(w0 * w0 + w1 * w1 + w2 * w2)) / c;
+  }
+  return track_segment_of(sw, tau);
+}
+
+// Largest departure of ping p's table from the line of segment j over delays
+// [ta, tb]: past each knot where the slope changes (t_{j+1} .. t_{N-2} above
+// the segment, t_j .. t_1 below it) the table turns by at most A, the
+// largest velocity change between neighbouring segments, so at distance d
+// past the first such knot it is off by at most A sum_k (d - k h) over the
+// knots passed.
+__device__ __forceinline__ double track_line_error(const SwathDev& sw, int p, int j, double ta, double tb) {
+  const double h = sw.track_h;
+  const double A = (double)sw.tstats[p].y * (1.0 + 1e-6);
+  double e = 0.0;
+  const double db = tb - (double)(j + 1) * h;
+  if (db > 0.0) {
+    const double k = fmin(floor(db / h) + 1.0, (double)(sw.track_n - 2 - j));
+    if (k > 0.0) e += A * (k * db - 0.5 * h * k * (k - 1.0));
+  }
+  const double da = (double)j * h - ta;
+  if (da > 0.0) {
+    const double k = fmin(floor(da / h) + 1.0, (double)j);
+    if (k > 0.0) e += A * (k * da - 0.5 * h * k * (k - 1.0));
+  }
+  return e;
+}
+
 // Receiver record and window start for (ping p, element e) of the tile centred
 // at C. Returns false if the navigation is not finite (record marked skip).
 //
-// MOTION (receivers moving at v_p during reception, R(t) = R + v_p t): the
-// reference delay is the exact root of c tau = d_T + |C - R - v_p tau| at the
-// tile centre (the larger root of (c^2 - |v|^2) tau^2 - 2 (c d_T - a.v) tau +
-// d_T^2 - |a|^2 = 0, a = C - R), *dc_out the extra path c tau - d_T - d_R it
-// implies, and the window starts one sample earlier (the plan adds two samples
-// to W). A bound on how much that extra path changes across the tile,
-// r (2 |v| tau_max / (d_R - r) + 4 |v| / c), must stay within one sample;
-// otherwise, or for a velocity not finite or of |v| >= c / 2, the record is
-// refused like bad navigation.
+// MOTION (receivers moving during reception along the straight line
+// R(t) = R + q + v t: a constant velocity v_p with q = 0, or segment jseg of
+// the ping's position table): the reference delay is the exact root of
+// c tau = d_T + |C - R - q - v tau| at the tile centre (the larger root of
+// (c^2 - |v|^2) tau^2 - 2 (c d_T - a.v) tau + d_T^2 - |a|^2 = 0, a = C - R - q),
+// *dc_out the extra path c tau - d_T - d_R it implies, and the window starts
+// one sample earlier (the plan adds two samples to W). A bound on how much
+// that extra path changes across the tile, r (2 W / (d_R - r) + 4 |v| / c)
+// with W = |q| + |v| tau_max the line's largest displacement, must stay
+// within one sample; for a table, the table's departure from the line over
+// the tile's delays must stay within kTrackTol; otherwise, or for a line not
+// finite or of |v| >= c / 2, the record is refused like bad navigation.
 template <bool MOTION = false>
 __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c, const double C[3], int p, int e,
-                                               RxRec* rec, int* n0_out, double c = 0.0, float* dc_out = nullptr) {
+                                               RxRec* rec, int* n0_out, double c = 0.0, float* dc_out = nullptr,
+                                               int jseg = 0) {
   const double* T = sw.tx + (size_t)p * 3;
   const double* R = sw.rx + ((size_t)p * sw.E + e) * 3;
   const double tx0 = T[0], tx1 = T[1], tx2 = T[2];
@@ -117,16 +184,33 @@ __device__ __forceinline__ bool make_rx_record(const SwathDev& sw, double inv_c,
   bool ok = finite3(tx0, tx1, tx2) && finite3(rx0, rx1, rx2);
   double tau = (d0T + d0R) * inv_c;
   if constexpr (MOTION) {
-    const double* V = sw.vel + (size_t)p * 3;
-    const double v0 = V[0], v1 = V[1], v2 = V[2];
+    double q[3] = {0.0, 0.0, 0.0}, v[3];
+    if (sw.motion == 2) {
+      track_line(sw, p, jseg, q, v);
+    } else {
+      const double* V = sw.vel + (size_t)p * 3;
+      v[0] = V[0];
+      v[1] = V[1];
+      v[2] = V[2];
+    }
+    const double v0 = v[0], v1 = v[1], v2 = v[2];
+    const double a0 = uR0 - q[0], a1 = uR1 - q[1], a2 = uR2 - q[2];
     const double vv = v0 * v0 + v1 * v1 + v2 * v2;
-    const double av = uR0 * v0 + uR1 * v1 + uR2 * v2;
+    const double av = a0 * v0 + a1 * v1 + a2 * v2;
     const double A = c * c - vv;
     const double Bh = c * d0T - av;
-    const double tm = (Bh + sqrt(Bh * Bh - A * (d0T * d0T - d0R * d0R))) / A;
+    const double tm = (Bh + sqrt(Bh * Bh - A * (d0T * d0T - (a0 * a0 + a1 * a1 + a2 * a2)))) / A;
     const double r = sw.half_diag, vm = sqrt(vv);
-    const double bound = r * (2.0 * vm * (tm + 2.0 * r * inv_c) / fmax(d0R - r, 1e-3) + 4.0 * vm * inv_c);
-    ok = ok && finite3(v0, v1, v2) && vv < 0.25 * c * c && isfinite(tm) && bound * sw.fs * inv_c <= 1.0;
+    const double wm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) + vm * (tm + 2.0 * r * inv_c);
+    const double bound = r * (2.0 * wm / fmax(d0R - r, 1e-3) + 4.0 * vm * inv_c);
+    ok = ok && finite3(v0, v1, v2) && finite3(q[0], q[1], q[2]) && vv < 0.25 * c * c && isfinite(tm) &&
+         bound * sw.fs * inv_c <= 1.0;
+    if (sw.motion == 2 && ok) {
+      // the pixels' delays lie within 2 r / c of the centre's, plus the one
+      // sample the motion path may change across the tile
+      const double s = 2.0 * r * inv_c + 2.0 / sw.fs;
+      ok = sw.tstats[p].w == 0.0f && track_line_error(sw, p, jseg, tm - s, tm + s) <= kTrackTol;
+    }
     double dcm = 0.0;
     if (ok) {
       dcm = c * tm - d0T - d0R;
@@ -261,7 +345,8 @@ struct LdsLayout {
 };
 
 // Continuous motion appends the records' motion offsets (float [NR]) and the
-// pings' velocities (float4 [NS]) after the windows.
+// pings' receiver lines (3 float4 each [NS], as in the geometry region) after
+// the windows.
 __host__ __device__ inline LdsLayout lds_layout(int NR, int NS, int W, int ROWS, bool gate, bool motion = false) {
   LdsLayout L;
   int o = 0;
@@ -273,7 +358,7 @@ __host__ __device__ inline LdsLayout lds_layout(int NR, int NS, int W, int ROWS,
   o = (o + 15) & ~15;
   L.off_win = o;  o += NR * (W + 1) * 16;
   L.off_dc = o;   o += motion ? ((NR * 4 + 15) & ~15) : 0;
-  L.off_vel = o;  o += motion ? NS * 16 : 0;
+  L.off_vel = o;  o += motion ? NS * kMotionLineBytes : 0;
   L.bytes = o;
   return L;
 }
@@ -288,7 +373,7 @@ struct Geo {
   TxRec* tx;
   int* rows;
   float* dc;      // continuous motion only
-  float4* vel;
+  float4* vel;    // 3 per ping: the receivers' line
 };
 
 __device__ __forceinline__ Geo geo_for(const Workspace& ws, const SwathDev& sw, int ROWS, bool gate) {
@@ -325,6 +410,27 @@ __device__ __forceinline__ void build_geometry(const Geo& g, int* lpart, int* ln
   const double by0 = sw.o[1] + (double)y0 * sw.d[1], by1 = by0 + (double)(LY - 1) * sw.d[1];
   const double bz0 = sw.o[2] + (double)z0 * sw.d[2], bz1 = bz0 + (double)(LZ - 1) * sw.d[2];
   if (tid == 0) *lnpart = 0;
+  if (MOTION) {
+    // each ping's receiver line first: the records of the ping share it
+#pragma unroll 1
+    for (int s = tid; s < sc; s += NT) {
+      const int p = P0 + s;
+      double q[3] = {0.0, 0.0, 0.0}, v[3];
+      int j = 0;
+      if (sw.motion == 2) {
+        j = track_segment(sw, p, C, c);
+        track_line(sw, p, j, q, v);
+      } else {
+        const double* V = sw.vel + (size_t)p * 3;
+        v[0] = V[0];
+        v[1] = V[1];
+        v[2] = V[2];
+      }
+      g.vel[3 * s] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+      g.vel[3 * s + 1] = make_float4((float)q[0], (float)q[1], (float)q[2], (float)(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]));
+      g.vel[3 * s + 2] = make_float4((float)(q[0] * v[0] + q[1] * v[1] + q[2] * v[2]), __int_as_float(j), 0.0f, 0.0f);
+    }
+  }
   __syncthreads();
 #pragma unroll 1
   for (int r = tid; r < sc * E; r += NT) {
@@ -333,7 +439,8 @@ __device__ __forceinline__ void build_geometry(const Geo& g, int* lpart, int* ln
     RxRec rec;
     int n0;
     float dcv = 0.0f;
-    if (!make_rx_record<MOTION>(sw, inv_c, C, p, e, &rec, &n0, c, &dcv)) atomicOr(&ws.counters[1], kStatusNav);
+    const int jseg = MOTION ? __float_as_int(g.vel[3 * slot + 2].y) : 0;
+    if (!make_rx_record<MOTION>(sw, inv_c, C, p, e, &rec, &n0, c, &dcv, jseg)) atomicOr(&ws.counters[1], kStatusNav);
     if (MOTION) g.dc[r] = dcv;
     unsigned f = __float_as_uint(rec.q0.w);
     if (!gate_on) {
@@ -355,13 +462,7 @@ __device__ __forceinline__ void build_geometry(const Geo& g, int* lpart, int* ln
     g.n0[r] = n0;
   }
 #pragma unroll 1
-  for (int s = tid; s < sc; s += NT) {
-    make_tx_record(sw, C, P0 + s, &g.tx[s]);
-    if (MOTION) {
-      const double* V = sw.vel + (size_t)(P0 + s) * 3;
-      g.vel[s] = make_float4((float)V[0], (float)V[1], (float)V[2], (float)(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]));
-    }
-  }
+  for (int s = tid; s < sc; s += NT) make_tx_record(sw, C, P0 + s, &g.tx[s]);
   __syncthreads();
   if (gate_on) {
     const int np = *lnpart;
@@ -596,7 +697,7 @@ __device__ __forceinline__ void load_records(unsigned char* lds, const Geo& g, c
     float* ldc = reinterpret_cast<float*>(lds + L.off_dc);
     float4* lvel = reinterpret_cast<float4*>(lds + L.off_vel);
     for (int r = tid; r < nr; r += NT) ldc[r] = g.dc[q0 + r];
-    for (int s = tid; s < ns; s += NT) lvel[s] = g.vel[s0 + s];
+    for (int s = tid; s < 3 * ns; s += NT) lvel[s] = g.vel[3 * s0 + s];
   }
   if (GATE && sw.tan_g > 0.0) {
     // rows of records that are not partial hold stale values and are never read

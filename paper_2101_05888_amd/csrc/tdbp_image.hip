@@ -58,11 +58,16 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
       // record test: the two-way delay of the tile lies within [dT0+dR0 - 2r, dT0+dR0 + 2r]
       const double u0 = C[0] - T[0], u1 = C[1] - T[1], u2 = C[2] - T[2];
       const double dT = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
-      // continuous motion moves a delay by at most |v| tau (the receiver's displacement)
-      double vm = 0.0;
-      if (sw.motion) {
+      // continuous motion moves a delay by at most the receiver's displacement:
+      // |v| tau for a velocity, the table's largest one over the record (with
+      // the line's departure from the table) for a table
+      double vm = 0.0, dmax = 0.0;
+      if (sw.motion == 1) {
         const double* V = sw.vel + (size_t)p * 3;
         vm = sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]);
+      } else if (sw.motion == 2) {
+        const float4 st = sw.tstats[p];
+        dmax = st.w == 0.0f ? (double)st.x * (1.0 + 1e-6) + 1e-5 : __builtin_nan("");
       }
       bool in_record = false;
       bool rx_hit = false;
@@ -73,7 +78,8 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
         const double ulo = ((dT + dR - 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
         const double uhi = ((dT + dR + 2.0 * sw.half_diag) / c - sw.t0) * sw.fs;
         double reach = sw.interp == 1 ? (double)kSincHalf : 0.0;   // taps beyond the delay
-        if (sw.motion) reach += vm * (dT + dR + 2.0 * sw.half_diag) / c * sw.fs / c + 1.0;
+        if (sw.motion == 1) reach += vm * (dT + dR + 2.0 * sw.half_diag) / c * sw.fs / c + 1.0;
+        if (sw.motion == 2) reach += dmax * sw.fs / c + 1.0;
         // refracted legs are not straight: the record test is left to the kernel
         const bool rec_e = sw.refract || sw.no_cull ||
                            ((uhi >= -2.0 - reach) && (ulo <= (double)sw.Ns + 1.0 + reach));
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
       if (sw.tan_g > 0.0 && !sw.no_cull) hit = cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, T) && rx_hit;
       // non-finite navigation makes every comparison false; keep such pings so
       // that the image kernel can flag them
-      const bool bad = !(isfinite(dT)) || !isfinite(vm);
+      const bool bad = !(isfinite(dT)) || !isfinite(vm) || !isfinite(dmax);
       if ((hit && in_record) || bad) {
         atomicMin(&s_lo, p);
         atomicMax(&s_hi, p);
@@ -102,6 +108,65 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
     int b = (int)(npe >> bucket_shift);
     b = b > kBuckets - 1 ? kBuckets - 1 : b;
     atomicAdd(&ws.bucket[b], 1u);
+  }
+}
+
+// Position tables (motion 2): per ping, over the delays a record can hold
+// (t in [0, t_end], t_end the end of the record plus two windows), the
+// largest displacement |Delta(t)| (at a sample or at t_end, Delta being
+// piecewise linear), the largest velocity change between neighbouring
+// segments, the largest segment speed, and a flag for values that are not
+// finite. One workgroup per ping; maxima of non-negative floats through
+// their bit patterns.
+__global__ __launch_bounds__(kThreads) void track_stats_kernel(Workspace ws, int s) {
+  const SwathDev& sw = ws.swaths[s];
+  const int p = blockIdx.x;
+  const int N = sw.track_n;
+  const double h = sw.track_h;
+  const double t_end = sw.t0 + (double)(sw.Ns + 2 * sw.W + 4) / sw.fs;
+  const double* a = sw.track + (size_t)p * N * 3;
+  // samples up to the last one at or before t_end, and the segment past it
+  const int jl = (int)fmin((double)(N - 1), fmax(1.0, floor(t_end / h) + 1.0));
+  __shared__ unsigned s_max[4];
+  if (threadIdx.x < 4) s_max[threadIdx.x] = 0u;
+  __syncthreads();
+  unsigned m0 = 0u, m1 = 0u, m2 = 0u, bad = 0u;
+  for (int j = threadIdx.x; j <= jl; j += blockDim.x) {
+    const double x = a[3 * j], y = a[3 * j + 1], z = a[3 * j + 2];
+    bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+    if ((double)j * h <= t_end) m0 = max(m0, __float_as_uint((float)sqrt(x * x + y * y + z * z)));
+    if (j < N - 1) {
+      const double* b = a + 3 * (j + 1);
+      const double vx = (b[0] - x) / h, vy = (b[1] - y) / h, vz = (b[2] - z) / h;
+      m2 = max(m2, __float_as_uint((float)sqrt(vx * vx + vy * vy + vz * vz)));
+      if (j > 0) {
+        const double* o = a + 3 * (j - 1);
+        const double ux = vx - (x - o[0]) / h, uy = vy - (y - o[1]) / h, uz = vz - (z - o[2]) / h;
+        m1 = max(m1, __float_as_uint((float)sqrt(ux * ux + uy * uy + uz * uz)));
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    // the displacement at t_end, on the segment that holds it (or the last one)
+    const int j = (int)fmin((double)(N - 2), fmax(0.0, floor(t_end / h)));
+    const double f = t_end / h - (double)j;
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double v = a[3 * j + k] + f * (a[3 * (j + 1) + k] - a[3 * j + k]);
+      d2 += v * v;
+    }
+    m0 = max(m0, __float_as_uint((float)sqrt(d2)));
+    bad |= !isfinite(d2);
+  }
+  atomicMax(&s_max[0], m0);
+  atomicMax(&s_max[1], m1);
+  atomicMax(&s_max[2], m2);
+  if (bad) atomicOr(&s_max[3], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // maxima rounded to FP32: nudged up so that they stay bounds
+    sw.tstats[p] = make_float4(__uint_as_float(s_max[0]) * 1.000001f, __uint_as_float(s_max[1]) * 1.000001f,
+                               __uint_as_float(s_max[2]) * 1.000001f, s_max[3] ? 1.0f : 0.0f);
   }
 }
 
@@ -129,12 +194,15 @@ __global__ __launch_bounds__(kThreads) void order_kernel(Workspace ws, int n_til
   }
 }
 
-// Continuous motion: per-record constants of the per-pixel correction.
+// Continuous motion: per-record constants of the per-pixel correction, the
+// receivers on the line R + q + v t.
 //   hx = (C - R)_x, avyz = ((C - R)_y + dy) v_y + ((C - R)_z + dz) v_z for the
 //   lane's row, (vx, vv) = (v_x, |v|^2), tc = (d0_T + d0_R + dc) / c with dc
-//   the motion path at the tile centre, ic = 1 / c.
+//   the motion path at the tile centre, ic = 1 / c; for a position table also
+//   (qx, aqyz) as (vx, avyz) for q, qq = |q|^2, qv = q.v.
 struct MotionTerm {
   float hx, avyz, vx, vv, tc, dc, ic;
+  float qx, aqyz, qq, qv;
 };
 
 // One (ping, element) record applied to the K pixels of a lane. DEG selects
@@ -149,12 +217,15 @@ struct MotionTerm {
 //     g = n / (|a - v tau_1| + |a|),  n = tau_1 (tau_1 |v|^2 - 2 a.v),
 //     F = g - dc,  eps = (a.v - tau_1 |v|^2) / (c |a - v tau_1|),
 //     delta = dc + F (1 - eps)
+// TRK (a position table) replaces the displacement v tau by the line's
+// w = q + v tau: n = |w|^2 - 2 a.w with a.w = a.q + tau_1 a.v and
+// |w|^2 = |q|^2 + tau_1 (2 q.v + tau_1 |v|^2), eps = (a.v - w.v) / (c |a - w|).
 // (the cancellation-free form of |a - w| - |a|; 1/(1 + eps) to first order,
 // eps ~ |v|/c, and 1/|a - v tau_1| as 2 / (|a - v tau_1| + |a|); the step
 // leaves errors far below a micrometre while |F| stays within the sample the
 // plan allows). The record's reference already holds dc, so the offset grows
 // by F (1 - eps).
-template <int K, int LX, int DEG, bool TEST, bool MOT = false>
+template <int K, int LX, int DEG, bool TEST, bool MOT = false, bool TRK = false>
 __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __restrict__ win, const float* dx,
                                            const float* dsq, const float* dT, float dyl, float dzl, float fs_c,
                                            float fc_c, float szero, int da, int span, float* accr,
@@ -181,14 +252,23 @@ __device__ __forceinline__ void accumulate(const RxRec& rec, const float4* __res
         dR = num * __builtin_amdgcn_rcpf(d0 + sq);
       }
       D = dR + dT[k];
-      const float av = fmaf(mt.hx + dx[k], mt.vx, mt.avyz);
+      const float hxd = mt.hx + dx[k];
+      const float av = fmaf(hxd, mt.vx, mt.avyz);
       const float am = d0 + dR;
       const float t1 = fmaf(D, mt.ic, mt.tc);
-      const float tvv = t1 * mt.vv;
-      const float n = t1 * fmaf(-2.0f, av, tvv);
+      float n, wv;
+      if constexpr (TRK) {
+        const float aq = fmaf(hxd, mt.qx, mt.aqyz);
+        const float ww = fmaf(t1, fmaf(t1, mt.vv, 2.0f * mt.qv), mt.qq);
+        n = fmaf(-2.0f, fmaf(t1, av, aq), ww);
+        wv = fmaf(t1, mt.vv, mt.qv);
+      } else {
+        wv = t1 * mt.vv;
+        n = t1 * fmaf(-2.0f, av, wv);
+      }
       const float rr = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(fmaf(am, am, n)) + am);
       const float F = fmaf(n, rr, -mt.dc);
-      const float eps = (av - tvv) * (2.0f * mt.ic * rr);
+      const float eps = (av - wv) * (2.0f * mt.ic * rr);
       D += fmaf(-F, eps, F);
     } else if (DEG > 0) {
       float h = DEG == 5 ? fmaf(rec.q1.z, num, rec.q2.w) : rec.q2.w;
@@ -361,7 +441,8 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
     const float fc_c = (float)(sw.fc / c);
     const float ic = (float)(1.0 / c);
     const PingRange pr = prange[t];
-    constexpr bool MOT = INTERP == 2;   // linear interpolation, receivers moving during reception
+    constexpr bool MOT = INTERP >= 2;   // linear interpolation, receivers moving during reception
+    constexpr bool TRK = INTERP == 3;   // ... along a position table
     const LdsLayout Ld = lds_layout(RC, chunk_pings(RC, E), W, ROWS, GATE, MOT);
     const TxRec* ltx = reinterpret_cast<const TxRec*>(lds + Ld.off_tx);
     const RxRec* lrx = reinterpret_cast<const RxRec*>(lds + Ld.off_rx);
@@ -397,6 +478,8 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
       int dT_slot = -1;
       float d0T = 0.0f;
       float4 vel = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      float4 line_q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      float line_qv = 0.0f;
       for (int q0 = 0; q0 < sc * E; q0 += RC) {
         const int nr = min(RC, sc * E - q0);
         const int sa = q0 / E, sb = (q0 + nr - 1) / E;
@@ -416,7 +499,12 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
             dT_slot = slot;
             if (MOT) {
               d0T = tr.d0;
-              vel = reinterpret_cast<const float4*>(lds + Ld.off_vel)[slot - sa];
+              const float4* lline = reinterpret_cast<const float4*>(lds + Ld.off_vel) + 3 * (slot - sa);
+              vel = lline[0];
+              if (TRK) {
+                line_q = lline[1];
+                line_qv = lline[2].x;
+              }
             }
           }
           const int r_lo = max(slot * E, q0) - q0, r_hi = min(slot * E + E, q0 + nr) - q0;
@@ -449,6 +537,12 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
               mt.avyz = fmaf(fmaf(0.5f, rec.q0.y, dyl), vel.y, fmaf(0.5f, rec.q0.z, dzl) * vel.z);
               mt.vx = vel.x;
               mt.vv = vel.w;
+              if (TRK) {
+                mt.qx = line_q.x;
+                mt.aqyz = fmaf(fmaf(0.5f, rec.q0.y, dyl), line_q.y, fmaf(0.5f, rec.q0.z, dzl) * line_q.z);
+                mt.qq = line_q.w;
+                mt.qv = line_qv;
+              }
               mt.ic = ic;
               mt.dc = reinterpret_cast<const float*>(lds + Ld.off_dc)[r];
               mt.tc = (d0T + rec.q1.w + mt.dc) * ic;
@@ -460,11 +554,11 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
                 span = row_hi(v) - row_lo(v);
               }
               if (f & kFlagPoly) {
-                if (test) accumulate<K, LX, 5, true, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, da, span, accr, acci, mt);
-                else accumulate<K, LX, 5, false, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci, mt);
+                if (test) accumulate<K, LX, 5, true, true, TRK>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, da, span, accr, acci, mt);
+                else accumulate<K, LX, 5, false, true, TRK>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci, mt);
               } else {
-                if (test) accumulate<K, LX, 0, true, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, da, span, accr, acci, mt);
-                else accumulate<K, LX, 0, false, true>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci, mt);
+                if (test) accumulate<K, LX, 0, true, true, TRK>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, da, span, accr, acci, mt);
+                else accumulate<K, LX, 0, false, true, TRK>(rec, win, dx, dsq, dT, dyl, dzl, fs_c, fc_c, szero, 0, 0, accr, acci, mt);
               }
               continue;
             }
@@ -541,11 +635,13 @@ static ImageKernelFn image_for_interp(int layout, bool gate, int dt) {
   }
 }
 
-// interp: 0 linear, 1 windowed sinc, 2 linear with the receivers moving during reception
+// interp: 0 linear, 1 windowed sinc, 2 linear with the receivers moving during
+// reception at a velocity, 3 ... along a position table
 ImageKernelFn image_kernel_for(int layout, bool gate, int dt, int interp) {
   switch (interp) {
     case 1: return image_for_interp<1>(layout, gate, dt);
     case 2: return image_for_interp<2>(layout, gate, dt);
+    case 3: return image_for_interp<3>(layout, gate, dt);
     default: return image_for_interp<0>(layout, gate, dt);
   }
 }
@@ -562,6 +658,11 @@ hipError_t launch_init(const Workspace& ws, hipStream_t st) {
 hipError_t launch_cull(const Workspace& ws, int n_tiles, int TX, int TY, int TZ, int bucket_shift,
                        hipStream_t st) {
   hipLaunchKernelGGL(cull_kernel, dim3(n_tiles), dim3(kThreads), 0, st, ws, TX, TY, TZ, bucket_shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_track_stats(const Workspace& ws, int swath, int n_ping, hipStream_t st) {
+  hipLaunchKernelGGL(track_stats_kernel, dim3(n_ping), dim3(kThreads), 0, st, ws, swath);
   return hipGetLastError();
 }
 

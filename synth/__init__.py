@@ -8,10 +8,10 @@ baseband. It never backprojects: interpolation of echoes, carrier-phase
 re-application and accumulation over pixels live only in the oracle and in the
 HIP kernels, which share no code.
 """
-from .scenario import Scenario, Grid, make_config, CONFIG_IDS, subset_indices, receiver_velocity, dpc_track
+from .scenario import Scenario, Grid, make_config, CONFIG_IDS, subset_indices, receiver_velocity, receiver_track, dpc_track
 from .echo import synthesize_echo, add_noise, quantize_echo, dequantize_echo
 
 __all__ = [
-    "Scenario", "Grid", "make_config", "CONFIG_IDS", "subset_indices", "receiver_velocity", "dpc_track",
+    "Scenario", "Grid", "make_config", "CONFIG_IDS", "subset_indices", "receiver_velocity", "receiver_track", "dpc_track",
     "synthesize_echo", "add_noise", "quantize_echo", "dequantize_echo",
 ]

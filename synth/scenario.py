@@ -405,6 +405,28 @@ def receiver_velocity(scn: Scenario, pri: float | None = None) -> np.ndarray:
     return np.gradient(t, axis=0) / pri
 
 
+def receiver_track(scn: Scenario, n_samp: int | None = None, h: float = 2e-3, seed: int = 5):
+    """An up-sampled position table per ping for continuous-motion tests:
+    the receivers' displacement from their ping-time positions at t = j h
+    after transmit (j = 0..n_samp - 1): a 1.5 m/s surge plus sinusoidal sway
+    and heave of a few millimetres at 5 to 15 rad/s with seeded phases
+    (accelerations up to about 0.9 m/s^2), zero at transmit. n_samp defaults
+    to a table that covers the record plus 10 ms. Returns (table [P, n, 3], h)."""
+    if n_samp is None:
+        n_samp = int(math.ceil((scn.t0 + scn.n_sample / scn.fs + 0.01) / h)) + 1
+    rng = np.random.default_rng(seed)
+    t = np.arange(n_samp) * h
+    P = scn.n_ping
+    tab = np.zeros((P, n_samp, 3))
+    amp = np.array([0.003, 0.004, 0.002])
+    for i in range(P):
+        w = rng.uniform(5.0, 15.0, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        tab[i] = amp * (np.sin(w * t[:, None] + ph) - np.sin(ph))
+        tab[i, :, 0] += 1.5 * t
+    return tab, h
+
+
 def subset_indices(scn: Scenario, count: int) -> np.ndarray:
     """Seeded pixel subset (flat image indices, sorted) drawn without replacement."""
     rng = scn.streams()["subset"]

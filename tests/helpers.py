@@ -28,15 +28,15 @@ def workers() -> int:
 
 
 def desc_for(api, scn: Scenario, echo_dtype: str = "c64", c_min: float = 0.0, interp: str = "linear",
-             motion: bool = False, refraction=None):
+             motion=False, refraction=None, track=None):
     g = scn.grid
     return api.swath_desc(scn.n_ping, scn.n_elem, scn.n_sample, g.n, g.origin, g.spacing,
                           scn.fc, scn.fs, scn.t0, scn.gate_half_angle, echo_dtype, c_min, interp, motion,
-                          refraction)
+                          refraction, track)
 
 
 def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scale=None,
-                tx=None, rx=None, c=None, rx_vel=None):
+                tx=None, rx=None, c=None, rx_vel=None, rx_track=None):
     g = scn.grid
     dev = torch.device(device)
     tx = scn.tx if tx is None else tx
@@ -50,14 +50,19 @@ def buffers_for(api, scn: Scenario, echo: torch.Tensor, device="cuda", echo_scal
         echo_scale=None if echo_scale is None else echo_scale.to(dev).contiguous(),
         rx_vel=None if rx_vel is None else torch.as_tensor(np.ascontiguousarray(rx_vel), dtype=torch.float64,
                                                            device=dev),
+        rx_track=None if rx_track is None else torch.as_tensor(np.ascontiguousarray(rx_track), dtype=torch.float64,
+                                                               device=dev),
     )
 
 
 def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_scale=None, interp="linear",
-              rx_vel=None, refraction=None, **plan_kw):
-    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype, interp=interp, motion=rx_vel is not None,
-                                     refraction=refraction)], **plan_kw)
-    buf = buffers_for(api, scn, echo, echo_scale=echo_scale, rx_vel=rx_vel)
+              rx_vel=None, refraction=None, rx_track=None, **plan_kw):
+    motion = "table" if rx_track is not None else rx_vel is not None
+    track = None if rx_track is None else (rx_track[0].shape[1], rx_track[1])
+    plan = api.sas_bp_plan([desc_for(api, scn, echo_dtype, interp=interp, motion=motion, refraction=refraction,
+                                     track=track)], **plan_kw)
+    buf = buffers_for(api, scn, echo, echo_scale=echo_scale, rx_vel=rx_vel,
+                      rx_track=None if rx_track is None else rx_track[0])
     api.sas_bp_image(plan, [buf])
     torch.cuda.synchronize()
     assert plan.status() == 0
@@ -65,12 +70,13 @@ def gpu_image(api, scn: Scenario, echo: torch.Tensor, echo_dtype="c64", echo_sca
 
 
 def oracle_image(scn: Scenario, echo_np: np.ndarray, index=None, interp="linear", rx_vel=None, refraction=None,
-                 chunk=4096):
+                 chunk=4096, rx_track=None):
     g = scn.grid
     pts = oracle.pixel_points(g.origin, g.spacing, g.n, index)
     return oracle.backproject(echo_np, scn.tx, scn.rx, scn.c, scn.fc, scn.fs, scn.t0, pts,
                               scn.gate_half_angle, workers=workers(), chunk=chunk,
-                              interp="sinc" if interp == "sinc8" else interp, rx_vel=rx_vel, refraction=refraction)
+                              interp="sinc" if interp == "sinc8" else interp, rx_vel=rx_vel, refraction=refraction,
+                              rx_track=rx_track)
 
 
 def volume_subset(scn: Scenario, count: int, seabed_z: float) -> np.ndarray:

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_error_strings():
     from paper_2101_05888_amd import _native as N
-    assert N.lib().sas_bp_abi_version() == 5
+    assert N.lib().sas_bp_abi_version() == 6
     for s in range(7):
         assert N.lib().sas_bp_error_string(s) != b"unknown status"
     assert N.lib().sas_bp_error_string(99) == b"unknown status"

@@ -100,3 +100,96 @@ def test_full_size_operational_swath_motion_sampled(api):
     ref = oracle_image(scn, echo_np, idx, rx_vel=vel)
     r, ph = report("motion c2-full-subset", img, ref)
     assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+
+
+# ------------------------------------------------------------ position table
+#
+# The receivers displaced along an up-sampled position table (samples every
+# 2 ms, linear between them; sinusoidal sway and heave accelerations up to
+# about 0.9 m/s^2 on a 1.5 m/s surge, zero at transmit), the echoes
+# synthesized with the same table (fixed-point delays), the image against the
+# oracle's bisection root. Same FP32 bounds. The kernel follows each ping's
+# table on the straight line of the segment that holds the tile centre's
+# delay, and certifies the departure below 2e-6 m (about 1 mrad of phase).
+
+from tests.test_oracle_motion import curved_track
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_table_motion_image_matches_oracle(api, case):
+    name, kw = CASES[case]
+    print(f"case table motion {case}", flush=True)
+    scn = make_config(name, **kw)
+    tab, h = curved_track(scn)
+    echo = synthesize_echo(scn, dtype=torch.complex64, rx_track=(tab, h))
+    img, plan, _ = gpu_image(api, scn, echo, rx_track=(tab, h))
+    ref = oracle_image(scn, echo.numpy(), rx_track=(tab, h), chunk=512).reshape(img.shape)
+    r, ph = report(f"table motion {case}", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+    static = oracle_image(scn, echo.numpy()).reshape(img.shape)
+    assert oracle.rel_l2(static, ref) > 0.1
+
+
+def test_straight_table_equals_velocity_mode(api):
+    # a table that samples R + v t exactly is the constant-velocity model
+    scn = make_config("c2", n_ping=24, n_elem=8, nx=150, ny=70, n_sample=4096, n_scat=30, n_speckle=100)
+    vel = receiver_velocity(scn)
+    h = 1e-3
+    n = 60
+    tab = np.arange(n)[None, :, None] * h * vel[:, None, :]
+    echo = synthesize_echo(scn, dtype=torch.complex64, rx_vel=vel)
+    img_v, _, _ = gpu_image(api, scn, echo, rx_vel=vel)
+    img_t, _, _ = gpu_image(api, scn, echo, rx_track=(tab, h))
+    r, ph = report("straight table vs velocity", img_t, img_v)
+    assert r <= 1e-5
+
+
+def test_table_with_velocity_jumps_is_refused(api):
+    # velocity changes of 0.5 m/s between 1 ms segments depart from any one
+    # segment's line by far more than the certified 2e-6 m inside a tile
+    scn = make_config("c1", n_ping=6, n_elem=4, nx=64, ny=32)
+    h = 1e-3
+    n = 60
+    rng = np.random.default_rng(1)
+    vel = np.cumsum(rng.choice([-0.5, 0.5], size=(scn.n_ping, n, 3)), axis=1)
+    tab = np.concatenate([np.zeros((scn.n_ping, 1, 3)), np.cumsum(vel[:, :-1] * h, axis=1)], axis=1)
+    echo = synthesize_echo(scn, dtype=torch.complex64)
+    plan = api.sas_bp_plan([desc_for(api, scn, motion="table", track=(n, h))])
+    buf = buffers_for(api, scn, echo, rx_track=tab)
+    api.sas_bp_image(plan, [buf])
+    torch.cuda.synchronize()
+    assert plan.status() == 5
+    # a table that is not finite is refused the same way
+    bad = tab.copy()
+    bad[2, 5, 1] = np.nan
+    plan2 = api.sas_bp_plan([desc_for(api, scn, motion="table", track=(n, h))])
+    buf2 = buffers_for(api, scn, echo, rx_track=bad)
+    api.sas_bp_image(plan2, [buf2])
+    torch.cuda.synchronize()
+    assert plan2.status() == 5
+    with pytest.raises(RuntimeError):   # a table of one sample
+        api.sas_bp_plan([desc_for(api, scn, motion="table", track=(1, h))])
+    with pytest.raises(ValueError):     # a table of the wrong shape
+        api.sas_bp_image(plan, [buffers_for(api, scn, echo, rx_track=tab[:, :-1])])
+
+
+def test_full_size_operational_swath_table_sampled(api):
+    """The operational swath in the benchmark's launch configuration with the
+    receivers on a position table (2 ms samples over the 205 ms record), on a
+    seeded pixel subset."""
+    print("case table motion c2 full size", flush=True)
+    scn = make_config("c2")
+    tab, h = curved_track(scn, n_samp=110)
+    echo = synthesize_echo(scn, device="cuda", dtype=torch.complex64, rx_track=(tab, h))
+    plan = api.sas_bp_plan([desc_for(api, scn, motion="table", track=(tab.shape[1], h))])
+    buf = buffers_for(api, scn, echo, rx_track=tab)
+    api.sas_bp_image(plan, [buf])
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    idx = subset_indices(scn, 512)
+    img = buf.image.reshape(-1)[torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    echo_np = echo.cpu().numpy()
+    del echo, buf
+    ref = oracle_image(scn, echo_np, idx, rx_track=(tab, h), chunk=32)
+    r, ph = report("table motion c2-full-subset", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD

@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import make_config, synthesize_echo, receiver_velocity
+from synth import make_config, synthesize_echo, receiver_velocity, receiver_track
 from synth.echo import pulse
 
 
@@ -133,19 +133,7 @@ def test_p12_pins_reject_mutation(name):
 #   exact at the samples and linear between and past them.
 
 def curved_track(scn, n_samp=40, h=2e-3, seed=5):
-    """A table per ping: surge 1.5 m/s plus sinusoidal sway and heave
-    accelerations (up to about 0.5 m/s^2), displacement zero at transmit."""
-    rng = np.random.default_rng(seed)
-    t = np.arange(n_samp) * h
-    P = scn.n_ping
-    tab = np.zeros((P, n_samp, 3))
-    for i in range(P):
-        w = rng.uniform(5.0, 15.0, 3)
-        ph = rng.uniform(0, 2 * np.pi, 3)
-        amp = np.array([0.003, 0.004, 0.002])
-        tab[i] = amp * (np.sin(w * t[:, None] + ph) - np.sin(ph))
-        tab[i, :, 0] += 1.5 * t
-    return tab, h
+    return receiver_track(scn, n_samp, h, seed)
 
 
 def test_p12d_straight_table_equals_constant_velocity_root():
