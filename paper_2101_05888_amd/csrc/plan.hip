@@ -390,7 +390,7 @@ Layout make_layout(int n_swaths, int n_tiles, size_t n_partials, size_t geo_stri
   L.swaths = o;     o = align_up(o + sizeof(SwathDev) * n_swaths);
   L.prange = o;     o = align_up(o + sizeof(PingRange) * n_tiles);
   L.order = o;      o = align_up(o + sizeof(int) * n_tiles);
-  L.counters = o;   o = align_up(o + sizeof(unsigned) * 16);
+  L.counters = o;   o = align_up(o + sizeof(unsigned) * kCounterWords);
   L.bucket = o;     o = align_up(o + sizeof(unsigned) * kBuckets);
   L.tile_swath = o; o = align_up(o + sizeof(int) * n_tiles);
   L.scratch = o;    o = align_up(o + sizeof(double) * (kSharpScratch + 16));
@@ -1343,9 +1343,9 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
   std::vector<int> tile_swath(n_tiles);
   for (int i = 0; i < n_swaths; ++i)
     for (int k = 0; k < sw[i].ntiles; ++k) tile_swath[sw[i].tile0 + k] = i;
-  std::vector<unsigned> zeros(16, 0u);
+  std::vector<unsigned> zeros(kCounterWords, 0u);
   e = hipMemcpy(p->ws.tile_swath, tile_swath.data(), sizeof(int) * n_tiles, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->ws.counters, zeros.data(), sizeof(unsigned) * 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->ws.counters, zeros.data(), sizeof(unsigned) * kCounterWords, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&p->host_sw), sizeof(SwathDev) * n_swaths, hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);

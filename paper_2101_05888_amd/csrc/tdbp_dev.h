@@ -139,6 +139,30 @@ __host__ __device__ inline int chunk_pings(int RC, int E) {
 }
 
 constexpr int kBuckets = 64;
+
+// The MI355X has 8 accelerator complex dies (XCDs), each with its own L2;
+// the dispatcher hands workgroups to them round-robin by workgroup index.
+// The image kernel keeps one tile queue per XCD (tiles of neighbouring
+// along-track stripes read the same echo windows, so a stripe per XCD keeps
+// them in one L2) and takes from the other queues once its own is empty.
+// Layout of ws.counters: [0] work counter of the single-queue kernels,
+// [1] status word, [kQueueCursor + x] next item of XCD x's queue,
+// [kQueueStart + x] its first slot in ws.order, [kQueueLen + x] its length.
+constexpr int kXcds = 8;
+constexpr int kQueueCursor = 4, kQueueStart = 12, kQueueLen = 20, kCounterWords = 32;
+
+// Next tile for a workgroup on XCD xcd: its own queue, then the others in
+// turn; -1 once every queue is empty.
+__device__ __forceinline__ int next_tile(const Workspace& ws, int xcd) {
+  for (int k = 0; k < kXcds; ++k) {
+    const int q = (xcd + k) % kXcds;
+    const unsigned len = ws.counters[kQueueLen + q];
+    const unsigned i = atomicAdd(&ws.counters[kQueueCursor + q], 1u);
+    if (i < len) return (int)(ws.counters[kQueueStart + q] + i);
+  }
+  return -1;
+}
+
 // Sharpness: one partial (sum |I|^4, sum |I|^2) pair per block of a fixed grid,
 // then the two sums; scratch of 2 kSharpBlocks + 2 doubles.
 constexpr int kSharpBlocks = 1024;

@@ -119,10 +119,10 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
   __shared__ int s_item;
   for (;;) {
     __syncthreads();
-    if (tid == 0) s_item = (int)atomicAdd(&ws.counters[0], 1u);
+    if (tid == 0) s_item = next_tile(ws, blockIdx.x % kXcds);
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(s_item);
-    if (item >= n_tiles) break;
+    if (item < 0) break;
     const int t = __builtin_amdgcn_readfirstlane(order[item]);
     const int s = __builtin_amdgcn_readfirstlane(tile_swath[t]);
     const SwathDev& sw = swaths[s];

@@ -122,10 +122,10 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void reproject_ke
 
   for (;;) {
     __syncthreads();
-    if (tid == 0) s_item = (int)atomicAdd(&ws.counters[0], 1u);
+    if (tid == 0) s_item = next_tile(ws, blockIdx.x % kXcds);
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(s_item);
-    if (item >= n_tiles) break;
+    if (item < 0) break;
     const int t = __builtin_amdgcn_readfirstlane(order[item]);
     const int s = __builtin_amdgcn_readfirstlane(tile_swath[t]);
     const SwathDev& sw = swaths[s];
