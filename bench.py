@@ -368,7 +368,8 @@ def tvg_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
 def whiten_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
     """Spectral whitening (Eq. 9) of the operational echo cube on a copy:
     forward FFT, power estimate, gain, inverse FFT (16384 rows of 16384
-    points)."""
+    points; the hand-written two-pass form). Algorithmic bytes: the cube read
+    and written twice (spectra in place between the passes)."""
     x = echo.clone()
     api.sas_bp_whiten(plan, 0, x, 0.1)   # warm-up (also makes the FFT plan)
     torch.cuda.synchronize()
@@ -380,9 +381,11 @@ def whiten_leg(api, plan, echo: torch.Tensor, steps: int) -> dict:
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
-    log(f"whiten: {ms:.3f} ms for {x.numel()} samples")
+    moved = 4 * echo.numel() * 8
+    log(f"whiten: {ms:.3f} ms for {x.numel()} samples, {moved / (ms * 1e-3) / 1e9:.0f} GB/s")
     del x
-    return {"samples": int(echo.numel()), "ms": ms}
+    return {"samples": int(echo.numel()), "ms": ms, "algorithmic_bytes": moved,
+            "gb_per_s": moved / (ms * 1e-3) / 1e9, "hbm_peak_frac": moved / (ms * 1e-3) / 8e12}
 
 
 def rangec_leg(api, plan, echo: torch.Tensor, fs: float, steps: int) -> dict:

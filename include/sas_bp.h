@@ -420,10 +420,12 @@ int sas_bp_dpc_solve(const sas_bp_dpc_desc* desc, const double* vx, const double
  * G(f) = h(1 / (gamma mean_f P^ + P^(f))), h the normalisation to max G = 1
  * (0 dB smallest attenuation); every row's spectrum is multiplied by
  * sqrt(G(f)) and transformed back. echo is complex64 [P][E][N_s] with the
- * swath's sizes. gamma >= 0. Transforms are rocFFT's (through hipFFT); the
- * power sums are FP64 in a fixed order. The plan makes the swath's FFT plan
- * and a workspace of 8 (65 N_s) + 4 N_s bytes on the first call.
- * Asynchronous on `stream`. */
+ * swath's sizes. gamma >= 0. Rows of 4096, 8192 or 16384 samples use the
+ * library's own transforms (FP32, in LDS; per-bin power summed in FP32 over
+ * each workgroup's run of rows, then in FP64 over the runs in a fixed order);
+ * other lengths use rocFFT through hipFFT (FP64 power sums in a fixed order),
+ * whose FFT plan the plan makes on the first call. The plan allocates a
+ * workspace of at most 34 MB on the first call. Asynchronous on `stream`. */
 int sas_bp_whiten(sas_bp_plan_t plan, int swath, void* echo, double gamma, void* stream);
 
 /* Time-varying gain of swath `swath`'s echo cube, in place (Eq. 10, Sec.

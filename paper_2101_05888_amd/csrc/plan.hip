@@ -64,6 +64,7 @@ hipError_t launch_tvg(void* echo, long long rows, int Ns, double alpha, float* w
                       hipStream_t st);
 size_t whiten_work_bytes(int Ns);
 int launch_whiten(void* fft_plan, void* echo, long long rows, int Ns, double gamma, void* work, hipStream_t st);
+bool whiten_hand_written(int Ns);
 int make_fft_plan(int Ns, long long rows, void** out);
 void destroy_fft_plan(void* p);
 int rc_transform_length(long long n);
@@ -1555,7 +1556,8 @@ int sas_bp_whiten(sas_bp_plan_t p, int swath, void* echo, double gamma, void* st
     }
   }
   if (p->fft_plans.empty()) p->fft_plans.assign(p->n_swaths, nullptr);
-  if (!p->fft_plans[swath] && make_fft_plan(d.n_sample, rows, &p->fft_plans[swath]) != 0) {
+  if (!whiten_hand_written(d.n_sample) && !p->fft_plans[swath] &&
+      make_fft_plan(d.n_sample, rows, &p->fft_plans[swath]) != 0) {
     p->fft_plans[swath] = nullptr;
     return fail(SAS_BP_EDEVICE, "FFT plan for %d x %lld samples could not be made", d.n_sample, rows);
   }

@@ -27,14 +27,23 @@ def _coloured(P, E, Ns, seed=2):
     return np.fft.ifft(np.fft.fft(w, axis=-1) * shape, axis=-1).astype(np.complex64)
 
 
-@pytest.mark.parametrize("case,gamma", [("c1", 0.0), ("c1", 0.5), ("coloured-1000", 0.0), ("coloured-1000", 2.0)])
+# 4096, 8192 and 16384 samples take the hand-written transforms (radix 1, 2
+# and 4 before the 4096-point passes; 600 rows: several rows per workgroup);
+# 1000 samples the library's
+CUBES = {"coloured-1000": (10, 3, 1000), "coloured-8192": (4, 3, 8192), "coloured-16384": (20, 30, 16384)}
+
+
+@pytest.mark.parametrize("case,gamma", [("c1", 0.0), ("c1", 0.5), ("coloured-1000", 0.0), ("coloured-1000", 2.0),
+                                        ("coloured-8192", 0.0), ("coloured-8192", 0.7),
+                                        ("coloured-16384", 0.0), ("coloured-16384", 1.5)])
 def test_whiten_matches_oracle(api, case, gamma):
     if case == "c1":
         scn = make_config("c1", n_ping=16, n_elem=4)
         e = synthesize_echo(scn, dtype=torch.complex64).numpy()
     else:
-        scn = make_config("c1", n_ping=10, n_elem=3, n_sample=1000)
-        e = _coloured(10, 3, 1000)
+        P, E, Ns = CUBES[case]
+        scn = make_config("c1", n_ping=P, n_elem=E, n_sample=Ns, nx=16, ny=16)
+        e = _coloured(P, E, Ns)
     plan = api.sas_bp_plan([desc_for(api, scn)])
     x = torch.as_tensor(e, device="cuda").contiguous()
     api.sas_bp_whiten(plan, 0, x, gamma)
