@@ -160,16 +160,30 @@ __global__ __launch_bounds__(kFftThreads) void rc_fused_kernel(float2* x, long l
   const int t = threadIdx.x;
   for (int i = t; i < kFftTw; i += kFftThreads) T[i] = tw[i];
   __syncthreads();
+  // the next segment's samples and mix factors, loaded while the current one
+  // is transformed (a segment reads [s U, s U + 4096) and writes [s U, s U +
+  // U): no later segment reads what an earlier one wrote)
+  float2 nx[16], nm[16];
+  auto load_seg = [&](long long row, int s) {
+    const float2* xr = x + (size_t)row * Ns;
+    const int i0 = s * U;
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) {
+      const int i = i0 + n1 * kFftThreads + t;
+      nx[n1] = i < Ns ? xr[i] : make_float2(0.0f, 0.0f);
+      nm[n1] = i < Ns ? mix[i] : make_float2(0.0f, 0.0f);
+    }
+  };
+  if (blockIdx.x < rows) load_seg(blockIdx.x, 0);
   for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
     float2* xr = x + (size_t)row * Ns;
     for (int s = 0; s < nseg; ++s) {
       const int i0 = s * U;
       float2 v[16];
 #pragma unroll
-      for (int n1 = 0; n1 < 16; ++n1) {
-        const int i = i0 + n1 * kFftThreads + t;
-        v[n1] = i < Ns ? fft_cmul(xr[i], mix[i]) : make_float2(0.0f, 0.0f);
-      }
+      for (int n1 = 0; n1 < 16; ++n1) v[n1] = fft_cmul(nx[n1], nm[n1]);
+      if (s + 1 < nseg) load_seg(row, s + 1);
+      else if (row + gridDim.x < rows) load_seg(row + gridDim.x, 0);
       fft_pass1_compute<false>(v, t, T);
       __syncthreads();   // the previous segment's last LDS reads are done
       fft_pass1_store(v, t, A);
