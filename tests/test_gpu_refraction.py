@@ -36,13 +36,17 @@ def _scene(**kw):
     return make_config("c3", **base)
 
 
-def test_refraction_image_matches_oracle(api):
-    print("case refraction c3 small", flush=True)
+@pytest.mark.parametrize("c_sed", [1650.0, 1450.0])
+def test_refraction_image_matches_oracle(api, c_sed):
+    # sand (faster than water: a critical crossing bounds the bracket) and
+    # mud (slower: no critical crossing)
+    print(f"case refraction c3 small c_sed {c_sed}", flush=True)
+    refr = (c_sed, REFR[1])
     scn = _scene()
-    echo = synthesize_echo(scn, dtype=torch.complex64, refraction=REFR)
-    img, plan, _ = gpu_image(api, scn, echo, refraction=REFR)
-    ref = oracle_image(scn, echo.numpy(), refraction=REFR).reshape(img.shape)
-    r, ph = report("refraction c3 small", img, ref)
+    echo = synthesize_echo(scn, dtype=torch.complex64, refraction=refr)
+    img, plan, _ = gpu_image(api, scn, echo, refraction=refr)
+    ref = oracle_image(scn, echo.numpy(), refraction=refr).reshape(img.shape)
+    r, ph = report(f"refraction c3 small c_sed {c_sed}", img, ref)
     assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
     # the case exercises the interface: straight-path imaging of this echo is far off
     straight = oracle_image(scn, echo.numpy()).reshape(img.shape)
