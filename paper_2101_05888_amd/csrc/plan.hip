@@ -1318,7 +1318,10 @@ int sas_bp_plan(const sas_bp_swath_desc* desc, int n_swaths, const sas_bp_option
     return fail(SAS_BP_EUNSUPPORTED, "tiling needs %d bytes of LDS; no workgroup fits", max_lds);
   }
   p->occ = occ;
-  p->grid = std::max(1, std::min(std::min(n_tiles, occ * prop.multiProcessorCount), lay.geo_slots));
+  // the refraction kernel keeps its references in static LDS, not in the
+  // geometry scratch: its resident workgroups are set by its occupancy alone
+  p->grid = std::max(1, std::min(std::min(n_tiles, occ * prop.multiProcessorCount),
+                                 p->refract ? n_tiles : lay.geo_slots));
   p->adj_grid = std::max(1, std::min(std::min(n_tiles, adj_occ * prop.multiProcessorCount), lay.geo_slots));
   p->rep_grid = std::max(1, std::min(std::min(n_tiles, rep_occ * prop.multiProcessorCount), lay.geo_slots));
 

@@ -79,11 +79,15 @@ __device__ __forceinline__ double rsq_fp64(double A) {
 
 // FP64 crossing at horizontal distance D: Newton steps kept inside the bracket
 // [0, min(D, h1 rc_ratio)] (a step that leaves it is replaced by bisection)
-// until a step is below FP64 resolution. The step divides by f' in FP32 (a
-// relative error of the step near 1e-7 still gains seven digits a step).
-__device__ double crossing_fp64(double D, double h1, double h2, double inv_c, double inv_cs, double rc_ratio) {
+// until a step is below FP64 resolution, from r = q D (q a nearby leg's
+// crossing ratio; the straight-line crossing when q is outside [0, 1]). The
+// step divides by f' in FP32 (a relative error of the step near 1e-7 still
+// gains seven digits a step).
+__device__ double crossing_fp64(double D, double h1, double h2, double inv_c, double inv_cs, double rc_ratio,
+                                float q) {
   double lo = 0.0, hi = fmin(D, h1 * rc_ratio);
-  double r = fmin(D * h1 / (h1 + h2), hi);
+  const double q0 = (q >= 0.0f && q <= 1.0f) ? (double)q : h1 / (h1 + h2);
+  double r = fmin(D * q0, hi);
   const double tol = 1e-14 * (D + h1 + h2), h1s = h1 * h1, h2s = h2 * h2;
   for (int it = 0; it < 80; ++it) {
     const double u = D - r;
@@ -106,7 +110,7 @@ __device__ double crossing_fp64(double D, double h1, double h2, double inv_c, do
 // non-finite apex sets bad and leaves an inert straight reference.
 __device__ void refract_reference(RefractRef& R, double Xx, double Xy, double Xz, double xc, double yc, double pz,
                                   double rho, const SwathDev& sw, double inv_c, double inv_cs, double rc_ratio,
-                                  double tt, double t_shift, bool& bad) {
+                                  double tt, double t_shift, float q_start, bool& bad) {
   RefractRef q;
   q.rc = q.rd = q.rdd = q.h1s = q.h2s = q.ac = q.uc = q.bc = q.thr = q.hic = q.hsum = q.gz = 0.0f;
   if (!finite3(Xx, Xy, Xz)) {
@@ -130,7 +134,7 @@ __device__ void refract_reference(RefractRef& R, double Xx, double Xy, double Xz
     t = Rr * inv_c;
   } else {
     const double D = sqrt(dx * dx + dy * dy);
-    const float rcf = (float)crossing_fp64(D, h1, h2, inv_c, inv_cs, rc_ratio);
+    const float rcf = (float)crossing_fp64(D, h1, h2, inv_c, inv_cs, rc_ratio, q_start);
     const double r = rcf, u = D - r;
     const double a = sqrt(r * r + h1 * h1), b = sqrt(u * u + h2 * h2);
     t = a * inv_c + b * inv_cs;
@@ -234,7 +238,7 @@ __device__ __forceinline__ void leg_offsets(const RefractRef& R, const float (&o
   const float thr = R.thr;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    float r = fminf(fmaxf(fmaf(dD[k], fmaf(rdd, dD[k], rd), rc), 0.0f), D[k]);   // warm start
+    float r = __builtin_amdgcn_fmed3f(fmaf(dD[k], fmaf(rdd, dD[k], rd), rc), 0.0f, D[k]);   // warm start in [0, D]
     float u = D[k] - r;
     float A = fmaf(r, r, h1s), B = fmaf(u, u, h2s);
     float ia = __builtin_amdgcn_rsqf(A), ib = __builtin_amdgcn_rsqf(B);
@@ -322,8 +326,12 @@ __global__ __launch_bounds__(kLayouts[L].LX * kLayouts[L].LY * kLayouts[L].LZ) v
           if (leg == 0 && e0 != 0) continue;   // the transmit leg once per ping
           const double pz = sw.o[2] + (double)(tiz * TZ + lev) * sw.d[2];
           const double* X = leg == 0 ? sw.tx + (size_t)p * 3 : sw.rx + ((size_t)p * E + e0 + leg - 1) * 3;
+          // the slot's previous leg (the same element and level one ping
+          // back when a ping fits one chunk) starts the crossing
+          const RefractRef& prev = s_ref[j];
+          const float q0 = prev.straight == 0 && prev.dc > 0.0f ? prev.rc / prev.dc : -1.0f;
           refract_reference(s_ref[j], X[0], X[1], X[2], xc, yc, pz, rho, sw, inv_c, inv_cs, rc_ratio, ttd,
-                            leg == 0 ? sw.t0 : 0.0, bad);
+                            leg == 0 ? sw.t0 : 0.0, q0, bad);
         }
         if (bad) s_bad = 1;
         __syncthreads();
