@@ -210,10 +210,9 @@ __global__ __launch_bounds__(whiten_threads<R>()) void whiten_inverse_kernel(flo
   float2* L = reinterpret_cast<float2*>(smem);
   const int T = threadIdx.x, h = T >> 8, t = T & 255;
   const long long r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
-  // this thread's gained spectrum values of group g (bins g + R (t + 256 j));
-  // with one group per thread the next row's are loaded ahead, with two
-  // (R = 4) each group's just before its passes (loading ahead would spill)
-  constexpr bool PRE = G == 1;
+  // this thread's gained spectrum values of group g (bins g + R (t + 256 j)),
+  // one group ahead: while a group's passes run, the next group's loads (the
+  // same row's next group, else the next row's first) are in flight
   float2 s[16];
   auto load_group = [&](long long r, int g, float2* dst) {
     const float2* row = X + (size_t)r * N;
@@ -224,7 +223,7 @@ __global__ __launch_bounds__(whiten_threads<R>()) void whiten_inverse_kernel(flo
       dst[j] = make_float2(x.x * a, x.y * a);
     }
   };
-  if (PRE && r0 < r1) load_group(r0, h, s);
+  if (r0 < r1) load_group(r0, h, s);
   for (long long r = r0; r < r1; ++r) {
     float2* row = X + (size_t)r * N;
 #pragma unroll
@@ -232,13 +231,10 @@ __global__ __launch_bounds__(whiten_threads<R>()) void whiten_inverse_kernel(flo
       const int g = h + H * i;
       float2* A = L + g * kFftLds;
       float2 v[16];
-      if (PRE) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = s[j];
-        if (r + 1 < r1) load_group(r + 1, h, s);
-      } else {
-        load_group(r, g, v);
-      }
+      for (int j = 0; j < 16; ++j) v[j] = s[j];
+      if (i + 1 < G) load_group(r, g + H, s);
+      else if (r + 1 < r1) load_group(r + 1, h, s);
       fft_pass1_compute<true>(v, t, tw);
       __syncthreads();   // the previous group's or row's last LDS reads are done
       fft_pass1_store(v, t, A);
@@ -259,7 +255,7 @@ __global__ __launch_bounds__(whiten_threads<R>()) void whiten_inverse_kernel(flo
     if constexpr (R > 1) {
       __syncthreads();
       // the radix-R pass: x[n2 + 4096 n1] for this thread's n2 = T + NT m
-#pragma unroll
+#pragma unroll 2
       for (int m = 0; m < M; ++m) {
         const int n2 = T + NT * m;
         float2 u[R];
