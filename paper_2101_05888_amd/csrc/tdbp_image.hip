@@ -56,7 +56,6 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
   if (c_ok) {
     for (int p = threadIdx.x; p < sw.P; p += blockDim.x) {
       const double* T = sw.tx + (size_t)p * 3;
-      bool hit = true;
       // record test: the two-way delay of the tile lies within [dT0+dR0 - 2r, dT0+dR0 + 2r]
       const double u0 = C[0] - T[0], u1 = C[1] - T[1], u2 = C[2] - T[2];
       const double dT = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
@@ -71,9 +70,12 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
         const float4 st = sw.tstats[p];
         dmax = st.w == 0.0f ? (double)st.x * (1.0 + 1e-6) + 1e-5 : __builtin_nan("");
       }
+      // the ping is kept when its transmitter's cone may hit the tile and one
+      // element's cone and record both may (the elements are not tested
+      // once the transmitter misses, nor after the first that passes)
+      const bool tx_hit = !(sw.tan_g > 0.0 && !sw.no_cull) || cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, T);
       bool in_record = false;
-      bool rx_hit = false;
-      for (int e = 0; e < sw.E; ++e) {
+      for (int e = 0; tx_hit && !in_record && e < sw.E; ++e) {
         const double* R = sw.rx + ((size_t)p * sw.E + e) * 3;
         const double v0 = C[0] - R[0], v1 = C[1] - R[1], v2 = C[2] - R[2];
         const double dR = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
@@ -86,14 +88,12 @@ __global__ __launch_bounds__(kThreads) void cull_kernel(Workspace ws, int TX, in
         const bool rec_e = sw.refract || sw.no_cull ||
                            ((uhi >= -2.0 - reach) && (ulo <= (double)sw.Ns + 1.0 + reach));
         const bool gate_e = (sw.tan_g > 0.0 && !sw.no_cull) ? cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, R) : true;
-        in_record |= rec_e && gate_e;
-        rx_hit |= gate_e;
+        in_record = rec_e && gate_e;
       }
-      if (sw.tan_g > 0.0 && !sw.no_cull) hit = cone_may_hit(sw.tan_g, xa, xb, ya, yb, za, zb, T) && rx_hit;
       // non-finite navigation makes every comparison false; keep such pings so
       // that the image kernel can flag them
       const bool bad = !(isfinite(dT)) || !isfinite(vm) || !isfinite(dmax);
-      if ((hit && in_record) || bad) {
+      if ((tx_hit && in_record) || bad) {
         atomicMin(&s_lo, p);
         atomicMax(&s_hi, p);
       }
