@@ -520,6 +520,13 @@ __device__ __forceinline__ float2 load_guarded(const SwathDev& sw, size_t rowbas
   return load_sample(sw.echo, rowbase + (size_t)n, dt, scale);
 }
 
+// Ping slot x / E of chunk record x by a multiply with the FP32 reciprocal of
+// E instead of an integer division (a long dependent sequence on the staging
+// path): (x + 1/2) / E lies at least 1/(2E) from an integer, and the rounding
+// of 1/E and of the product moves it by less than (x + 1/2) 2^-23 / E, so the
+// truncation is exact for x < 2^21.
+__device__ __forceinline__ int slot_of(int x, float invE) { return (int)(((float)x + 0.5f) * invE); }
+
 // Echo windows of a chunk of nrows records into LDS; record r of the chunk is
 // echo row row0 + r of the swath (rows in (ping, element) order), element e0
 // + r of the chunk's first ping when r < E - e0, and its ping's transmitter
@@ -539,10 +546,14 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
   constexpr int NW = NT / 64;
   constexpr int SPL = 2;                    // samples per lane per load
   constexpr int JS = 64 * SPL;              // samples per part
-  constexpr int B = 8;                      // rows in flight per wave
+  // rows in flight per wave: three, so that a chunk of 24 records spreads over
+  // the four waves in two even passes (with eight, one wave of four sat idle
+  // and the staging spilled more registers)
+  constexpr int B = 3;
   constexpr int SB = DT == 0 ? 8 : 4;       // bytes per sample
   const int wave = __builtin_amdgcn_readfirstlane(wave_id);
   const int E = sw.E, W = sw.W, Ns = sw.Ns;
+  const float invE = 1.0f / (float)E;
   const int J = (W + JS) / JS;              // parts per window (samples 0..W)
   const bool aligned = (Ns % SPL) == 0;
   const char* echo = reinterpret_cast<const char*>(sw.echo);
@@ -554,17 +565,20 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
       LoadT q[B];
       float2 tail[B];                       // lane 63: the sample after the part
       int first[B];                         // sample index of the part's first lane (uniform)
+      float scl[B];                         // the row's ping scale (16-bit storage), read with the loads
       unsigned live = 0u, fast = 0u;        // per-row bits (uniform)
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         const int r = r0 + b;
         tail[b] = make_float2(0.0f, 0.0f);
         first[b] = 0;
+        scl[b] = 1.0f;
         if (r >= nrows) continue;
         const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(lrx[r].q0.w));
         if (f & kFlagSkip) continue;
         live |= 1u << b;
         first[b] = __builtin_amdgcn_readfirstlane(ln0[r]) + part * JS;
+        if (DT != 0) scl[b] = ltx[slot_of(e0 + r, invE)].scale;
         if (aligned && first[b] >= 0 && first[b] + JS < Ns) {
           fast |= 1u << b;
           const size_t row = (size_t)(row0 + r) * (size_t)Ns + (size_t)first[b];
@@ -577,7 +591,7 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
         if (!(live & (1u << b))) continue;
         const int r = r0 + b;
         const size_t rowbase = (size_t)(row0 + r) * (size_t)Ns;
-        const float scale = DT == 0 ? 1.0f : ltx[(e0 + r) / E].scale;
+        const float scale = scl[b];
         const int n = first[b] + lane_off;
         float2 s[SPL + 1];
         if (fast & (1u << b)) {
@@ -624,6 +638,7 @@ __device__ __forceinline__ void stage_windows_raw(float2* lwin, const RxRec* lrx
   constexpr int SB = DT == 0 ? 8 : 4;
   const int wave = __builtin_amdgcn_readfirstlane(wave_id);
   const int E = sw.E, Ns = sw.Ns;
+  const float invE = 1.0f / (float)E;
   const int WR = sw.W + 2 * kSincHalf;     // entries per raw window
   const int stride = 2 * (sw.W + 1);       // float2 entries per record slot
   const int J = (WR + JS - 1) / JS;
@@ -636,16 +651,19 @@ __device__ __forceinline__ void stage_windows_raw(float2* lwin, const RxRec* lrx
     for (int part = 0; part < J; ++part) {
       LoadT q[B];
       int first[B];
+      float scl[B];                         // the row's ping scale (16-bit storage), read with the loads
       unsigned live = 0u, fast = 0u;
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         const int r = r0 + b;
         first[b] = 0;
+        scl[b] = 1.0f;
         if (r >= nrows) continue;
         const unsigned f = __builtin_amdgcn_readfirstlane(__float_as_uint(lrx[r].q0.w));
         if (f & kFlagSkip) continue;
         live |= 1u << b;
         first[b] = __builtin_amdgcn_readfirstlane(ln0[r]) - kSincHalf + part * JS;
+        if (DT != 0) scl[b] = ltx[slot_of(e0 + r, invE)].scale;
         if (aligned && first[b] >= 0 && first[b] + JS <= Ns) {
           fast |= 1u << b;
           const size_t row = (size_t)(row0 + r) * (size_t)Ns + (size_t)first[b];
@@ -657,7 +675,7 @@ __device__ __forceinline__ void stage_windows_raw(float2* lwin, const RxRec* lrx
         if (!(live & (1u << b))) continue;
         const int r = r0 + b;
         const size_t rowbase = (size_t)(row0 + r) * (size_t)Ns;
-        const float scale = DT == 0 ? 1.0f : ltx[(e0 + r) / E].scale;
+        const float scale = scl[b];
         const int n = first[b] + lane_off;
         float2 sm[SPL];
         if (fast & (1u << b)) {
