@@ -563,14 +563,14 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
 #pragma unroll 1
     for (int part = 0; part < J; ++part) {
       LoadT q[B];
-      float2 tail[B];                       // lane 63: the sample after the part
+      float2 nxt[B];                        // the sample after the lane's pair (loaded, not shuffled)
       int first[B];                         // sample index of the part's first lane (uniform)
       float scl[B];                         // the row's ping scale (16-bit storage), read with the loads
       unsigned live = 0u, fast = 0u;        // per-row bits (uniform)
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         const int r = r0 + b;
-        tail[b] = make_float2(0.0f, 0.0f);
+        nxt[b] = make_float2(0.0f, 0.0f);
         first[b] = 0;
         scl[b] = 1.0f;
         if (r >= nrows) continue;
@@ -583,7 +583,7 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
           fast |= 1u << b;
           const size_t row = (size_t)(row0 + r) * (size_t)Ns + (size_t)first[b];
           q[b] = *reinterpret_cast<const LoadT*>(echo + (row + lane_off) * SB);
-          if (lane == 63) tail[b] = load_sample(sw.echo, row + JS, DT, 1.0f);
+          nxt[b] = load_sample(sw.echo, row + lane_off + SPL, DT, 1.0f);
         }
       }
 #pragma unroll
@@ -601,12 +601,8 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
 #pragma unroll
           for (int i = 0; i < SPL; ++i) s[i] = load_guarded(sw, rowbase, n + i, DT, scale);
         }
-        s[SPL].x = __shfl_down(s[0].x, 1, 64);
-        s[SPL].y = __shfl_down(s[0].y, 1, 64);
-        if (lane == 63) {
-          s[SPL] = (fast & (1u << b)) ? make_float2(tail[b].x * scale, tail[b].y * scale)
-                                      : load_guarded(sw, rowbase, n + SPL, DT, scale);
-        }
+        s[SPL] = (fast & (1u << b)) ? make_float2(nxt[b].x * scale, nxt[b].y * scale)
+                                    : load_guarded(sw, rowbase, n + SPL, DT, scale);
         float4* dst = lwin + (size_t)r * (W + 1) + part * JS;
 #pragma unroll
         for (int i = 0; i < SPL; ++i) {
