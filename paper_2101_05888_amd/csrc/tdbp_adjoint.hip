@@ -21,10 +21,23 @@
 
 namespace sasbp {
 
+// One DPP-moved operand per step (no LDS round trip, unlike a shuffle):
+// xor 1 and 2 within quads, the half-row and row mirrors give every lane its
+// 16-lane row sum, then row broadcasts of lanes 15 and 31 fold the rows into
+// lane 63, which is read out. A fixed order, so the sum is reproducible.
+// Needs every lane of the wave active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  v += dpp_move<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp_move<0x140, 0xf>(v);   // row_mirror
+  v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 // Extra LDS after the image layout: per (slot, element, wave) 6 floats of
@@ -141,22 +154,34 @@ __attribute__((amdgpu_waves_per_eu(kAdjointWaves, kAdjointWaves))) void adjoint_
             const float d0 = rec.q1.w;
             const float d0sq = d0 * d0;
             const float4* win = lwin + (size_t)r * (W + 1);
+            // delays first, then every window read in flight at once, then
+            // the per-pixel terms (as in the image kernel)
+            float dRk[K], Dk[K], sidx[K], cyc[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
               const float num = fmaf(rec.q0.x, dx[k], ryz + dsq[k]);
               const float sq = __builtin_amdgcn_sqrtf(d0sq + num);
-              const float dR = num * __builtin_amdgcn_rcpf(d0 + sq);
-              const float D = dT[k] + dR;
-              float sidx = fmaf(D, fs_c, rec.q1.x);
-              const float cyc = fmaf(D, fc_c, rec.q1.y);
+              dRk[k] = num * __builtin_amdgcn_rcpf(d0 + sq);
+              Dk[k] = dT[k] + dRk[k];
+              float si = fmaf(Dk[k], fs_c, rec.q1.x);
+              cyc[k] = fmaf(Dk[k], fc_c, rec.q1.y);
               if (test) {
                 const bool in = (unsigned)(da + LX * k) <= (unsigned)span;
-                sidx = in ? sidx : szero;
+                si = in ? si : szero;
               }
-              float wt;
-              const float4 v = window_read(window_base(win), sidx, &wt);
-              const float sn = __builtin_amdgcn_sinf(cyc);
-              const float cs = __builtin_amdgcn_cosf(cyc);
+              sidx[k] = si;
+            }
+            float4 vk[K];
+            float wk[K];
+            const unsigned wbase = window_base(win);
+#pragma unroll
+            for (int k = 0; k < K; ++k) vk[k] = window_read(wbase, sidx[k], &wk[k]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+              const float D = Dk[k], dR = dRk[k], wt = wk[k];
+              const float4 v = vk[k];
+              const float sn = __builtin_amdgcn_sinf(cyc[k]);
+              const float cs = __builtin_amdgcn_cosf(cyc[k]);
               const float dar = v.z, dai = v.w;
               const float Lr = fmaf(wt, dar, v.x), Li = fmaf(wt, dai, v.y);
               const float Xr = fmaf(fsf, dar, -tpf * Li);
