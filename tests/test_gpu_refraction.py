@@ -73,6 +73,38 @@ def test_voxels_just_below_the_interface_beyond_the_critical_distance(api, offse
     assert r3 <= FP32_REL_L2
 
 
+def test_more_receivers_than_one_reference_chunk(api):
+    # 80 receivers (2 x 40) and 3D tiles of four voxel levels: a ping's
+    # references span two chunks (the transmitter and 64 elements at four
+    # levels fill one), so the transmitter leg's offsets carry over into the
+    # second and each reference slot starts its crossing from another element
+    print("case refraction 80 receivers", flush=True)
+    scn = _scene(n_ping=8, n_across=40, nx=24, ny=16, nz=16)
+    echo = synthesize_echo(scn, dtype=torch.complex64, refraction=REFR)
+    img, plan, _ = gpu_image(api, scn, echo, refraction=REFR)
+    assert scn.n_elem == 80 and plan.info()["tile_z"] == 4
+    ref = oracle_image(scn, echo.numpy(), refraction=REFR).reshape(img.shape)
+    r, ph = report("refraction 80 receivers", img, ref)
+    assert r <= FP32_REL_L2 and ph <= FP32_PHASE_MRAD
+
+
+def test_nonfinite_receiver_sets_status_and_zero_image(api):
+    # a receiver position that is not finite: the plan reports bad navigation
+    # and every tile (each one's pings include it: no gate) comes out zero
+    print("case refraction non-finite receiver", flush=True)
+    scn = _scene(n_ping=6, nx=16, ny=8, nz=8)
+    echo = synthesize_echo(scn, dtype=torch.complex64, refraction=REFR)
+    rx = scn.rx.copy()
+    rx[2, 3, 0] = np.nan
+    plan = api.sas_bp_plan([desc_for(api, scn, refraction=REFR)])
+    buf = buffers_for(api, scn, echo, rx=rx)
+    buf.image.fill_(3.0)
+    api.sas_bp_image(plan, [buf])
+    torch.cuda.synchronize()
+    assert plan.status() == 5
+    assert np.count_nonzero(buf.image.cpu().numpy()) == 0
+
+
 def test_gated_2d_with_an_interface(api):
     # the stripmap geometry with a gate, pixels 0.2 m below an interface at z = -0.2
     print("case refraction gated 2D", flush=True)
