@@ -144,8 +144,12 @@ typedef struct {
                                a pixel below it crosses at the point of least travel time
                                (Snell's law), legs to pixels at or above it are straight;
                                the gate keeps straight lines. Linear interpolation, no
-                               motion, image only; the crossing is found in FP32, the
-                               leg times and the delay are FP64. */
+                               motion, image only; each leg's time is an FP32 offset
+                               from an FP64 reference leg to its tile's centre column
+                               (its crossing solved in FP64), the pixel's crossing
+                               taken from the reference's second-order expansion when
+                               a convexity bound certifies it, else from bracketed FP32
+                               Newton steps (SAS_BP_ECONVERGE if those do not stop). */
     int32_t track_n;        /* samples per ping of io.rx_track, 2..2^24 (motion = TABLE) */
     double c_sediment;      /* m/s, > 0 (refract = 1)                             */
     double z_interface;     /* m, the interface depth (refract = 1)               */
