@@ -534,8 +534,9 @@ __device__ __forceinline__ int slot_of(int x, float invE) { return (int)(((float
 // difference of E[n0+k] and E[n0+k+1] (k < W); entry W is zero.
 // Each wave takes B windows (rows r = (ping, element) of the chunk) at a
 // time and, per part of JS = 128 samples, issues the loads of all B rows
-// before consuming any: a lane loads two consecutive samples and takes the
-// sample after them from the next lane (lane 63 loads it itself). Row
+// before consuming any: a lane loads two consecutive samples and the sample
+// after them (loaded, not taken from the next lane: a cross-lane shuffle
+// would add an LDS round trip to the staging path). Row
 // bookkeeping is wave-uniform and stays in scalar registers. Samples outside
 // the record read as zero.
 template <int NT, int DT>
