@@ -539,7 +539,7 @@ __device__ __forceinline__ int slot_of(int x, float invE) { return (int)(((float
 // would add an LDS round trip to the staging path). Row
 // bookkeeping is wave-uniform and stays in scalar registers. Samples outside
 // the record read as zero.
-template <int NT, int DT>
+template <int NT, int DT, int SR = 3>
 __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, const int* ln0, const TxRec* ltx,
                                               const SwathDev& sw, long long row0, int e0, int nrows, int tid,
                                               int lane, int wave_id) {
@@ -547,10 +547,11 @@ __device__ __forceinline__ void stage_windows(float4* lwin, const RxRec* lrx, co
   constexpr int NW = NT / 64;
   constexpr int SPL = 2;                    // samples per lane per load
   constexpr int JS = 64 * SPL;              // samples per part
-  // rows in flight per wave: three, so that a chunk of 24 records spreads over
-  // the four waves in two even passes (with eight, one wave of four sat idle
-  // and the staging spilled more registers)
-  constexpr int B = 3;
+  // rows in flight per wave: SR, so that a chunk spreads over the four waves
+  // in even passes (24 records of the 2D tiles with three, 32 of the 3D
+  // tiles with four; with eight, one wave of four sat idle on 24 records and
+  // the staging spilled more registers)
+  constexpr int B = SR;
   constexpr int SB = DT == 0 ? 8 : 4;       // bytes per sample
   const int wave = __builtin_amdgcn_readfirstlane(wave_id);
   const int E = sw.E, W = sw.W, Ns = sw.Ns;
@@ -725,7 +726,7 @@ __device__ __forceinline__ void load_records(unsigned char* lds, const Geo& g, c
 // One chunk (as for load_records): the records into LDS, then the echo
 // windows (midpoint form, or raw samples for the windowed-sinc variant).
 // Ends with a barrier.
-template <int NT, int ROWS, bool GATE, int DT, bool RAW = false, bool MOTION = false>
+template <int NT, int ROWS, bool GATE, int DT, bool RAW = false, bool MOTION = false, int SR = 3>
 __device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, const SwathDev& sw, int P0, int q0,
                                            int nr, int s0, int ns, const LdsLayout& L, int tid, int lane,
                                            int wave) {
@@ -736,7 +737,7 @@ __device__ __forceinline__ void load_chunk(unsigned char* lds, const Geo& g, con
                               reinterpret_cast<const int*>(lds + L.off_n0), reinterpret_cast<const TxRec*>(lds + L.off_tx),
                               sw, (long long)P0 * sw.E + q0, q0 - s0 * sw.E, nr, lane, wave);
   else
-    stage_windows<NT, DT>(reinterpret_cast<float4*>(lds + L.off_win), reinterpret_cast<const RxRec*>(lds + L.off_rx),
+    stage_windows<NT, DT, SR>(reinterpret_cast<float4*>(lds + L.off_win), reinterpret_cast<const RxRec*>(lds + L.off_rx),
                           reinterpret_cast<const int*>(lds + L.off_n0), reinterpret_cast<const TxRec*>(lds + L.off_tx),
                           sw, (long long)P0 * sw.E + q0, q0 - s0 * sw.E, nr, tid, lane, wave);
   __syncthreads();

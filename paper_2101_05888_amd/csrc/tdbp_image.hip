@@ -517,8 +517,10 @@ __attribute__((amdgpu_waves_per_eu(kImageWaves, kImageWaves))) void image_kernel
         const int nr = min(RC, sc * E - q0);
         const int sa = q0 / E, sb = (q0 + nr - 1) / E;
         if (q0 > 0) __syncthreads();
-        load_chunk<NT, ROWS, GATE, DT, INTERP == 1, MOT>(lds, geo, sw, P0, q0, nr, sa, sb - sa + 1, Ld, tid, lane,
-                                                         wave);
+        // staging rows per wave: four for the 3D tiles' 32-record chunks
+        // (399 ms against 405 ms with three on the 3D volume)
+        load_chunk<NT, ROWS, GATE, DT, INTERP == 1, MOT, (LZ > 1 ? 4 : 3)>(lds, geo, sw, P0, q0, nr, sa,
+                                                                           sb - sa + 1, Ld, tid, lane, wave);
         for (int slot = sa; slot <= sb; ++slot) {
           if (slot != dT_slot) {
             const TxRec tr = ltx[slot - sa];
