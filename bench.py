@@ -635,7 +635,7 @@ def main() -> int:
     ap.add_argument("--no-motion", action="store_true")
     ap.add_argument("--no-dpc", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3 runs)")
-    ap.add_argument("--profile-leg", choices=["rangec", "tvg", "drc", "whiten", "dpc", "volume", "autofocus", "mixed"], default=None,
+    ap.add_argument("--profile-leg", choices=["rangec", "tvg", "drc", "whiten", "dpc", "volume", "autofocus", "mixed", "sinc"], default=None,
                     help="with --profile, also run this one leg")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -632,7 +632,9 @@ __device__ __forceinline__ void stage_windows_raw(float2* lwin, const RxRec* lrx
   constexpr int NW = NT / 64;
   constexpr int SPL = 2;
   constexpr int JS = 64 * SPL;
-  constexpr int B = 8;
+  // rows in flight per wave: six, one even pass over four waves for the
+  // variant's 24-record chunks (81.5 ms against 84.3 ms with eight)
+  constexpr int B = 6;
   constexpr int SB = DT == 0 ? 8 : 4;
   const int wave = __builtin_amdgcn_readfirstlane(wave_id);
   const int E = sw.E, Ns = sw.Ns;
